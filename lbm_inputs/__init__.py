@@ -1,0 +1,140 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the oracle.
+
+This module holds no arithmetic of the lattice Boltzmann method: it only
+draws random numbers and places particles.  Both the GPU library and the CPU
+oracle receive what it produces as plain arrays.
+
+Random numbers come from SplitMix64 (Steele, Lea & Flood, "Fast splittable
+pseudorandom number generators", OOPSLA 2014): the state advances by the
+golden-ratio increment and each output is the state passed through the
+variant-13 finaliser of MurmurHash3.  A uniform double in [0, 1) is the top
+53 bits of an output times 2^-53.
+
+Particle seeding is random sequential addition: candidate centres are drawn
+uniformly (x first, then y) and accepted when the surface gap to every
+accepted particle is at least `min_gap` (minimum image along the periodic x
+axis) and the disk keeps one lattice spacing from both flat walls, which sit
+halfway between nodes at y = -1/2 and y = ny - 1/2.  After 1000 * n attempts
+without completing the set, seeding fails.
+"""
+import math
+
+import numpy as np
+
+MASK64 = (1 << 64) - 1
+GOLDEN_GAMMA = 0x9E3779B97F4A7C15
+
+
+class SplitMix64:
+    def __init__(self, seed):
+        self.state = int(seed) & MASK64
+
+    def next_u64(self):
+        self.state = (self.state + GOLDEN_GAMMA) & MASK64
+        z = self.state
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & MASK64
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & MASK64
+        return z ^ (z >> 31)
+
+    def uniform(self):
+        return (self.next_u64() >> 11) * (1.0 / 9007199254740992.0)
+
+
+class SeedingError(RuntimeError):
+    pass
+
+
+def rsa_particles(nx, ny, n, diameter, min_gap=1.0, seed=1):
+    """Return an (n, 7) array of rows (x, y, r, ux, uy, theta, omega), all at rest.
+
+    The acceptance test is evaluated exactly as written (binary64, no fused
+    operations), so any implementation of the same steps gives bit-identical
+    centres.
+    """
+    r = 0.5 * diameter
+    ylo = (-0.5 + 1.0) + r
+    yhi = (ny - 0.5 - 1.0) - r
+    if n < 0 or not (r > 0.0):
+        raise ValueError("need n >= 0 and diameter > 0")
+    if n > 0 and yhi < ylo:
+        raise SeedingError("channel too narrow for the particles")
+    rng = SplitMix64(seed)
+    cell = 2.0 * r + max(min_gap, 0.0)
+    ncx = max(1, int(nx // cell))
+    ncy = max(1, int(ny // cell))
+    grid = {}
+    xs, ys = [], []
+    half = 0.5 * nx
+    attempts = 0
+    while len(xs) < n:
+        if attempts >= 1000 * n:
+            raise SeedingError(f"placed {len(xs)} of {n} particles in {attempts} attempts")
+        attempts += 1
+        x = rng.uniform() * nx
+        y = ylo + rng.uniform() * (yhi - ylo)
+        cx = min(int(x / nx * ncx), ncx - 1)
+        cy = min(max(int((y + 0.5) / ny * ncy), 0), ncy - 1)
+        ok = True
+        for dcy in (-1, 0, 1):
+            yy = cy + dcy
+            if yy < 0 or yy >= ncy:
+                continue
+            for dcx in (-1, 0, 1):
+                for q in grid.get(((cx + dcx) % ncx, yy), ()):
+                    dx = x - xs[q]
+                    if dx > half:
+                        dx = dx - nx
+                    elif dx < -half:
+                        dx = dx + nx
+                    dy = y - ys[q]
+                    gap = (math.sqrt(dx * dx + dy * dy) - r) - r
+                    if gap < min_gap:
+                        ok = False
+                        break
+                if not ok:
+                    break
+            if not ok:
+                break
+        if ok:
+            grid.setdefault((cx, cy), []).append(len(xs))
+            xs.append(x)
+            ys.append(y)
+    out = np.zeros((n, 7))
+    out[:, 0] = xs
+    out[:, 1] = ys
+    out[:, 2] = r
+    return out
+
+
+def smooth_fields(nx, ny, seed, amp_u=0.02, amp_T=0.5, modes=3, rho0=1.0):
+    """Smooth random macroscopic fields (rho, ux, uy, T), each (ny, nx).
+
+    A few Fourier modes, periodic in x and vanishing velocity at the walls, with
+    SplitMix64-drawn amplitudes and phases.  They serve as initial conditions
+    for parity runs of the lattice without particles.
+    """
+    rng = SplitMix64(seed)
+    x = np.arange(nx)[None, :] + 0.0
+    y = np.arange(ny)[:, None] + 0.0
+    H = float(ny)
+    wall = np.sin(np.pi * (y + 0.5) / H)
+    ux = np.zeros((ny, nx))
+    uy = np.zeros((ny, nx))
+    T = np.zeros((ny, nx))
+    rho = np.full((ny, nx), rho0)
+    for m in range(1, modes + 1):
+        a = [rng.uniform() - 0.5 for _ in range(6)]
+        ph = [2 * np.pi * rng.uniform() for _ in range(4)]
+        kx = 2 * np.pi * m / nx
+        ky = np.pi * m / H
+        ux += amp_u * a[0] * wall * np.cos(kx * x + ph[0]) * np.cos(ky * (y + 0.5))
+        uy += amp_u * a[1] * wall * np.sin(kx * x + ph[1]) * np.sin(ky * (y + 0.5))
+        T += amp_T * a[2] * np.cos(kx * x + ph[2]) * np.sin(ky * (y + 0.5))
+        rho += 0.01 * a[3] * np.cos(kx * x + ph[3]) * np.cos(ky * y)
+    return rho, ux, uy, T
+
+
+def random_state(n, seed, lo=0.0, hi=1.0):
+    """n uniform doubles in [lo, hi) from SplitMix64."""
+    rng = SplitMix64(seed)
+    return np.array([lo + (hi - lo) * rng.uniform() for _ in range(n)])
