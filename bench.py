@@ -1,0 +1,178 @@
+"""Benchmark: MLUPS of the coupled flow + thermal step with 4800 particles.
+
+Workload (default "paper_scale"): 4000 x 4000 periodic-x channel between
+cold walls, 4800 hot circular particles of diameter 20 seeded uniformly at
+random (seed 2, gap >= 1), density ratio 1.5, Pr 0.7, Ra 1e8, links
+recollected every step, FP64.  One step = link collection, bounce-back and
+momentum exchange, particle update, solid map, refilling and the fused
+stream-collide over the whole lattice.  MLUPS counts every lattice node,
+solid included (mesh size x steps / time).
+
+Prints one JSON line.  Besides the throughput it carries:
+  roofline     the fused stream-collide kernel (the dominant one), timed with
+               HIP events on the library's stream; achieved = algorithmic
+               bytes per launch / mean launch time, against 8 TB/s.
+  cpu_baseline the CPU oracle (single thread, FP64) on a bounded sample of
+               the same workload, timed on this host.
+"""
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS (coupled flow+thermal) at 4000², 4800 particles; served p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+STORE_BYTES = {"f64": 8, "f32": 4, "shift_f32": 4, "shift_f16": 2, "shift_bf16": 2}
+STORE_DTYPE = {"f64": "f64", "f32": "f32", "shift_f32": "f32", "shift_f16": "f32 (f16 storage)",
+               "shift_bf16": "f32 (bf16 storage)"}
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2308_16597_amd", "csrc", f)
+                  for f in ("kernels.hip", "device.h")]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, storage):
+    """HBM bytes per launch of the stream-collide kernel from the committed
+    rocprofv3 counter summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"stream_collide_{workload}_{storage}_pmc.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"kernel_source_sha256:\s*([0-9a-f]+)", text)
+    t = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not m or not t or m.group(1) != kernel_hash():
+        return None
+    return float(t.group(1))
+
+
+def cpu_baseline(workload, steps):
+    """The CPU oracle on `steps` steps of the same workload (one thread)."""
+    import lbm_inputs
+    from oracle import Oracle
+    from paper_2308_16597_amd import params
+    kw = params.workload_params(workload)
+    w = params.WORKLOADS[workload]
+    okw = {k: v for k, v in kw.items() if k not in ("storage", "max_particles", "max_diameter")}
+    rows = lbm_inputs.rsa_particles(w["nx"], w["ny"], w["n"], w["d"], 1.0, w["seed"])
+    orc = Oracle(**okw)
+    orc.set_particles(rows)
+    t0 = time.perf_counter()
+    orc.step(steps)
+    dt = time.perf_counter() - t0
+    orc.close()
+    return dict(value=round(params.mlups(w["nx"] * w["ny"], steps, dt), 4), unit="MLUPS", cores=1,
+                kind="oracle",
+                sample=f"{steps} steps of the {w['nx']}x{w['ny']} workload with {w['n']} particles "
+                       f"(FP64, one thread), {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--workload", default="paper_scale")
+    ap.add_argument("--storage", default="f64", choices=sorted(STORE_BYTES))
+    ap.add_argument("--phase-steps", type=int, default=100)
+    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the lattice would shard as y-slabs; see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2308_16597_amd import lbm, params
+
+    w = params.WORKLOADS[args.workload]
+    nx, ny = w["nx"], w["ny"]
+    p = lbm.lbm_params_default(**params.workload_params(args.workload, lbm.STORE[args.storage]))
+    log(f"[bench] {args.workload} {nx}x{ny} n={w['n']} d={w['d']} storage={args.storage}")
+    sim = lbm.Sim(p)
+    sim.seed_particles(w["n"], w["d"], 1.0, w["seed"])
+    sim.step(args.warmup)
+    sim.sync()
+    log(f"[bench] warmup {args.warmup} steps done")
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(args.steps)
+    sim.sync()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    mlups = params.mlups(nx * ny, args.steps, dt)
+    log(f"[bench] timed {args.steps} steps in {dt:.3f} s: {mlups:.1f} MLUPS")
+
+    phases = sim.time_phases(args.phase_steps)
+    stats = sim.stats()
+    owner = sim.fields()["owner"]
+    n_fluid = int((owner < 0).sum())
+    es = STORE_BYTES[args.storage]
+    alg_bytes = n_fluid * 28 * es + nx * ny * 1
+    lat_ms = phases["lattice"]
+    achieved = alg_bytes / (lat_ms * 1e-3) / 1e9
+    traffic = measured_traffic(args.workload, args.storage)
+    log(f"[bench] phases (ms/step): {phases}")
+
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(dt / args.steps * 1e3, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": STORE_DTYPE[args.storage],
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.workload}: {nx}x{ny} periodic-x channel, {w['n']} hot particles "
+                        f"d={w['d']:g}, rho_p/rho_f={w['rho_ratio']}, Pr={w['Pr']}, Ra={w['Ra']:g}, "
+                        f"{args.storage} storage, links rebuilt every step",
+            "nx": nx, "ny": ny, "particles": w["n"], "diameter": w["d"], "storage": args.storage,
+            "parallelism": "single GPU",
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_stream_collide",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "bytes_per_launch": alg_bytes,
+            "launch_ms": round(lat_ms, 5),
+        },
+        "phases_ms": {k: round(v, 5) for k, v in phases.items()},
+        "links_per_step": stats["links"],
+        "fluid_nodes": n_fluid,
+    }
+    sim.close()
+    del sim
+    if not args.no_cpu_baseline:
+        log(f"[bench] cpu baseline: oracle, {args.cpu_steps} steps")
+        out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,212 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) particle-resolved thermal lattice
+ * Boltzmann library: the per-step hot path of Xu & Li, "Particle-resolved
+ * thermal lattice Boltzmann simulation using OpenACC on multi-GPUs"
+ * (arXiv 2308.16597).
+ *
+ * One step (Sec. 2 and Sec. 3 of the paper) is:
+ *   1. collect the fluid-particle links into a compacted index array
+ *      (the paper's extended indirect addressing, Sec. 3);
+ *   2. at every link: interpolated moving-wall bounce-back (Sec. 2.3,
+ *      Eqs. (9)-(10)), the thermal curved-wall condition (Eqs. (11)-(12)) and
+ *      the momentum-exchange force and torque (Sec. 2.4, Eqs. (13)-(14));
+ *   3. per particle: FP64 reduction, spring repulsion (Eq. (15)), net weight
+ *      and the Newton-Euler update (Sec. 2.2, Eqs. (7)-(8));
+ *   4. the solid/fluid map at the new positions;
+ *   5. the fused pull-stream + collide of the D2Q9 flow and D2Q5 heat MRT
+ *      models with Boussinesq buoyancy (Sec. 2.1, Eqs. (5)-(6)) over the
+ *      whole lattice, flat walls included;
+ *   6. refilling of newly uncovered fluid nodes (Sec. 2.5, Eqs. (16)-(17)).
+ *
+ * Geometry: node (i, j) is at (x, y) = (i, j), 0 <= i < nx, 0 <= j < ny; x is
+ * periodic; the flat walls are halfway between nodes, at y = -1/2 and
+ * y = ny - 1/2.  Gravity points along -y.  D2Q9 velocities e0..e8 are
+ * (0,0) (1,0) (0,1) (-1,0) (0,-1) (1,1) (-1,1) (-1,-1) (1,-1); D2Q5 uses the
+ * first five.
+ *
+ * Conventions for every function:
+ *   - The return value is a status (LBM_OK or a negative LBM_E* code);
+ *     lbm_last_error gives a message for the handle (or, for a failed
+ *     create, for the calling thread).
+ *   - Host arrays belong to the caller and are never retained.  Field arrays
+ *     hold nx*ny values, row-major (index j*nx + i).  Any output pointer may
+ *     be NULL to skip that output.
+ *   - Work is enqueued on the handle's HIP stream.  lbm_step returns without
+ *     waiting; the lbm_read_* functions, lbm_sync and lbm_destroy wait for the
+ *     stream.  Errors detected on the device (non-finite populations, a
+ *     particle moving more than half a lattice spacing in one step, link
+ *     array overflow) are reported by the next waiting call as
+ *     LBM_EUNSTABLE.
+ *   - A handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBM_ABI_VERSION 1
+
+typedef struct lbm_sim* lbm_handle;
+
+enum {
+    LBM_OK = 0,
+    LBM_EINVAL = -1,     /* invalid argument or parameter (checked on the host) */
+    LBM_ENOMEM = -2,     /* device allocation failed, or the arena is too small */
+    LBM_EDEVICE = -3,    /* HIP runtime error */
+    LBM_ESEED = -4,      /* particle seeding could not place every particle */
+    LBM_EUNSTABLE = -5,  /* the run became non-finite or a particle moved too fast */
+    LBM_ESTATE = -6,     /* call not allowed in the handle's current state */
+};
+
+/* Population storage.  F64 computes in FP64; the others compute in FP32.
+ * The SHIFT_ modes store deviations f_i - w_i rho0 and g_k - w_k T_shift. */
+enum {
+    LBM_STORE_F64 = 0,
+    LBM_STORE_F32 = 1,
+    LBM_STORE_SHIFT_F32 = 2,
+    LBM_STORE_SHIFT_F16 = 3,
+    LBM_STORE_SHIFT_BF16 = 4,
+};
+
+/* Simulation parameters, all in lattice units.  Fill with lbm_params_default
+ * and override.  Relaxation rates <= 0 select the defaults:
+ *   s_nu = 1/(3 nu + 1/2); s_e = s_eps = s_nu; s_q from
+ *   (1/s_nu - 1/2)(1/s_q - 1/2) = 3/16; s_alpha = 1/(alpha/cs_T^2 + 1/2) with
+ *   cs_T^2 = (4 + a_T)/10; sT_e = sT_p from (1/s_alpha - 1/2)(1/s_T - 1/2) = 1/4. */
+typedef struct {
+    int32_t abi_version;   /* must be LBM_ABI_VERSION */
+    int32_t nx, ny;        /* 8 <= nx, ny <= 65535 */
+    int32_t periodic_x;    /* must be 1 */
+    int32_t periodic_y;    /* 0: flat walls at y (required with particles); 1: periodic */
+    int32_t storage;       /* LBM_STORE_* */
+    double rho0;           /* reference density (> 0) */
+    double nu, alpha;      /* kinematic viscosity, thermal diffusivity (> 0) */
+    double gravity;        /* |g|, along -y */
+    double beta;           /* thermal expansion coefficient */
+    double T_ref;          /* T0 of the buoyancy force rho g beta (T - T0) y^ */
+    double body_fx;        /* uniform extra force density along +x */
+    double s_e, s_eps, s_q;/* D2Q9 free rates */
+    double a_T;            /* D2Q5 equilibrium constant (n_e^eq = a_T T), -4 < a_T <= 1 */
+    double sT_e, sT_p;     /* D2Q5 free rates */
+    double wall_T[2];      /* Dirichlet temperature of the [bottom, top] wall */
+    double wall_ux[2];     /* tangential velocity of the [bottom, top] wall */
+    double T_fluid0;       /* initial fluid temperature */
+    double particle_T;     /* particle surface temperature T_w */
+    double rho_ratio;      /* particle/fluid density ratio */
+    int32_t repulsion;     /* 1: spring repulsion between particles and with walls */
+    double rep_eps;        /* stiffness epsilon_w */
+    double rep_range;      /* threshold distance s */
+    double T_shift;        /* SHIFT_ storage: g is stored as g_k - w_k T_shift */
+    int32_t max_particles; /* capacity for particles (>= 0) */
+    double max_diameter;   /* largest particle diameter the buffers are sized for */
+} lbm_params;
+
+/* Phases reported by lbm_time_phases, in launch order. */
+enum {
+    LBM_PHASE_COMPACT = 0,   /* link collection (and clearing of stale maps) */
+    LBM_PHASE_LINKS = 1,     /* bounce-back, thermal wall, momentum exchange */
+    LBM_PHASE_PARTICLES = 2, /* reduction, repulsion, Newton-Euler */
+    LBM_PHASE_MASK = 3,      /* solid map at the new positions */
+    LBM_PHASE_REFILL = 4,    /* refilling of newborn nodes (and node flags) */
+    LBM_PHASE_LATTICE = 5,   /* fused stream + collide over the lattice */
+    LBM_NPHASES = 6
+};
+
+/* Library ABI version (LBM_ABI_VERSION). */
+int32_t lbm_abi_version(void);
+
+/* Defaults: 64 x 64 periodic-x channel, rho0 = 1, nu = alpha = 0.1, no
+ * gravity, a_T = -2, FP64 storage, repulsion on with eps = 0.001 and s = 3
+ * (Sec. 2.4), particle_T = 1, rho_ratio = 1.5, no particles. */
+void lbm_params_default(lbm_params* p);
+
+/* Device bytes a handle with these parameters needs (0 if invalid); the
+ * size lbm_create_in_arena requires. */
+size_t lbm_bytes_required(const lbm_params* p);
+
+/* Create a handle: validate on the host, allocate device memory with
+ * hipMalloc, and initialise the fluid at rest (rho0, T_fluid0) with no
+ * particles.  hip_stream is a hipStream_t (NULL: the handle creates its own
+ * stream).  On failure *out is NULL and lbm_last_error(NULL) explains. */
+int lbm_create(const lbm_params* p, void* hip_stream, lbm_handle* out);
+
+/* Same, carving every device buffer out of the caller's allocation
+ * [dev_ptr, dev_ptr + bytes), which must hold lbm_bytes_required(p) bytes,
+ * be 256-byte aligned and outlive the handle. */
+int lbm_create_in_arena(const lbm_params* p, void* dev_ptr, size_t bytes, void* hip_stream,
+                        lbm_handle* out);
+
+/* Wait for the stream and release the handle (and the memory it allocated). */
+void lbm_destroy(lbm_handle h);
+
+/* Message of the last error on h; with h == NULL, of the last failed
+ * lbm_create* on the calling thread.  Valid until the next call on h. */
+const char* lbm_last_error(lbm_handle h);
+
+/* Host-only: random sequential addition of n disks of the given diameter in
+ * an nx x ny channel, written to rows7 (n rows of x, y, r, ux, uy, theta,
+ * omega; at rest).  Candidates come from SplitMix64 (x then y, each the top
+ * 53 bits of an output times 2^-53, x scaled by nx, y into
+ * [r + 1/2, ny - 3/2 - r]); a candidate is accepted when its surface gap to
+ * every accepted disk (minimum image along x) is >= min_gap.  Fails with
+ * LBM_ESEED after 1000 n attempts. */
+int lbm_rsa_seed(int32_t nx, int32_t ny, int32_t n, double diameter, double min_gap,
+                 uint64_t seed, double* rows7);
+
+/* lbm_rsa_seed with the handle's lattice, then lbm_set_particles. */
+int lbm_seed_particles(lbm_handle h, int32_t n, double diameter, double min_gap, uint64_t seed);
+
+/* Replace the particles (n rows of x, y, r, ux, uy, theta, omega; host
+ * memory) and re-initialise the run: fluid at rest at rho0 and T_fluid0,
+ * step counter 0.  Requires n <= max_particles, 1 < r <= max_diameter/2,
+ * finite values and walls in y. */
+int lbm_set_particles(lbm_handle h, int32_t n, const double* rows7);
+
+/* Re-initialise fluid nodes to the equilibria f^eq(rho, u) and g^eq(T, u)
+ * of the given fields (host arrays of nx*ny); particles are kept; step
+ * counter 0. */
+int lbm_set_equilibrium(lbm_handle h, const double* rho, const double* ux, const double* uy,
+                        const double* T);
+
+/* Enqueue nsteps steps on the handle's stream and return. */
+int lbm_step(lbm_handle h, int32_t nsteps);
+
+/* Wait for the stream; report deferred device errors. */
+int lbm_sync(lbm_handle h);
+
+/* Pre-collision macroscopics at the current time (Sec. 2.1): rho, u with
+ * the half force, T (NaN inside particles), and the owner map (-1 for
+ * fluid, else the particle index). */
+int lbm_read_fields(lbm_handle h, double* rho, double* ux, double* uy, double* T, int32_t* owner);
+
+/* Particle state: n rows of x, y, r, ux, uy, theta, omega, Fx, Fy, Tz, where
+ * (Fx, Fy, Tz) is the momentum-exchange force and torque of the last step.
+ * rows10 may be NULL to query *n only. */
+int lbm_read_particles(lbm_handle h, double* rows10, int32_t* n);
+
+/* Collect the fluid-particle links of the current state (Sec. 3) and copy
+ * them out: node index j*nx + i of the fluid node, direction 1..8, particle,
+ * and the link fraction q of Sec. 2.3.  The order of the links is
+ * unspecified.  With every output NULL only *n_out is set; otherwise cap
+ * must be >= the number of links. */
+int lbm_read_links(lbm_handle h, int32_t* node, int32_t* dir, int32_t* particle, double* q,
+                   int64_t cap, int64_t* n_out);
+
+/* Run nsteps steps with HIP events around each phase and return the mean
+ * device time per step of each phase in ms_out[LBM_NPHASES] and, in
+ * ms_out[LBM_NPHASES], the mean time of a whole step.  Waits. */
+int lbm_time_phases(lbm_handle h, int32_t nsteps, double* ms_out);
+
+/* Counters: out[0] steps done, out[1] links of the last step, out[2]
+ * particles, out[3] lattice nodes, out[4] device bytes held. */
+int lbm_stats(lbm_handle h, double* out5);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

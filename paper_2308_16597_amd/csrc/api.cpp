@@ -1,0 +1,650 @@
+// api.cpp -- the C ABI declared in include/lbm.h: parameter validation,
+// device memory layout, particle seeding, step sequencing and read-back.
+// All arithmetic of the method runs in the kernels of kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "launch.h"
+#include "lbm.h"
+
+using namespace ptlbm;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+constexpr size_t kAlign = 256;
+constexpr size_t kArrayAlign = 65536;
+constexpr size_t kStagger = 4096;   // start offset between consecutive population arrays
+
+size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+size_t elem_size(int mode) {
+    switch (mode) {
+        case LBM_STORE_F64: return 8;
+        case LBM_STORE_F32:
+        case LBM_STORE_SHIFT_F32: return 4;
+        case LBM_STORE_SHIFT_F16:
+        case LBM_STORE_SHIFT_BF16: return 2;
+        default: return 0;
+    }
+}
+
+// Largest window edge for a diameter: INT(x + r) - INT(x - r) + 3 <= floor(2r) + 4.
+int window_cap(double max_diameter) { return (int)std::floor(max_diameter) + 4; }
+
+struct Layout {
+    int pitch = 0;
+    size_t npitched = 0, array_stride = 0, state_bytes = 0;
+    size_t off_S[2] = {0, 0}, off_O[2] = {0, 0}, off_flag = 0, off_P = 0, off_Fh = 0, off_seg = 0,
+           off_links = 0, off_lscratch = 0, off_counter = 0, off_status = 0, total = 0;
+    int nwin = 0;
+    size_t link_cap = 0;
+};
+
+Layout make_layout(const lbm_params& p) {
+    Layout L;
+    L.pitch = (int)round_up((size_t)p.nx, 64);
+    L.npitched = (size_t)L.pitch * p.ny;
+    const size_t es = elem_size(p.storage);
+    L.array_stride = round_up(L.npitched * es, kArrayAlign) + kStagger;
+    L.state_bytes = round_up(14 * L.array_stride, kArrayAlign);
+    size_t off = 0;
+    L.off_S[0] = off; off += L.state_bytes;
+    L.off_S[1] = off; off += L.state_bytes;
+    L.off_O[0] = off; off = round_up(off + L.npitched * 4, kArrayAlign);
+    L.off_O[1] = off; off = round_up(off + L.npitched * 4, kArrayAlign);
+    L.off_flag = off; off = round_up(off + L.npitched, kArrayAlign);
+    const size_t cap = (size_t)(p.max_particles > 0 ? p.max_particles : 0);
+    L.nwin = window_cap(p.max_diameter > 0 ? p.max_diameter : 2.0);
+    L.link_cap = cap * (size_t)(12 * L.nwin - 12);
+    L.off_P = off; off = round_up(off + 3 * cap * sizeof(PState), kAlign);
+    L.off_Fh = off; off = round_up(off + cap * 4 * sizeof(double), kAlign);
+    L.off_seg = off; off = round_up(off + cap * sizeof(int2), kAlign);
+    L.off_links = off; off = round_up(off + L.link_cap * sizeof(uint2), kAlign);
+    L.off_lscratch = off; off = round_up(off + L.link_cap * (3 * sizeof(int32_t) + sizeof(double)), kAlign);
+    L.off_counter = off; off = round_up(off + 64, kAlign);
+    L.off_status = off; off = round_up(off + 64, kAlign);
+    L.total = off;
+    return L;
+}
+
+}  // namespace
+
+struct lbm_sim {
+    lbm_params p{};
+    Layout L;
+    DevState d{};
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    char* base = nullptr;
+    bool own_mem = false;
+    int cur = 0;    // time level holding the current (post-collision) state
+    int ring = 0;   // particle slot of the current time level
+    int np = 0;
+    int64_t steps = 0;
+    std::string err;
+    std::vector<double> host_fields;
+};
+
+namespace {
+
+int fail(lbm_sim* h, int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (h) h->err = buf;
+    else g_create_error = buf;
+    return code;
+}
+
+int hip_fail(lbm_sim* h, hipError_t e, const char* what) {
+    return fail(h, LBM_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIPCHK(h, expr)                                   \
+    do {                                                  \
+        hipError_t e_ = (expr);                           \
+        if (e_ != hipSuccess) return hip_fail(h, e_, #expr); \
+    } while (0)
+
+bool validate(const lbm_params* p, std::string& why) {
+    char buf[256];
+    auto bad = [&](const char* m) { why = m; return false; };
+    if (!p) return bad("null parameters");
+    if (p->abi_version != LBM_ABI_VERSION) {
+        snprintf(buf, sizeof buf, "abi_version %d, library has %d", p->abi_version, LBM_ABI_VERSION);
+        why = buf;
+        return false;
+    }
+    if (p->nx < 8 || p->ny < 8 || p->nx > 65535 || p->ny > 65535) return bad("nx and ny must lie in [8, 65535]");
+    if (p->periodic_x != 1) return bad("periodic_x must be 1");
+    if (p->periodic_y != 0 && p->periodic_y != 1) return bad("periodic_y must be 0 or 1");
+    if (elem_size(p->storage) == 0) return bad("unknown storage mode");
+    if (!(p->rho0 > 0) || !(p->nu > 0) || !(p->alpha > 0)) return bad("rho0, nu and alpha must be > 0");
+    if (!(p->a_T > -4.0 && p->a_T <= 1.0)) return bad("a_T must lie in (-4, 1]");
+    const double rates[5] = {p->s_e, p->s_eps, p->s_q, p->sT_e, p->sT_p};
+    for (double r : rates)
+        if (!(r < 2.0) || std::isnan(r)) return bad("relaxation rates must be < 2 (<= 0 selects the default)");
+    if (p->max_particles < 0) return bad("max_particles must be >= 0");
+    if (p->max_particles > 0) {
+        if (p->periodic_y) return bad("particles need flat walls in y (periodic_y = 0)");
+        if (!(p->max_diameter > 2.0)) return bad("max_diameter must be > 2");
+        if (window_cap(p->max_diameter) > p->nx) return bad("particle window wider than the lattice");
+        if (window_cap(p->max_diameter) > 100) return bad("max_diameter must be <= 96");
+        if ((double)p->max_particles * (12.0 * window_cap(p->max_diameter) - 12) > 2.0e9)
+            return bad("too many link slots");
+        if (!(p->rep_eps > 0) || !(p->rep_range > 0)) return bad("rep_eps and rep_range must be > 0");
+        if (!(p->rho_ratio > 0)) return bad("rho_ratio must be > 0");
+    }
+    const double vals[] = {p->gravity, p->beta, p->T_ref, p->body_fx, p->wall_T[0], p->wall_T[1],
+                           p->wall_ux[0], p->wall_ux[1], p->T_fluid0, p->particle_T, p->T_shift};
+    for (double v : vals)
+        if (!std::isfinite(v)) return bad("parameters must be finite");
+    return true;
+}
+
+void fill_lp(lbm_sim* h) {
+    const lbm_params& p = h->p;
+    LP& lp = h->d.lp;
+    lp.nx = p.nx;
+    lp.ny = p.ny;
+    lp.pitch = h->L.pitch;
+    lp.periodic_y = p.periodic_y;
+    lp.rho0 = p.rho0;
+    lp.gbeta = p.gravity * p.beta;
+    lp.T_ref = p.T_ref;
+    lp.body_fx = p.body_fx;
+    const double s_nu = 1.0 / (p.nu * 3.0 + 0.5);
+    lp.s_nu = s_nu;
+    lp.s_e = p.s_e > 0 ? p.s_e : s_nu;
+    lp.s_eps = p.s_eps > 0 ? p.s_eps : s_nu;
+    lp.s_q = p.s_q > 0 ? p.s_q : 1.0 / (0.5 + (3.0 / 16.0) / (1.0 / s_nu - 0.5));
+    const double a = p.a_T;
+    lp.a_T = a;
+    lp.w5_0 = (1.0 - a) / 5.0;
+    lp.w5_k = (4.0 + a) / 20.0;
+    const double cs2T = (4.0 + a) / 10.0;
+    const double s_a = 1.0 / (p.alpha / cs2T + 0.5);
+    lp.s_a = s_a;
+    const double s_T = 1.0 / (0.5 + 0.25 / (1.0 / s_a - 0.5));
+    lp.s_Te = p.sT_e > 0 ? p.sT_e : s_T;
+    lp.s_Tp = p.sT_p > 0 ? p.sT_p : s_T;
+    for (int w = 0; w < 2; ++w) {
+        lp.wall_T[w] = p.wall_T[w];
+        lp.wall_ux[w] = p.wall_ux[w];
+    }
+    const bool shifted = p.storage >= LBM_STORE_SHIFT_F32;
+    lp.T_sh = shifted ? p.T_shift : 0.0;
+    lp.particle_T = p.particle_T;
+    lp.rho_ratio = p.rho_ratio;
+    lp.gravity = p.gravity;
+    lp.rep_eps = p.rep_eps;
+    lp.rep_range = p.rep_range;
+    lp.repulsion = p.repulsion;
+    lp.np = 0;
+    lp.nwin = h->L.nwin;
+    lp.link_cap = (int)h->L.link_cap;
+}
+
+int create_common(const lbm_params* p, void* dev_ptr, size_t bytes, void* stream, lbm_handle* out) {
+    if (!out) return fail(nullptr, LBM_EINVAL, "null output handle");
+    *out = nullptr;
+    std::string why;
+    if (!validate(p, why)) return fail(nullptr, LBM_EINVAL, "%s", why.c_str());
+    lbm_sim* h = new lbm_sim();
+    h->p = *p;
+    h->L = make_layout(*p);
+    if (dev_ptr) {
+        if (bytes < h->L.total || ((uintptr_t)dev_ptr % kAlign) != 0) {
+            delete h;
+            return fail(nullptr, LBM_ENOMEM, "arena of %zu bytes (need %zu, 256-byte aligned)", bytes, h->L.total);
+        }
+        h->base = (char*)dev_ptr;
+    } else {
+        hipError_t e = hipMalloc((void**)&h->base, h->L.total);
+        if (e != hipSuccess) {
+            delete h;
+            (void)hipGetLastError();
+            return fail(nullptr, LBM_ENOMEM, "hipMalloc of %zu bytes: %s", h->L.total, hipGetErrorString(e));
+        }
+        h->own_mem = true;
+    }
+    if (stream) {
+        h->stream = (hipStream_t)stream;
+    } else {
+        hipError_t e = hipStreamCreate(&h->stream);
+        if (e != hipSuccess) {
+            if (h->own_mem) (void)hipFree(h->base);
+            delete h;
+            return fail(nullptr, LBM_EDEVICE, "hipStreamCreate: %s", hipGetErrorString(e));
+        }
+        h->own_stream = true;
+    }
+    DevState& d = h->d;
+    d.mode = p->storage;
+    const Layout& L = h->L;
+    for (int s = 0; s < 2; ++s)
+        for (int i = 0; i < 14; ++i) d.S[s][i] = h->base + L.off_S[s] + (size_t)i * L.array_stride;
+    d.O[0] = (int32_t*)(h->base + L.off_O[0]);
+    d.O[1] = (int32_t*)(h->base + L.off_O[1]);
+    d.flag = (uint8_t*)(h->base + L.off_flag);
+    const size_t cap = (size_t)(p->max_particles > 0 ? p->max_particles : 0);
+    for (int r = 0; r < 3; ++r) d.P[r] = (PState*)(h->base + L.off_P) + r * cap;
+    d.Fh = (double*)(h->base + L.off_Fh);
+    d.seg = (int2*)(h->base + L.off_seg);
+    d.links = (uint2*)(h->base + L.off_links);
+    d.counter = (unsigned*)(h->base + L.off_counter);
+    d.status = (unsigned*)(h->base + L.off_status);
+    fill_lp(h);
+    *out = h;
+    int rc = lbm_set_particles(h, 0, nullptr);
+    if (rc != LBM_OK) {
+        g_create_error = h->err;
+        lbm_destroy(h);
+        *out = nullptr;
+    }
+    return rc;
+}
+
+int check_status(lbm_sim* h) {
+    unsigned st = 0;
+    HIPCHK(h, hipMemcpyAsync(&st, h->d.status, sizeof st, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    if (st == 0) return LBM_OK;
+    std::string m = "device reported:";
+    if (st & ST_NONFINITE) m += " non-finite populations;";
+    if (st & ST_OVERSPEED) m += " a particle moved more than 0.5 in one step;";
+    if (st & ST_LINK_OVERFLOW) m += " link array overflow;";
+    if (st & ST_BAD_PARTICLE) m += " particle state not finite or outside the lattice;";
+    return fail(h, LBM_EUNSTABLE, "%s", m.c_str());
+}
+
+int enqueue_step(lbm_sim* h, hipEvent_t* ev) {
+    const DevState& d = h->d;
+    hipStream_t st = h->stream;
+    const int c = h->cur, r = h->ring;
+    int ph = 0;
+    auto mark = [&]() {
+        if (ev) (void)hipEventRecord(ev[ph], st);
+        ++ph;
+    };
+    mark();
+    HIPCHK(h, launch_compact(d, c, r, st));
+    mark();
+    HIPCHK(h, launch_link_pass(d, c, r, st));
+    mark();
+    HIPCHK(h, launch_particles(d, r, st));
+    mark();
+    HIPCHK(h, launch_mask_mark(d, 1 - c, d.P[ring_next(r)], st));
+    mark();
+    HIPCHK(h, launch_refill(d, c, r, st));
+    mark();
+    HIPCHK(h, launch_stream_collide(d, c, st));
+    mark();
+    h->cur = 1 - c;
+    h->ring = ring_next(r);
+    h->steps += 1;
+    return LBM_OK;
+}
+
+void* scratch_of(lbm_sim* h) { return h->d.S[1 - h->cur][0]; }
+
+}  // namespace
+
+extern "C" {
+
+int32_t lbm_abi_version(void) { return LBM_ABI_VERSION; }
+
+void lbm_params_default(lbm_params* p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof *p);
+    p->abi_version = LBM_ABI_VERSION;
+    p->nx = 64;
+    p->ny = 64;
+    p->periodic_x = 1;
+    p->periodic_y = 0;
+    p->storage = LBM_STORE_F64;
+    p->rho0 = 1.0;
+    p->nu = 0.1;
+    p->alpha = 0.1;
+    p->a_T = -2.0;
+    p->particle_T = 1.0;
+    p->rho_ratio = 1.5;
+    p->repulsion = 1;
+    p->rep_eps = 1e-3;
+    p->rep_range = 3.0;
+    p->T_shift = 0.5;
+    p->max_particles = 0;
+    p->max_diameter = 0.0;
+}
+
+size_t lbm_bytes_required(const lbm_params* p) {
+    std::string why;
+    if (!validate(p, why)) return 0;
+    return make_layout(*p).total;
+}
+
+int lbm_create(const lbm_params* p, void* hip_stream, lbm_handle* out) {
+    return create_common(p, nullptr, 0, hip_stream, out);
+}
+
+int lbm_create_in_arena(const lbm_params* p, void* dev_ptr, size_t bytes, void* hip_stream, lbm_handle* out) {
+    if (!dev_ptr) return fail(nullptr, LBM_EINVAL, "null arena");
+    return create_common(p, dev_ptr, bytes, hip_stream, out);
+}
+
+void lbm_destroy(lbm_handle h) {
+    if (!h) return;
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    if (h->own_mem && h->base) (void)hipFree(h->base);
+    if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+    delete h;
+}
+
+const char* lbm_last_error(lbm_handle h) { return h ? h->err.c_str() : g_create_error.c_str(); }
+
+int lbm_rsa_seed(int32_t nx, int32_t ny, int32_t n, double diameter, double min_gap, uint64_t seed,
+                 double* rows7) {
+    if (n < 0 || !(diameter > 0) || nx < 1 || ny < 1 || (n > 0 && !rows7))
+        return fail(nullptr, LBM_EINVAL, "invalid seeding arguments");
+    const double r = 0.5 * diameter;
+    const double ylo = (-0.5 + 1.0) + r;
+    const double yhi = ((ny - 0.5) - 1.0) - r;
+    if (n > 0 && yhi < ylo) return fail(nullptr, LBM_ESEED, "channel too narrow for the particles");
+    // SplitMix64 (Steele, Lea & Flood 2014)
+    uint64_t state = seed;
+    auto next_u64 = [&]() {
+        state += 0x9E3779B97F4A7C15ull;
+        uint64_t z = state;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        return z ^ (z >> 31);
+    };
+    auto uniform = [&]() { return (double)(next_u64() >> 11) * (1.0 / 9007199254740992.0); };
+    // neighbour search on cells at least one exclusion distance wide
+    const double cell = 2.0 * r + (min_gap > 0 ? min_gap : 0.0);
+    const int ncx = std::max(1, (int)std::floor(nx / cell));
+    const int ncy = std::max(1, (int)std::floor(ny / cell));
+    std::vector<std::vector<int>> grid((size_t)ncx * ncy);
+    std::vector<double> xs, ys;
+    xs.reserve(n);
+    ys.reserve(n);
+    const double half = 0.5 * nx;
+    long long attempts = 0;
+    while ((int)xs.size() < n) {
+        if (attempts >= 1000LL * n)
+            return fail(nullptr, LBM_ESEED, "placed %zu of %d particles in %lld attempts", xs.size(), n, attempts);
+        ++attempts;
+        const double x = uniform() * nx;
+        const double y = ylo + uniform() * (yhi - ylo);
+        const int cx = std::min((int)(x / nx * ncx), ncx - 1);
+        const int cy = std::min(std::max((int)((y + 0.5) / ny * ncy), 0), ncy - 1);
+        bool ok = true;
+        for (int dcy = -1; dcy <= 1 && ok; ++dcy) {
+            const int yy = cy + dcy;
+            if (yy < 0 || yy >= ncy) continue;
+            for (int dcx = -1; dcx <= 1 && ok; ++dcx) {
+                const int xx = ((cx + dcx) % ncx + ncx) % ncx;
+                for (int q : grid[(size_t)yy * ncx + xx]) {
+                    double dx = x - xs[q];
+                    if (dx > half) dx = dx - nx;
+                    else if (dx < -half) dx = dx + nx;
+                    const double dy = y - ys[q];
+                    const double gap = (std::sqrt(dx * dx + dy * dy) - r) - r;
+                    if (gap < min_gap) {
+                        ok = false;
+                        break;
+                    }
+                }
+            }
+        }
+        if (ok) {
+            grid[(size_t)cy * ncx + cx].push_back((int)xs.size());
+            xs.push_back(x);
+            ys.push_back(y);
+        }
+    }
+    for (int i = 0; i < n; ++i) {
+        double* row = rows7 + 7 * (size_t)i;
+        row[0] = xs[i];
+        row[1] = ys[i];
+        row[2] = r;
+        row[3] = row[4] = row[5] = row[6] = 0.0;
+    }
+    return LBM_OK;
+}
+
+int lbm_seed_particles(lbm_handle h, int32_t n, double diameter, double min_gap, uint64_t seed) {
+    if (!h) return LBM_EINVAL;
+    if (n < 0) return fail(h, LBM_EINVAL, "negative particle count");
+    std::vector<double> rows((size_t)n * 7 + 1);
+    int rc = lbm_rsa_seed(h->p.nx, h->p.ny, n, diameter, min_gap, seed, rows.data());
+    if (rc != LBM_OK) return fail(h, rc, "%s", g_create_error.c_str());
+    return lbm_set_particles(h, n, rows.data());
+}
+
+int lbm_set_particles(lbm_handle h, int32_t n, const double* rows7) {
+    if (!h) return LBM_EINVAL;
+    if (n < 0 || n > h->p.max_particles) return fail(h, LBM_EINVAL, "particle count %d outside [0, %d]", n, h->p.max_particles);
+    if (n > 0 && !rows7) return fail(h, LBM_EINVAL, "null particle rows");
+    std::vector<PState> P((size_t)n);
+    const double rmax = 0.5 * h->p.max_diameter;
+    for (int i = 0; i < n; ++i) {
+        const double* in = rows7 + 7 * (size_t)i;
+        for (int c = 0; c < 7; ++c)
+            if (!std::isfinite(in[c])) return fail(h, LBM_EINVAL, "particle %d: non-finite value", i);
+        if (!(in[2] > 1.0) || in[2] > rmax) return fail(h, LBM_EINVAL, "particle %d: radius %g outside (1, %g]", i, in[2], rmax);
+        if (in[1] < -0.5 || in[1] > h->p.ny - 0.5) return fail(h, LBM_EINVAL, "particle %d: centre outside the channel", i);
+        double x = std::fmod(in[0], (double)h->p.nx);
+        if (x < 0) x += h->p.nx;
+        P[i] = PState{x, in[1], in[2], in[3], in[4], in[5], in[6], 0.0};
+    }
+    DevState& d = h->d;
+    hipStream_t st = h->stream;
+    HIPCHK(h, hipStreamSynchronize(st));
+    h->np = n;
+    d.lp.np = n;
+    h->cur = 0;
+    h->ring = 0;
+    const size_t nb = h->L.npitched;
+    HIPCHK(h, hipMemsetAsync(d.O[0], 0xff, nb * 4, st));
+    HIPCHK(h, hipMemsetAsync(d.O[1], 0xff, nb * 4, st));
+    HIPCHK(h, hipMemsetAsync(d.flag, 0, nb, st));
+    HIPCHK(h, hipMemsetAsync(d.counter, 0, 64, st));
+    HIPCHK(h, hipMemsetAsync(d.status, 0, 64, st));
+    if (n > 0) {
+        for (int r = 0; r < 3; ++r)
+            HIPCHK(h, hipMemcpyAsync(d.P[r], P.data(), sizeof(PState) * n, hipMemcpyHostToDevice, st));
+        HIPCHK(h, hipMemsetAsync(d.Fh, 0, sizeof(double) * 4 * n, st));
+        HIPCHK(h, hipMemsetAsync(d.seg, 0, sizeof(int2) * n, st));
+        HIPCHK(h, launch_mask_mark(d, 0, d.P[0], st));
+    }
+    HIPCHK(h, launch_init(d, 0, nullptr, nullptr, nullptr, nullptr, true, h->p.rho0, h->p.T_fluid0, st));
+    HIPCHK(h, hipStreamSynchronize(st));
+    h->steps = 0;
+    return LBM_OK;
+}
+
+int lbm_set_equilibrium(lbm_handle h, const double* rho, const double* ux, const double* uy, const double* T) {
+    if (!h) return LBM_EINVAL;
+    if (!rho || !ux || !uy || !T) return fail(h, LBM_EINVAL, "null field");
+    const size_t n = (size_t)h->p.nx * h->p.ny;
+    const bool f64 = h->p.storage == LBM_STORE_F64;
+    char* scr = (char*)scratch_of(h);
+    const double* src[4] = {rho, ux, uy, T};
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    if (f64) {
+        for (int c = 0; c < 4; ++c)
+            HIPCHK(h, hipMemcpyAsync(scr + c * n * 8, src[c], n * 8, hipMemcpyHostToDevice, h->stream));
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+    } else {
+        std::vector<float> tmp(4 * n);
+        for (int c = 0; c < 4; ++c)
+            for (size_t k = 0; k < n; ++k) tmp[c * n + k] = (float)src[c][k];
+        HIPCHK(h, hipMemcpyAsync(scr, tmp.data(), 4 * n * 4, hipMemcpyHostToDevice, h->stream));
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+    }
+    const size_t es = f64 ? 8 : 4;
+    HIPCHK(h, launch_init(h->d, h->cur, scr, scr + n * es, scr + 2 * n * es, scr + 3 * n * es, f64, 0.0, 0.0,
+                          h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    h->steps = 0;
+    return LBM_OK;
+}
+
+int lbm_step(lbm_handle h, int32_t nsteps) {
+    if (!h) return LBM_EINVAL;
+    if (nsteps < 0) return fail(h, LBM_EINVAL, "negative step count");
+    for (int32_t s = 0; s < nsteps; ++s) {
+        int rc = enqueue_step(h, nullptr);
+        if (rc != LBM_OK) return rc;
+    }
+    return LBM_OK;
+}
+
+int lbm_sync(lbm_handle h) {
+    if (!h) return LBM_EINVAL;
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return check_status(h);
+}
+
+int lbm_read_fields(lbm_handle h, double* rho, double* ux, double* uy, double* T, int32_t* owner) {
+    if (!h) return LBM_EINVAL;
+    int rc = lbm_sync(h);
+    if (rc != LBM_OK && rc != LBM_EUNSTABLE) return rc;
+    const size_t n = (size_t)h->p.nx * h->p.ny;
+    const bool f64 = h->p.storage == LBM_STORE_F64;
+    void* scr = scratch_of(h);
+    HIPCHK(h, launch_macros(h->d, h->cur, scr, h->stream));
+    double* outs[4] = {rho, ux, uy, T};
+    if (f64) {
+        for (int c = 0; c < 4; ++c)
+            if (outs[c])
+                HIPCHK(h, hipMemcpyAsync(outs[c], (char*)scr + c * n * 8, n * 8, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+    } else {
+        std::vector<float> tmp(n);
+        for (int c = 0; c < 4; ++c) {
+            if (!outs[c]) continue;
+            HIPCHK(h, hipMemcpyAsync(tmp.data(), (char*)scr + c * n * 4, n * 4, hipMemcpyDeviceToHost, h->stream));
+            HIPCHK(h, hipStreamSynchronize(h->stream));
+            for (size_t k = 0; k < n; ++k) outs[c][k] = tmp[k];
+        }
+    }
+    if (owner)
+        HIPCHK(h, hipMemcpy2DAsync(owner, (size_t)h->p.nx * 4, h->d.O[h->cur], (size_t)h->L.pitch * 4,
+                                   (size_t)h->p.nx * 4, h->p.ny, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return rc;
+}
+
+int lbm_read_particles(lbm_handle h, double* rows10, int32_t* n) {
+    if (!h) return LBM_EINVAL;
+    if (n) *n = h->np;
+    if (!rows10 || h->np == 0) return LBM_OK;
+    int rc = lbm_sync(h);
+    if (rc != LBM_OK && rc != LBM_EUNSTABLE) return rc;
+    std::vector<PState> P(h->np);
+    std::vector<double> F((size_t)4 * h->np);
+    HIPCHK(h, hipMemcpyAsync(P.data(), h->d.P[h->ring], sizeof(PState) * h->np, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipMemcpyAsync(F.data(), h->d.Fh, sizeof(double) * 4 * h->np, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    for (int i = 0; i < h->np; ++i) {
+        double* o = rows10 + 10 * (size_t)i;
+        o[0] = P[i].x; o[1] = P[i].y; o[2] = P[i].r; o[3] = P[i].ux; o[4] = P[i].uy;
+        o[5] = P[i].th; o[6] = P[i].om;
+        o[7] = F[4 * i]; o[8] = F[4 * i + 1]; o[9] = F[4 * i + 2];
+    }
+    return rc;
+}
+
+int lbm_read_links(lbm_handle h, int32_t* node, int32_t* dir, int32_t* particle, double* q, int64_t cap,
+                   int64_t* n_out) {
+    if (!h) return LBM_EINVAL;
+    int rc = lbm_sync(h);
+    if (rc != LBM_OK) return rc;
+    if (n_out) *n_out = 0;
+    if (h->np == 0) return LBM_OK;
+    DevState& d = h->d;
+    // The collection reads the owner map of the current time level; its
+    // clearing of the stale map is idempotent and the next step repeats it.
+    unsigned saved[2];
+    HIPCHK(h, hipMemcpyAsync(saved, d.counter, sizeof saved, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipMemsetAsync(d.counter, 0, sizeof(unsigned), h->stream));
+    HIPCHK(h, launch_compact(d, h->cur, h->ring, h->stream));
+    unsigned nl = 0;
+    HIPCHK(h, hipMemcpyAsync(&nl, d.counter, sizeof nl, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    rc = check_status(h);
+    if (rc != LBM_OK) return rc;
+    if (n_out) *n_out = nl;
+    char* ls = h->base + h->L.off_lscratch;
+    int32_t* dn = (int32_t*)ls;
+    int32_t* dd = dn + nl;
+    int32_t* dp = dd + nl;
+    double* dq = (double*)(ls + round_up((size_t)nl * 12, 8));
+    if (node || dir || particle || q) {
+        if ((int64_t)nl > cap) return fail(h, LBM_EINVAL, "cap %lld < %u links", (long long)cap, nl);
+        HIPCHK(h, launch_link_q(d, h->ring, (int)nl, dn, dd, dp, dq, h->stream));
+        if (node) HIPCHK(h, hipMemcpyAsync(node, dn, nl * 4, hipMemcpyDeviceToHost, h->stream));
+        if (dir) HIPCHK(h, hipMemcpyAsync(dir, dd, nl * 4, hipMemcpyDeviceToHost, h->stream));
+        if (particle) HIPCHK(h, hipMemcpyAsync(particle, dp, nl * 4, hipMemcpyDeviceToHost, h->stream));
+        if (q) HIPCHK(h, hipMemcpyAsync(q, dq, nl * 8, hipMemcpyDeviceToHost, h->stream));
+    }
+    HIPCHK(h, hipMemcpyAsync(d.counter, saved, sizeof saved, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return LBM_OK;
+}
+
+int lbm_time_phases(lbm_handle h, int32_t nsteps, double* ms_out) {
+    if (!h || !ms_out || nsteps <= 0) return h ? fail(h, LBM_EINVAL, "invalid arguments") : LBM_EINVAL;
+    hipEvent_t ev[LBM_NPHASES + 1];
+    for (auto& e : ev) HIPCHK(h, hipEventCreate(&e));
+    double acc[LBM_NPHASES + 1] = {0};
+    int rc = LBM_OK;
+    for (int32_t s = 0; s < nsteps && rc == LBM_OK; ++s) {
+        rc = enqueue_step(h, ev);
+        if (rc != LBM_OK) break;
+        hipError_t e = hipEventSynchronize(ev[LBM_NPHASES]);
+        if (e != hipSuccess) {
+            rc = hip_fail(h, e, "hipEventSynchronize");
+            break;
+        }
+        for (int ph = 0; ph < LBM_NPHASES; ++ph) {
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, ev[ph], ev[ph + 1]);
+            acc[ph] += ms;
+        }
+        float tot = 0.f;
+        (void)hipEventElapsedTime(&tot, ev[0], ev[LBM_NPHASES]);
+        acc[LBM_NPHASES] += tot;
+    }
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    if (rc != LBM_OK) return rc;
+    for (int ph = 0; ph <= LBM_NPHASES; ++ph) ms_out[ph] = acc[ph] / nsteps;
+    return check_status(h);
+}
+
+int lbm_stats(lbm_handle h, double* out5) {
+    if (!h || !out5) return LBM_EINVAL;
+    unsigned c[2] = {0, 0};
+    HIPCHK(h, hipMemcpyAsync(c, h->d.counter, sizeof c, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    out5[0] = (double)h->steps;
+    out5[1] = (double)c[1];
+    out5[2] = (double)h->np;
+    out5[3] = (double)h->p.nx * h->p.ny;
+    out5[4] = (double)h->L.total;
+    return LBM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,352 @@
+// device.h -- device-side building blocks of the gfx950 path: storage
+// policies, the fused D2Q9 + D2Q5 MRT collision in deviation variables, the
+// pull step with flat walls, and the particle-boundary schemes.
+//
+// Method: Xu & Li, arXiv 2308.16597, Sec. 2 (equations cited at each piece).
+// Readings of points the paper leaves open are the same as in the library's
+// header: Lallemand-Luo D2Q9 moment basis, Guo-type forcing in moment space,
+// D2Q5 with n_e^eq = a T, halfway flat walls, Bouzidi fallbacks.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lbm.h"
+
+namespace ptlbm {
+
+// --------------------------------------------------------------- storage ----
+// Populations are kept as deviations from the rest state inside the kernels:
+//   s_i = f_i - w_i rho0,   t_k = g_k - w_k T_sh.
+// Plain modes store f and g themselves (the kernels subtract/add w_i rho0;
+// T_sh is 0 for them); SHIFT_ modes store the deviations directly.
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t b) {
+    return __uint_as_float(((uint32_t)b) << 16);
+}
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+template <int MODE> struct Store;
+template <> struct Store<LBM_STORE_F64> {
+    using T = double; using R = double; static constexpr bool shifted = false;
+    __device__ static R ld(const T* p) { return *p; }
+    __device__ static void st(T* p, R v) { *p = v; }
+};
+template <> struct Store<LBM_STORE_F32> {
+    using T = float; using R = float; static constexpr bool shifted = false;
+    __device__ static R ld(const T* p) { return *p; }
+    __device__ static void st(T* p, R v) { *p = v; }
+};
+template <> struct Store<LBM_STORE_SHIFT_F32> {
+    using T = float; using R = float; static constexpr bool shifted = true;
+    __device__ static R ld(const T* p) { return *p; }
+    __device__ static void st(T* p, R v) { *p = v; }
+};
+template <> struct Store<LBM_STORE_SHIFT_F16> {
+    using T = _Float16; using R = float; static constexpr bool shifted = true;
+    __device__ static R ld(const T* p) { return (float)*p; }
+    __device__ static void st(T* p, R v) { *p = (_Float16)v; }
+};
+template <> struct Store<LBM_STORE_SHIFT_BF16> {
+    using T = uint16_t; using R = float; static constexpr bool shifted = true;
+    __device__ static R ld(const T* p) { return bf16_to_f32(*p); }
+    __device__ static void st(T* p, R v) { *p = f32_to_bf16_rne(v); }
+};
+
+template <class T> struct Pops {
+    T* f[9];
+    T* g[5];
+};
+
+// Lattice constants handed to every kernel (host-filled, FP64).
+struct LP {
+    int nx, ny, pitch, periodic_y;
+    double rho0, gbeta, T_ref, body_fx;
+    double s_e, s_eps, s_q, s_nu;      // D2Q9 rates (the j rates are immaterial)
+    double s_a, s_Te, s_Tp, a_T;       // D2Q5 rates and equilibrium constant
+    double w5_0, w5_k;                 // D2Q5 weights
+    double wall_T[2], wall_ux[2];      // [bottom, top]
+    double T_sh;                       // storage shift of g (0 for plain modes)
+    double particle_T, rho_ratio, gravity, rep_eps, rep_range;
+    int repulsion, np, nwin;           // particles, window edge capacity
+    int link_cap;
+};
+
+// Collision constants in the compute type.
+template <class R> struct CC {
+    R rho0, gbeta, T_ref, body_fx, s_e, s_eps, s_q, s_nu, s_a, s_Te, s_Tp, a_T, T_sh;
+    __device__ explicit CC(const LP& p)
+        : rho0((R)p.rho0), gbeta((R)p.gbeta), T_ref((R)p.T_ref), body_fx((R)p.body_fx),
+          s_e((R)p.s_e), s_eps((R)p.s_eps), s_q((R)p.s_q), s_nu((R)p.s_nu), s_a((R)p.s_a),
+          s_Te((R)p.s_Te), s_Tp((R)p.s_Tp), a_T((R)p.a_T), T_sh((R)p.T_sh) {}
+};
+
+// D2Q9 weights.
+template <class R> __device__ __forceinline__ R w9(int i) {
+    return i == 0 ? (R)(4.0 / 9.0) : (i < 5 ? (R)(1.0 / 9.0) : (R)(1.0 / 36.0));
+}
+__device__ __forceinline__ constexpr int EXd(int i) {
+    return (i == 1 || i == 5 || i == 8) ? 1 : ((i == 3 || i == 6 || i == 7) ? -1 : 0);
+}
+__device__ __forceinline__ constexpr int EYd(int i) {
+    return (i == 2 || i == 5 || i == 6) ? 1 : ((i == 4 || i == 7 || i == 8) ? -1 : 0);
+}
+__device__ __forceinline__ constexpr int OPPd(int i) {
+    return i == 0 ? 0 : (i <= 4 ? ((i + 1) % 4 + 1) : ((i - 5 + 2) % 4 + 5));
+}
+
+// ---------------------------------------------------------------- collide ----
+// Sec. 2.1, Eqs. (5)-(6), in deviation variables.  On entry s[9], t[5] are
+// the pre-collision deviations; on exit the post-collision deviations.
+// Outputs the pre-collision macroscopics rho, u (with the half force) and T.
+//   m = M f, f+ = f - M^-1 [S (m - m^eq) - (I - S/2) Fbar]   (flow)
+//   n = N g, g+ = g - N^-1 Q (n - n^eq)                      (heat)
+// M: Lallemand-Luo rows (rho, e, eps, jx, qx, jy, qy, pxx, pxy), squared
+// norms (9, 36, 36, 6, 12, 6, 12, 4, 4); N: rows (T, jx, jy, e, pxx) with
+// squared norms (5, 2, 2, 20, 4).  The rest state w_i rho0 carries e = -2 rho0,
+// eps = rho0 and nothing else; w_k T_sh carries T_sh and e = a T_sh.
+template <class R>
+__device__ __forceinline__ void collide(const CC<R>& c, R (&s)[9], R (&t)[5], R& rho, R& ux,
+                                        R& uy, R& T) {
+    const R ax = (s[1] + s[2]) + (s[3] + s[4]);
+    const R dg = (s[5] + s[6]) + (s[7] + s[8]);
+    const R drho = (s[0] + ax) + dg;
+    const R jx = (s[1] - s[3]) + ((s[5] - s[6]) + (s[8] - s[7]));
+    const R jy = (s[2] - s[4]) + ((s[5] + s[6]) - (s[7] + s[8]));
+    const R e_s = ((R)-4 * s[0] - ax) + (R)2 * dg;
+    const R eps_s = ((R)4 * s[0] - (R)2 * ax) + dg;
+    const R qx = (R)-2 * (s[1] - s[3]) + ((s[5] - s[6]) + (s[8] - s[7]));
+    const R qy = (R)-2 * (s[2] - s[4]) + ((s[5] + s[6]) - (s[7] + s[8]));
+    const R pxx = (s[1] + s[3]) - (s[2] + s[4]);
+    const R pxy = (s[5] + s[7]) - (s[6] + s[8]);
+
+    const R dT = ((t[0] + t[1]) + (t[2] + t[3])) + t[4];
+    T = c.T_sh + dT;
+    rho = c.rho0 + drho;
+    const R Fx = c.body_fx;
+    const R Fy = rho * c.gbeta * (T - c.T_ref);
+    const R irho = (R)1 / rho;
+    ux = (jx + (R)0.5 * Fx) * irho;
+    uy = (jy + (R)0.5 * Fy) * irho;
+    const R usq = ux * ux + uy * uy;
+    const R uF = ux * Fx + uy * Fy;
+
+    // dm = S (m - m^eq) - (I - S/2) Fbar, moment by moment
+    const R de = c.s_e * ((e_s + (R)2 * drho) - (R)3 * rho * usq) - ((R)1 - (R)0.5 * c.s_e) * ((R)6 * uF);
+    const R deps = c.s_eps * ((eps_s - drho) + (R)3 * rho * usq) + ((R)1 - (R)0.5 * c.s_eps) * ((R)6 * uF);
+    const R djx = -Fx, djy = -Fy;
+    const R dqx = c.s_q * (qx + jx + (R)0.5 * Fx) + ((R)1 - (R)0.5 * c.s_q) * Fx;
+    const R dqy = c.s_q * (qy + jy + (R)0.5 * Fy) + ((R)1 - (R)0.5 * c.s_q) * Fy;
+    const R dpxx = c.s_nu * (pxx - rho * (ux * ux - uy * uy)) -
+                   ((R)1 - (R)0.5 * c.s_nu) * ((R)2 * (ux * Fx - uy * Fy));
+    const R dpxy = c.s_nu * (pxy - rho * ux * uy) - ((R)1 - (R)0.5 * c.s_nu) * (ux * Fy + uy * Fx);
+
+    // f+ = f - M^-1 dm
+    const R A = -de * (R)(1.0 / 36.0) - deps * (R)(1.0 / 18.0);
+    const R Bd = de * (R)(1.0 / 18.0) + deps * (R)(1.0 / 36.0);
+    const R X1 = (djx - dqx) * (R)(1.0 / 6.0);
+    const R Y1 = (djy - dqy) * (R)(1.0 / 6.0);
+    const R X2 = djx * (R)(1.0 / 6.0) + dqx * (R)(1.0 / 12.0);
+    const R Y2 = djy * (R)(1.0 / 6.0) + dqy * (R)(1.0 / 12.0);
+    const R P1 = dpxx * (R)0.25, P2 = dpxy * (R)0.25;
+    s[0] -= (deps - de) * (R)(1.0 / 9.0);
+    s[1] -= (A + X1) + P1;
+    s[2] -= (A + Y1) - P1;
+    s[3] -= (A - X1) + P1;
+    s[4] -= (A - Y1) - P1;
+    s[5] -= (Bd + (X2 + Y2)) + P2;
+    s[6] -= (Bd + (Y2 - X2)) - P2;
+    s[7] -= (Bd - (X2 + Y2)) + P2;
+    s[8] -= (Bd + (X2 - Y2)) - P2;
+
+    // g+ = g - N^-1 dn
+    const R dnx = c.s_a * ((t[1] - t[3]) - ux * T);
+    const R dny = c.s_a * ((t[2] - t[4]) - uy * T);
+    const R dne = c.s_Te * ((((t[1] + t[2]) + (t[3] + t[4])) - (R)4 * t[0]) - c.a_T * dT);
+    const R dnp = c.s_Tp * ((t[1] + t[3]) - (t[2] + t[4]));
+    const R E = dne * (R)(1.0 / 20.0), Pp = dnp * (R)0.25;
+    t[0] += dne * (R)(1.0 / 5.0);
+    t[1] -= (dnx * (R)0.5 + E) + Pp;
+    t[2] -= (dny * (R)0.5 + E) - Pp;
+    t[3] -= (E - dnx * (R)0.5) + Pp;
+    t[4] -= (E - dny * (R)0.5) - Pp;
+}
+
+// Equilibria in deviation variables (second-order D2Q9; D2Q5 with moments
+// (T, ux T, uy T, a T, 0)).
+template <class R>
+__device__ __forceinline__ void feq_dev(R rho, R rho0, R ux, R uy, R (&s)[9]) {
+    const R usq = ux * ux + uy * uy;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const R eu = (R)EXd(i) * ux + (R)EYd(i) * uy;
+        s[i] = w9<R>(i) * (rho - rho0) + w9<R>(i) * rho * ((R)3 * eu + (R)4.5 * eu * eu - (R)1.5 * usq);
+    }
+}
+template <class R>
+__device__ __forceinline__ void geq_dev(R T, R Tsh, R ux, R uy, R w0, R wk, R (&t)[5]) {
+    t[0] = w0 * (T - Tsh);
+#pragma unroll
+    for (int k = 1; k < 5; ++k) t[k] = wk * (T - Tsh) + (R)0.5 * T * ((R)EXd(k) * ux + (R)EYd(k) * uy);
+}
+
+// ------------------------------------------------------------ streaming ----
+// Pull of the 9 + 5 populations arriving at node (x, y) from the
+// post-collision state A, as deviations: flat walls in y by halfway
+// bounce-back (moving tangentially at wall_ux) for f and anti-bounce-back
+// (Dirichlet wall_T) for g; x periodic.  Solid upstream nodes hold the
+// bounce-back values written by the link pass.  Plain modes store f (the
+// rest part w_i rho0 is removed here) and g with T_sh = 0; shifted modes
+// store the deviations.
+template <class S>
+__device__ __forceinline__ void pull_node(const Pops<typename S::T>& A, const LP& lp, int x, int y,
+                                          typename S::R (&s)[9], typename S::R (&t)[5]) {
+    using R = typename S::R;
+    const int nx = lp.nx, ny = lp.ny, pitch = lp.pitch;
+    const int xm = x == 0 ? nx - 1 : x - 1;
+    const int xp = x == nx - 1 ? 0 : x + 1;
+    const bool bot = !lp.periodic_y && y == 0;
+    const bool top = !lp.periodic_y && y == ny - 1;
+    const int ym = y == 0 ? ny - 1 : y - 1;
+    const int yp = y == ny - 1 ? 0 : y + 1;
+    const size_t r0 = (size_t)y * pitch, rm = (size_t)ym * pitch, rp = (size_t)yp * pitch;
+    const size_t k = r0 + x;
+    R fs[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) fs[i] = S::shifted ? (R)0 : w9<R>(i) * (R)lp.rho0;
+    s[0] = S::ld(A.f[0] + k) - fs[0];
+    s[1] = S::ld(A.f[1] + r0 + xm) - fs[1];
+    s[3] = S::ld(A.f[3] + r0 + xp) - fs[3];
+    t[0] = S::ld(A.g[0] + k);
+    t[1] = S::ld(A.g[1] + r0 + xm);
+    t[3] = S::ld(A.g[3] + r0 + xp);
+    const R w5k = (R)lp.w5_k;
+    if (bot) {
+        const R u = (R)lp.wall_ux[0] * (R)lp.rho0 * (R)(1.0 / 6.0);
+        s[2] = S::ld(A.f[4] + k) - fs[4];
+        s[5] = (S::ld(A.f[7] + k) - fs[7]) + u;
+        s[6] = (S::ld(A.f[8] + k) - fs[8]) - u;
+        t[2] = -S::ld(A.g[4] + k) + (R)2 * w5k * ((R)lp.wall_T[0] - (R)lp.T_sh);
+    } else {
+        s[2] = S::ld(A.f[2] + rm + x) - fs[2];
+        s[5] = S::ld(A.f[5] + rm + xm) - fs[5];
+        s[6] = S::ld(A.f[6] + rm + xp) - fs[6];
+        t[2] = S::ld(A.g[2] + rm + x);
+    }
+    if (top) {
+        const R u = (R)lp.wall_ux[1] * (R)lp.rho0 * (R)(1.0 / 6.0);
+        s[4] = S::ld(A.f[2] + k) - fs[2];
+        s[7] = (S::ld(A.f[5] + k) - fs[5]) - u;
+        s[8] = (S::ld(A.f[6] + k) - fs[6]) + u;
+        t[4] = -S::ld(A.g[2] + k) + (R)2 * w5k * ((R)lp.wall_T[1] - (R)lp.T_sh);
+    } else {
+        s[4] = S::ld(A.f[4] + rp + x) - fs[4];
+        s[7] = S::ld(A.f[7] + rp + xp) - fs[7];
+        s[8] = S::ld(A.f[8] + rp + xm) - fs[8];
+        t[4] = S::ld(A.g[4] + rp + x);
+    }
+}
+
+template <class S>
+__device__ __forceinline__ void store_node(const Pops<typename S::T>& B, const LP& lp, size_t k,
+                                           const typename S::R (&s)[9], const typename S::R (&t)[5]) {
+    using R = typename S::R;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) S::st(B.f[i] + k, s[i] + (S::shifted ? (R)0 : w9<R>(i) * (R)lp.rho0));
+#pragma unroll
+    for (int k5 = 0; k5 < 5; ++k5) S::st(B.g[k5] + k, t[k5]);
+}
+
+// ------------------------------------------------------------- geometry ----
+// The exact solid test shared by every kernel that builds or reads the
+// solid map: dx = (i - X) with the minimum image along the periodic x axis,
+// dy = j - Y, inside when dx*dx + dy*dy <= r*r (no fused multiply-add: the
+// translation unit is compiled with -ffp-contract=off).
+__device__ __forceinline__ double min_image_x(double d, int nx) {
+    const double h = 0.5 * nx;
+    if (d > h) return d - nx;
+    if (d < -h) return d + nx;
+    return d;
+}
+
+struct PState {   // one particle, FP64
+    double x, y, r, ux, uy, th, om, pad;
+};
+
+// Window of a particle (Sec. 3): x from INT(x_c - r) - 1 to INT(x_c + r) + 1
+// and likewise in y, INT read as floor.
+struct Win {
+    int x0, y0, nxw, nyw;
+};
+__device__ __forceinline__ Win window_of(const PState& P) {
+    Win w;
+    const int xa = (int)floor(P.x - P.r), xb = (int)floor(P.x + P.r);
+    const int ya = (int)floor(P.y - P.r), yb = (int)floor(P.y + P.r);
+    w.x0 = xa - 1;
+    w.y0 = ya - 1;
+    w.nxw = xb - xa + 3;
+    w.nyw = yb - ya + 3;
+    return w;
+}
+// A particle whose state is not finite or far outside the lattice is not
+// processed (its kernels would address outside the buffers); the step
+// reports it through the status word.
+__device__ __forceinline__ bool particle_ok(const PState& P, const LP& lp) {
+    return isfinite(P.x) && isfinite(P.y) && isfinite(P.r) && P.x >= -lp.nx && P.x <= 2.0 * lp.nx &&
+           P.y >= -(double)lp.ny && P.y <= 2.0 * lp.ny;
+}
+__device__ __forceinline__ int wrap_x(int x, int nx) {
+    x %= nx;
+    return x < 0 ? x + nx : x;
+}
+
+// Link fraction q of Sec. 2.3 for the circle: the nearer root of
+// |d + t e_i|^2 = r^2, clamped to [0, 1].
+__device__ __forceinline__ double link_q(double dx, double dy, double r, int i) {
+    const double ex = EXd(i), ey = EYd(i);
+    const double a = ex * ex + ey * ey;
+    const double b = dx * ex + dy * ey;
+    const double c = (dx * dx + dy * dy) - r * r;
+    double disc = b * b - a * c;
+    if (disc < 0.0) disc = 0.0;
+    double q = (-b - sqrt(disc)) / a;
+    if (q < 0.0) q = 0.0;
+    if (q > 1.0) q = 1.0;
+    return q;
+}
+
+// Interpolated bounce-back, Sec. 2.3 Eqs. (9)-(10), with the linear and
+// halfway fallbacks when stencil nodes are not fluid.  Works on stored
+// values of any mode: the coefficients sum to one and f_i, f_ibar share the
+// same rest weight.  wall = 2 w_i rho0 (e_ibar . u_w)/cs^2.
+__device__ __forceinline__ double bouzidi(double q, double fi, double fi1, double fi2, double fib,
+                                          double fib1, bool have1, bool have2, double wall) {
+    if (q <= 0.5) {
+        if (have1 && have2)
+            return q * (2.0 * q + 1.0) * fi + (1.0 - 4.0 * q * q) * fi1 - q * (1.0 - 2.0 * q) * fi2 + wall;
+        if (have1) return 2.0 * q * fi + (1.0 - 2.0 * q) * fi1 + wall;
+        return fi + wall;
+    }
+    const double a = 1.0 / (q * (2.0 * q + 1.0));
+    if (have1) return a * fi + (2.0 * q - 1.0) / q * fib - (2.0 * q - 1.0) / (2.0 * q + 1.0) * fib1 + a * wall;
+    return 1.0 / (2.0 * q) * fi + (2.0 * q - 1.0) / (2.0 * q) * fib + wall / (2.0 * q);
+}
+
+// Thermal curved wall, Sec. 2.3 Eqs. (11)-(12), on stored values whose rest
+// part is w T_store (T_store = T_sh for shifted storage, 0 for plain):
+// g_ibar = -g_i + c (g_i(x_f - e_i) + g_ibar) + c4 2 w (T_w - T_store),
+// c = (2q-1)/(2q+1), c4 = 2/(2q+1); anti-bounce-back without x_f - e_i.
+__device__ __forceinline__ double thermal_link(double q, double gi, double gi1, double gib, bool have1,
+                                               double w, double Tw_rel) {
+    if (!have1) return -gi + 2.0 * w * Tw_rel;
+    const double c = (2.0 * q - 1.0) / (2.0 * q + 1.0);
+    const double c4 = 2.0 / (2.0 * q + 1.0);
+    return (-gi + c * gi1 + c * gib) + c4 * (2.0 * w * Tw_rel);
+}
+
+}  // namespace ptlbm

@@ -1,0 +1,74 @@
+"""Shared helpers of the GPU parity tests: build the same run on the GPU
+library and on the CPU oracle from one parameter dict, and compare."""
+import numpy as np
+
+from oracle import Oracle
+
+ORACLE_KEYS = {"nx", "ny", "periodic_x", "periodic_y", "rho0", "nu", "alpha", "gravity", "beta",
+               "T_ref", "body_fx", "s_e", "s_eps", "s_q", "a_T", "sT_e", "sT_p", "wall_T",
+               "wall_ux", "T_fluid0", "particle_T", "rho_ratio", "repulsion", "rep_eps",
+               "rep_range"}
+
+
+def make_pair(torch_memory=True, **kw):
+    """(gpu Sim, Oracle) with identical physics; library-only keys (storage,
+    max_particles, max_diameter, T_shift) go to the GPU side only."""
+    from paper_2308_16597_amd import lbm
+    sim = lbm.Sim(lbm.lbm_params_default(**kw), torch_memory=torch_memory)
+    orc = Oracle(**{k: v for k, v in kw.items() if k in ORACLE_KEYS})
+    return sim, orc
+
+
+def rel_err(a, b, mask):
+    scale = np.abs(b[mask]).max()
+    if scale == 0:
+        scale = 1.0
+    return np.abs(a[mask] - b[mask]).max() / scale
+
+
+def compare_fields(fg, fo, tol=1e-12, keys=("rho", "ux", "uy", "T")):
+    np.testing.assert_array_equal(fg["owner"], fo["owner"])
+    fluid = fo["owner"] < 0
+    errs = {k: rel_err(fg[k], fo[k], fluid) for k in keys}
+    assert np.isnan(fg["rho"][~fluid]).all()
+    for k, e in errs.items():
+        assert e <= tol, (k, e, errs)
+    return errs
+
+
+def compare_particles(pg, po, tol=1e-12):
+    assert pg.shape == po.shape
+    if len(po) == 0:
+        return {}
+    dx = pg[:, 0] - po[:, 0]
+    nx_wrap = np.abs(dx) > 1.0
+    assert not nx_wrap.any(), "particle wrapped differently"
+    errs = dict(
+        pos=np.abs(pg[:, :2] - po[:, :2]).max() / max(1.0, np.abs(po[:, :2]).max()),
+        vel=np.abs(pg[:, 3:5] - po[:, 3:5]).max() / max(1e-300, np.abs(po[:, 3:5]).max()),
+        omega=np.abs(pg[:, 6] - po[:, 6]).max() / max(1e-300, np.abs(po[:, 6]).max()),
+        theta=np.abs(pg[:, 5] - po[:, 5]).max() / max(1e-300, np.abs(po[:, 5]).max()),
+        force=np.abs(pg[:, 7:9] - po[:, 7:9]).max() / max(1e-300, np.abs(po[:, 7:9]).max()),
+        torque=np.abs(pg[:, 9] - po[:, 9]).max() / max(1e-300, np.abs(po[:, 9]).max()),
+    )
+    np.testing.assert_array_equal(pg[:, 2], po[:, 2])
+    for k in ("pos", "vel", "omega", "theta"):
+        assert errs[k] <= tol, (k, errs)
+    for k in ("force", "torque"):
+        assert errs[k] <= 1e3 * tol, (k, errs)
+    return errs
+
+
+def sorted_links(L):
+    order = np.lexsort((L["particle"], L["dir"], L["node"]))
+    return {k: v[order] for k, v in L.items()}
+
+
+def compare_links(lg, lo, q_ulps=2):
+    a, b = sorted_links(lg), sorted_links(lo)
+    assert len(a["node"]) == len(b["node"])
+    for k in ("node", "dir", "particle"):
+        np.testing.assert_array_equal(a[k], b[k])
+    dq = np.abs(a["q"] - b["q"])
+    assert (dq <= q_ulps * np.spacing(np.maximum(np.abs(b["q"]), 1e-300)) + 0.0).all() or dq.max() == 0
+    return len(a["node"]), dq.max() if len(dq) else 0.0

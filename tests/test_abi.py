@@ -1,0 +1,66 @@
+"""The C ABI library on the host: it loads, exports every function the header
+declares, validates parameters before touching the GPU, and seeds particles
+bit-identically to the shared input generator."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import lbm_inputs
+from paper_2308_16597_amd import lbm
+
+
+def test_every_declared_function_is_exported():
+    names = lbm.declared_functions()
+    assert len(names) >= 17
+    so = ctypes.CDLL(lbm.LIB_PATH)
+    for n in names:
+        assert hasattr(so, n), n
+
+
+def test_abi_version_and_defaults():
+    assert lbm.lbm_abi_version() == 1
+    p = lbm.lbm_params_default()
+    assert (p.abi_version, p.nx, p.ny, p.periodic_x, p.periodic_y, p.storage) == (1, 64, 64, 1, 0, 0)
+    assert (p.rho0, p.a_T, p.rep_eps, p.rep_range, p.repulsion) == (1.0, -2.0, 1e-3, 3.0, 1)
+
+
+@pytest.mark.parametrize("bad", [dict(nx=4), dict(ny=70000), dict(periodic_x=0), dict(storage=9),
+                                 dict(nu=0.0), dict(alpha=-1.0), dict(s_q=2.5), dict(a_T=-5.0),
+                                 dict(max_particles=-1),
+                                 dict(max_particles=10, max_diameter=2.0),
+                                 dict(max_particles=10, max_diameter=12.0, periodic_y=1),
+                                 dict(nx=16, max_particles=10, max_diameter=14.0),
+                                 dict(gravity=float("inf")), dict(abi_version=7)])
+def test_invalid_parameters_rejected_on_the_host(bad):
+    p = lbm.lbm_params_default(**bad)
+    assert lbm.lbm_bytes_required(p) == 0
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_create(p)
+    assert e.value.rc == lbm.LBM_EINVAL
+    assert lbm.lbm_last_error()
+
+
+def test_bytes_required_grows_with_the_lattice_and_storage():
+    small = lbm.lbm_bytes_required(lbm.lbm_params_default(nx=256, ny=256))
+    big = lbm.lbm_bytes_required(lbm.lbm_params_default(nx=512, ny=256))
+    half = lbm.lbm_bytes_required(lbm.lbm_params_default(nx=512, ny=256, storage="shift_bf16"))
+    assert 0 < small < big and half < big
+    # 4000^2 in FP64 with 4800 particles: two time levels of 14 arrays dominate
+    p = lbm.lbm_params_default(nx=4000, ny=4000, max_particles=4800, max_diameter=20.0)
+    assert 2 * 14 * 4000 * 4000 * 8 < lbm.lbm_bytes_required(p) < 4.2e9
+
+
+@pytest.mark.parametrize("nx,ny,n,d,gap,seed", [(256, 256, 20, 12.0, 1.0, 1),
+                                                (4000, 4000, 4800, 20.0, 1.0, 2),
+                                                (300, 200, 120, 9.0, 2.0, 77)])
+def test_rsa_seed_is_bit_identical_to_the_input_generator(nx, ny, n, d, gap, seed):
+    a = lbm.lbm_rsa_seed(nx, ny, n, d, gap, seed)
+    b = lbm_inputs.rsa_particles(nx, ny, n, d, gap, seed)
+    np.testing.assert_array_equal(a, b)
+
+
+def test_rsa_seed_reports_infeasible_packing():
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_rsa_seed(32, 32, 40, 10.0, 1.0, 1)
+    assert e.value.rc == lbm.LBM_ESEED
