@@ -152,9 +152,9 @@ const char* lbm_last_error(lbm_handle h);
  * an nx x ny channel, written to rows7 (n rows of x, y, r, ux, uy, theta,
  * omega; at rest).  Candidates come from SplitMix64 (x then y, each the top
  * 53 bits of an output times 2^-53, x scaled by nx, y into
- * [r + 1/2, ny - 3/2 - r]); a candidate is accepted when its surface gap to
- * every accepted disk (minimum image along x) is >= min_gap.  Fails with
- * LBM_ESEED after 1000 n attempts. */
+ * [min_gap - 1/2 + r, ny - 1/2 - min_gap - r]); a candidate is accepted when
+ * its surface gap to every accepted disk (minimum image along x) is
+ * >= min_gap.  Fails with LBM_ESEED after 1000 n attempts. */
 int lbm_rsa_seed(int32_t nx, int32_t ny, int32_t n, double diameter, double min_gap,
                  uint64_t seed, double* rows7);
 

@@ -13,8 +13,8 @@ variant-13 finaliser of MurmurHash3.  A uniform double in [0, 1) is the top
 Particle seeding is random sequential addition: candidate centres are drawn
 uniformly (x first, then y) and accepted when the surface gap to every
 accepted particle is at least `min_gap` (minimum image along the periodic x
-axis) and the disk keeps one lattice spacing from both flat walls, which sit
-halfway between nodes at y = -1/2 and y = ny - 1/2.  After 1000 * n attempts
+axis) and the disk keeps the same clearance `min_gap` from both flat walls,
+which sit halfway between nodes at y = -1/2 and y = ny - 1/2.  After 1000 * n attempts
 without completing the set, seeding fails.
 """
 import math
@@ -52,8 +52,8 @@ def rsa_particles(nx, ny, n, diameter, min_gap=1.0, seed=1):
     centres.
     """
     r = 0.5 * diameter
-    ylo = (-0.5 + 1.0) + r
-    yhi = (ny - 0.5 - 1.0) - r
+    ylo = (-0.5 + min_gap) + r
+    yhi = ((ny - 0.5) - min_gap) - r
     if n < 0 or not (r > 0.0):
         raise ValueError("need n >= 0 and diameter > 0")
     if n > 0 and yhi < ylo:

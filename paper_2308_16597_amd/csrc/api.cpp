@@ -357,8 +357,8 @@ int lbm_rsa_seed(int32_t nx, int32_t ny, int32_t n, double diameter, double min_
     if (n < 0 || !(diameter > 0) || nx < 1 || ny < 1 || (n > 0 && !rows7))
         return fail(nullptr, LBM_EINVAL, "invalid seeding arguments");
     const double r = 0.5 * diameter;
-    const double ylo = (-0.5 + 1.0) + r;
-    const double yhi = ((ny - 0.5) - 1.0) - r;
+    const double ylo = (-0.5 + min_gap) + r;
+    const double yhi = ((ny - 0.5) - min_gap) - r;
     if (n > 0 && yhi < ylo) return fail(nullptr, LBM_ESEED, "channel too narrow for the particles");
     // SplitMix64 (Steele, Lea & Flood 2014)
     uint64_t state = seed;

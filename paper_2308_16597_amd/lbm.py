@@ -13,6 +13,14 @@ import re
 
 import numpy as np
 
+try:
+    # torch ships its own HIP runtime (libamdhip64.so); loading torch first makes
+    # the library bind to that same runtime instead of a second copy from
+    # /opt/rocm, so that torch-allocated arenas and streams are valid here.
+    import torch  # noqa: F401
+except ImportError:
+    torch = None
+
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libptlbm.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "lbm.h")

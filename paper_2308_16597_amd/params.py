@@ -53,13 +53,15 @@ def from_dimensionless(H, Ra, Pr, d, rho_ratio, Ma=0.1):
 # Workloads: sizes and physics of the cases the library is exercised on.
 WORKLOADS = {
     # 256^2 channel, 20 hot particles of diameter 12, Pr 0.7, Ra 1e5, 200 steps
-    "small": dict(nx=256, ny=256, n=20, d=12.0, seed=1, Ra=1e5, Pr=0.7, rho_ratio=1.5, steps=200),
-    # 4000^2 channel, 4800 hot particles of diameter 20, Pr 0.7, Ra 1e8, 2000 steps
-    "paper_scale": dict(nx=4000, ny=4000, n=4800, d=20.0, seed=2, Ra=1e8, Pr=0.7, rho_ratio=1.5,
-                        steps=2000),
+    "small": dict(nx=256, ny=256, n=20, d=12.0, seed=1, gap=1.0, Ra=1e5, Pr=0.7, rho_ratio=1.5,
+                  steps=200),
+    # 4000^2 channel, 4800 hot particles of diameter 20, Pr 0.7, Ra 1e8, 2000 steps;
+    # seeded outside the repulsion range s = 3 of each other and of the walls
+    "paper_scale": dict(nx=4000, ny=4000, n=4800, d=20.0, seed=2, gap=3.0, Ra=1e8, Pr=0.7,
+                        rho_ratio=1.5, steps=2000),
     # 4096^2, 64000 particles of diameter 10 (30 % solid), Ra 1e8
-    "dense": dict(nx=4096, ny=4096, n=64000, d=10.0, seed=5, Ra=1e8, Pr=0.7, rho_ratio=1.5,
-                  steps=1000),
+    "dense": dict(nx=4096, ny=4096, n=64000, d=10.0, seed=5, gap=1.0, Ra=1e8, Pr=0.7,
+                  rho_ratio=1.5, steps=1000),
 }
 
 

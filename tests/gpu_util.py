@@ -19,17 +19,24 @@ def make_pair(torch_memory=True, **kw):
     return sim, orc
 
 
-def rel_err(a, b, mask):
-    scale = np.abs(b[mask]).max()
+def rel_err(a, b, mask, floor=0.0):
+    scale = max(np.abs(b[mask]).max(), floor)
     if scale == 0:
         scale = 1.0
     return np.abs(a[mask] - b[mask]).max() / scale
 
 
-def compare_fields(fg, fo, tol=1e-12, keys=("rho", "ux", "uy", "T")):
+# Characteristic velocity of the particle workloads: the free-fall velocity
+# U_ff = Ma c_s (Ma = 0.1) their parameters are built on.  FP64 rounding of u
+# is absolute (u is a difference of O(rho0) population sums), so a velocity
+# field that is still near zero is compared against this scale.
+U_FF = 0.1 / np.sqrt(3.0)
+
+
+def compare_fields(fg, fo, tol=1e-12, keys=("rho", "ux", "uy", "T"), u_floor=0.0):
     np.testing.assert_array_equal(fg["owner"], fo["owner"])
     fluid = fo["owner"] < 0
-    errs = {k: rel_err(fg[k], fo[k], fluid) for k in keys}
+    errs = {k: rel_err(fg[k], fo[k], fluid, u_floor if k in ("ux", "uy") else 0.0) for k in keys}
     assert np.isnan(fg["rho"][~fluid]).all()
     for k, e in errs.items():
         assert e <= tol, (k, e, errs)
@@ -64,11 +71,17 @@ def sorted_links(L):
     return {k: v[order] for k, v in L.items()}
 
 
-def compare_links(lg, lo, q_ulps=2):
+def compare_links(lg, lo, q_ulps=2, q_abs=None):
+    """Link sets equal; q within q_ulps ulp (bit-identical particle input) or
+    within q_abs (after steps, when positions differ by rounding)."""
     a, b = sorted_links(lg), sorted_links(lo)
     assert len(a["node"]) == len(b["node"])
     for k in ("node", "dir", "particle"):
         np.testing.assert_array_equal(a[k], b[k])
     dq = np.abs(a["q"] - b["q"])
-    assert (dq <= q_ulps * np.spacing(np.maximum(np.abs(b["q"]), 1e-300)) + 0.0).all() or dq.max() == 0
+    if len(dq):
+        if q_abs is None:
+            assert (dq <= q_ulps * np.spacing(np.maximum(np.abs(b["q"]), 1e-300))).all(), dq.max()
+        else:
+            assert dq.max() <= q_abs, dq.max()
     return len(a["node"]), dq.max() if len(dq) else 0.0
