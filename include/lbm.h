@@ -16,7 +16,8 @@
  *   5. the fused pull-stream + collide of the D2Q9 flow and D2Q5 heat MRT
  *      models with Boussinesq buoyancy (Sec. 2.1, Eqs. (5)-(6)) over the
  *      whole lattice, flat walls included;
- *   6. refilling of newly uncovered fluid nodes (Sec. 2.5, Eqs. (16)-(17)).
+ *   6. refilling (and collision) of newly uncovered fluid nodes (Sec. 2.5,
+ *      Eqs. (16)-(17)).
  *
  * Geometry: node (i, j) is at (x, y) = (i, j), 0 <= i < nx, 0 <= j < ny; x is
  * periodic; the flat walls are halfway between nodes, at y = -1/2 and
@@ -38,6 +39,9 @@
  *     array overflow) are reported by the next waiting call as
  *     LBM_EUNSTABLE.
  *   - A handle is not thread-safe; distinct handles are independent.
+ *   - Particle neighbours are searched on a cell grid of cells at least
+ *     max_diameter + rep_range wide holding at most 7 particles each; a fuller
+ *     cell is reported as LBM_EUNSTABLE.
  */
 #ifndef LBM_H
 #define LBM_H
@@ -108,13 +112,12 @@ typedef struct {
 
 /* Phases reported by lbm_time_phases, in launch order. */
 enum {
-    LBM_PHASE_COMPACT = 0,   /* link collection (and clearing of stale maps) */
-    LBM_PHASE_LINKS = 1,     /* bounce-back, thermal wall, momentum exchange */
-    LBM_PHASE_PARTICLES = 2, /* reduction, repulsion, Newton-Euler */
-    LBM_PHASE_MASK = 3,      /* solid map at the new positions */
-    LBM_PHASE_REFILL = 4,    /* refilling of newborn nodes (and node flags) */
-    LBM_PHASE_LATTICE = 5,   /* fused stream + collide over the lattice */
-    LBM_NPHASES = 6
+    LBM_PHASE_LINKS = 0,     /* link collection, bounce-back, thermal wall, momentum exchange */
+    LBM_PHASE_PARTICLES = 1, /* repulsion, net weight, Newton-Euler */
+    LBM_PHASE_MASK = 2,      /* solid map at the new positions */
+    LBM_PHASE_LATTICE = 3,   /* fused stream + collide over the lattice */
+    LBM_PHASE_REFILL = 4,    /* refilling of newborn nodes */
+    LBM_NPHASES = 5
 };
 
 /* Library ABI version (LBM_ABI_VERSION). */

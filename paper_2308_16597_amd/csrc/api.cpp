@@ -43,9 +43,11 @@ struct Layout {
     int pitch = 0;
     size_t npitched = 0, array_stride = 0, state_bytes = 0;
     size_t off_S[2] = {0, 0}, off_O[2] = {0, 0}, off_flag = 0, off_P = 0, off_Fh = 0, off_seg = 0,
-           off_links = 0, off_lscratch = 0, off_counter = 0, off_status = 0, total = 0;
+           off_links = 0, off_lscratch = 0, off_counter = 0, off_status = 0, off_bins[2] = {0, 0},
+           off_bcnt[2] = {0, 0}, off_cand = 0, off_ncand = 0, total = 0;
     int nwin = 0;
     size_t link_cap = 0;
+    int ncx = 1, ncy = 1;
 };
 
 Layout make_layout(const lbm_params& p) {
@@ -71,6 +73,17 @@ Layout make_layout(const lbm_params& p) {
     L.off_lscratch = off; off = round_up(off + L.link_cap * (3 * sizeof(int32_t) + sizeof(double)), kAlign);
     L.off_counter = off; off = round_up(off + 64, kAlign);
     L.off_status = off; off = round_up(off + 64, kAlign);
+    // neighbour-search cells at least 2 r_max + s wide
+    const double cell = (p.max_diameter > 0 ? p.max_diameter : 2.0) + (p.rep_range > 0 ? p.rep_range : 0.0);
+    L.ncx = std::max(1, (int)std::floor(p.nx / cell));
+    L.ncy = std::max(1, (int)std::floor(p.ny / cell));
+    const size_t ncells = cap > 0 ? (size_t)L.ncx * L.ncy : 0;
+    for (int b = 0; b < 2; ++b) {
+        L.off_bins[b] = off; off = round_up(off + ncells * BINCAP * sizeof(unsigned), kAlign);
+        L.off_bcnt[b] = off; off = round_up(off + ncells * sizeof(unsigned), kAlign);
+    }
+    L.off_cand = off; off = round_up(off + cap * 4 * (size_t)L.nwin * sizeof(unsigned), kAlign);
+    L.off_ncand = off; off = round_up(off + cap * sizeof(unsigned), kAlign);
     L.total = off;
     return L;
 }
@@ -87,6 +100,7 @@ struct lbm_sim {
     bool own_mem = false;
     int cur = 0;    // time level holding the current (post-collision) state
     int ring = 0;   // particle slot of the current time level
+    int bin_parity = 0;  // cell grid holding the particles of the current time level
     int np = 0;
     int64_t steps = 0;
     std::string err;
@@ -193,6 +207,9 @@ void fill_lp(lbm_sim* h) {
     lp.np = 0;
     lp.nwin = h->L.nwin;
     lp.link_cap = (int)h->L.link_cap;
+    lp.ncx = h->L.ncx;
+    lp.ncy = h->L.ncy;
+    lp.ncells = p.max_particles > 0 ? h->L.ncx * h->L.ncy : 0;
 }
 
 int create_common(const lbm_params* p, void* dev_ptr, size_t bytes, void* stream, lbm_handle* out) {
@@ -244,6 +261,12 @@ int create_common(const lbm_params* p, void* dev_ptr, size_t bytes, void* stream
     d.links = (uint2*)(h->base + L.off_links);
     d.counter = (unsigned*)(h->base + L.off_counter);
     d.status = (unsigned*)(h->base + L.off_status);
+    for (int b = 0; b < 2; ++b) {
+        d.bins[b] = (unsigned*)(h->base + L.off_bins[b]);
+        d.bcnt[b] = (unsigned*)(h->base + L.off_bcnt[b]);
+    }
+    d.cand = (unsigned*)(h->base + L.off_cand);
+    d.ncand = (unsigned*)(h->base + L.off_ncand);
     fill_lp(h);
     *out = h;
     int rc = lbm_set_particles(h, 0, nullptr);
@@ -265,6 +288,8 @@ int check_status(lbm_sim* h) {
     if (st & ST_OVERSPEED) m += " a particle moved more than 0.5 in one step;";
     if (st & ST_LINK_OVERFLOW) m += " link array overflow;";
     if (st & ST_BAD_PARTICLE) m += " particle state not finite or outside the lattice;";
+    if (st & ST_BIN_OVERFLOW) m += " more than 7 particles in one neighbour-search cell;";
+    if (st & ST_CAND_OVERFLOW) m += " too many newborn nodes for one particle in one step;";
     return fail(h, LBM_EUNSTABLE, "%s", m.c_str());
 }
 
@@ -277,21 +302,21 @@ int enqueue_step(lbm_sim* h, hipEvent_t* ev) {
         if (ev) (void)hipEventRecord(ev[ph], st);
         ++ph;
     };
+    const int bp = h->bin_parity;
     mark();
-    HIPCHK(h, launch_compact(d, c, r, st));
+    HIPCHK(h, launch_links(d, c, r, true, st));
     mark();
-    HIPCHK(h, launch_link_pass(d, c, r, st));
+    HIPCHK(h, launch_particles(d, r, bp, st));
     mark();
-    HIPCHK(h, launch_particles(d, r, st));
-    mark();
-    HIPCHK(h, launch_mask_mark(d, 1 - c, d.P[ring_next(r)], st));
-    mark();
-    HIPCHK(h, launch_refill(d, c, r, st));
+    HIPCHK(h, launch_mask_mark(d, 1 - c, d.P[ring_next(r)], d.P[r], d.bcnt[bp], st));
     mark();
     HIPCHK(h, launch_stream_collide(d, c, st));
     mark();
+    HIPCHK(h, launch_refill(d, c, r, st));
+    mark();
     h->cur = 1 - c;
     h->ring = ring_next(r);
+    h->bin_parity = 1 - bp;
     h->steps += 1;
     return LBM_OK;
 }
@@ -455,6 +480,7 @@ int lbm_set_particles(lbm_handle h, int32_t n, const double* rows7) {
     d.lp.np = n;
     h->cur = 0;
     h->ring = 0;
+    h->bin_parity = 0;
     const size_t nb = h->L.npitched;
     HIPCHK(h, hipMemsetAsync(d.O[0], 0xff, nb * 4, st));
     HIPCHK(h, hipMemsetAsync(d.O[1], 0xff, nb * 4, st));
@@ -466,7 +492,11 @@ int lbm_set_particles(lbm_handle h, int32_t n, const double* rows7) {
             HIPCHK(h, hipMemcpyAsync(d.P[r], P.data(), sizeof(PState) * n, hipMemcpyHostToDevice, st));
         HIPCHK(h, hipMemsetAsync(d.Fh, 0, sizeof(double) * 4 * n, st));
         HIPCHK(h, hipMemsetAsync(d.seg, 0, sizeof(int2) * n, st));
-        HIPCHK(h, launch_mask_mark(d, 0, d.P[0], st));
+        for (int b = 0; b < 2; ++b)
+            HIPCHK(h, hipMemsetAsync(d.bcnt[b], 0, sizeof(unsigned) * (size_t)d.lp.ncells, st));
+        HIPCHK(h, hipMemsetAsync(d.ncand, 0, sizeof(unsigned) * n, st));
+        HIPCHK(h, launch_mask_mark(d, 0, d.P[0], nullptr, nullptr, st));
+        HIPCHK(h, launch_bin_init(d, d.P[0], 0, st));
     }
     HIPCHK(h, launch_init(d, 0, nullptr, nullptr, nullptr, nullptr, true, h->p.rho0, h->p.T_fluid0, st));
     HIPCHK(h, hipStreamSynchronize(st));
@@ -580,7 +610,7 @@ int lbm_read_links(lbm_handle h, int32_t* node, int32_t* dir, int32_t* particle,
     unsigned saved[2];
     HIPCHK(h, hipMemcpyAsync(saved, d.counter, sizeof saved, hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipMemsetAsync(d.counter, 0, sizeof(unsigned), h->stream));
-    HIPCHK(h, launch_compact(d, h->cur, h->ring, h->stream));
+    HIPCHK(h, launch_links(d, h->cur, h->ring, false, h->stream));
     unsigned nl = 0;
     HIPCHK(h, hipMemcpyAsync(&nl, d.counter, sizeof nl, hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));

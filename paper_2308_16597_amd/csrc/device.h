@@ -36,26 +36,31 @@ template <> struct Store<LBM_STORE_F64> {
     using T = double; using R = double; static constexpr bool shifted = false;
     __device__ static R ld(const T* p) { return *p; }
     __device__ static void st(T* p, R v) { *p = v; }
+    __device__ static void st_nt(T* p, R v) { __builtin_nontemporal_store(v, p); }
 };
 template <> struct Store<LBM_STORE_F32> {
     using T = float; using R = float; static constexpr bool shifted = false;
     __device__ static R ld(const T* p) { return *p; }
     __device__ static void st(T* p, R v) { *p = v; }
+    __device__ static void st_nt(T* p, R v) { __builtin_nontemporal_store(v, p); }
 };
 template <> struct Store<LBM_STORE_SHIFT_F32> {
     using T = float; using R = float; static constexpr bool shifted = true;
     __device__ static R ld(const T* p) { return *p; }
     __device__ static void st(T* p, R v) { *p = v; }
+    __device__ static void st_nt(T* p, R v) { __builtin_nontemporal_store(v, p); }
 };
 template <> struct Store<LBM_STORE_SHIFT_F16> {
     using T = _Float16; using R = float; static constexpr bool shifted = true;
     __device__ static R ld(const T* p) { return (float)*p; }
     __device__ static void st(T* p, R v) { *p = (_Float16)v; }
+    __device__ static void st_nt(T* p, R v) { __builtin_nontemporal_store((_Float16)v, p); }
 };
 template <> struct Store<LBM_STORE_SHIFT_BF16> {
     using T = uint16_t; using R = float; static constexpr bool shifted = true;
     __device__ static R ld(const T* p) { return bf16_to_f32(*p); }
     __device__ static void st(T* p, R v) { *p = f32_to_bf16_rne(v); }
+    __device__ static void st_nt(T* p, R v) { __builtin_nontemporal_store(f32_to_bf16_rne(v), p); }
 };
 
 template <class T> struct Pops {
@@ -75,7 +80,12 @@ struct LP {
     double particle_T, rho_ratio, gravity, rep_eps, rep_range;
     int repulsion, np, nwin;           // particles, window edge capacity
     int link_cap;
+    int ncx, ncy, ncells;              // neighbour-search cell grid
 };
+
+// Particles per cell of the neighbour-search grid (cells are at least
+// 2 r_max + s wide, so a cell of non-overlapping disks holds at most 4).
+constexpr int BINCAP = 7;
 
 // Collision constants in the compute type.
 template <class R> struct CC {
@@ -252,14 +262,23 @@ __device__ __forceinline__ void pull_node(const Pops<typename S::T>& A, const LP
     }
 }
 
-template <class S>
+// Store of the 14 post-collision values of node k; NT selects non-temporal
+// (streaming) stores.
+template <class S, bool NT = false>
 __device__ __forceinline__ void store_node(const Pops<typename S::T>& B, const LP& lp, size_t k,
                                            const typename S::R (&s)[9], const typename S::R (&t)[5]) {
     using R = typename S::R;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) S::st(B.f[i] + k, s[i] + (S::shifted ? (R)0 : w9<R>(i) * (R)lp.rho0));
+    for (int i = 0; i < 9; ++i) {
+        const R v = s[i] + (S::shifted ? (R)0 : w9<R>(i) * (R)lp.rho0);
+        if (NT) S::st_nt(B.f[i] + k, v);
+        else S::st(B.f[i] + k, v);
+    }
 #pragma unroll
-    for (int k5 = 0; k5 < 5; ++k5) S::st(B.g[k5] + k, t[k5]);
+    for (int k5 = 0; k5 < 5; ++k5) {
+        if (NT) S::st_nt(B.g[k5] + k, t[k5]);
+        else S::st(B.g[k5] + k, t[k5]);
+    }
 }
 
 // ------------------------------------------------------------- geometry ----

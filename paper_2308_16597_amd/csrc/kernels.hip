@@ -2,25 +2,26 @@
 // thermal lattice Boltzmann method (Xu & Li, arXiv 2308.16597).
 //
 // Per step, in launch order (cur = time level n, ring = particle slot of t_n):
-//   k_compact       one block per particle: clear the owner map and node
-//                   flags of two steps ago over the old window, then collect
-//                   the particle's links from the owner map of t_n into LDS in
+//   k_links         one wavefront per particle: clear the owner map and solid
+//                   bit of two steps ago over the old window; collect the
+//                   particle's links from the owner map of t_n into LDS in
 //                   the fixed slot order of Sec. 3 (one slot per lattice line
-//                   and direction), wave ballot + LDS prefix scan, one global
-//                   atomic per block to reserve a contiguous segment.
-//   k_link_pass     one wavefront per particle: q, wall velocity, Bouzidi
-//                   bounce-back (Eqs. (9)-(10)) and the thermal wall
-//                   (Eqs. (11)-(12)) written into the solid slots of the
-//                   post-collision state, momentum exchange (Eqs. (13)-(14))
-//                   reduced in FP64 in a fixed order.
+//                   and direction), wave ballot + prefix count, one global
+//                   atomic per block to reserve contiguous segments; then the
+//                   link pass: q, wall velocity, Bouzidi bounce-back
+//                   (Eqs. (9)-(10)) and the thermal wall (Eqs. (11)-(12))
+//                   written into the solid slots of the post-collision state,
+//                   momentum exchange (Eqs. (13)-(14)) reduced in FP64 in a
+//                   fixed order.
 //   k_particles     one wavefront per particle: repulsion (Eq. (15)) summed in
-//                   ascending partner order, net weight, Newton-Euler update.
-//   k_mask_mark     one block per particle: owner map of t_n+1 by atomic min.
-//   k_refill        one block per particle: node flags of (t_n, t_n+1) and
-//                   refilling + collision of newborn nodes (Sec. 2.5).
+//                   ascending partner order over a cell grid, net weight,
+//                   Newton-Euler update.
+//   k_mask_mark     one wavefront per particle: owner map and solid bit of
+//                   t_n+1 by atomic min; newborn-node candidates.
 //   k_stream_collide  one thread per node: fused pull-stream + D2Q9/D2Q5 MRT
-//                   collision with buoyancy (Sec. 2.1) of every node fluid at
-//                   both time levels.
+//                   collision with buoyancy (Sec. 2.1) of the whole lattice.
+//   k_refill        one wavefront per particle: refilling + collision of the
+//                   newborn nodes (Sec. 2.5), over the lattice kernel's output.
 // Built with -ffp-contract=off: the solid test and link fractions must round
 // exactly as the CPU oracle rounds them.
 #include <hip/hip_runtime.h>
@@ -30,7 +31,6 @@
 namespace ptlbm {
 
 constexpr int LAT_BLOCK = 256;
-constexpr int PBLOCK = 256;
 constexpr double kPi = 3.14159265358979323846;
 constexpr int OUTSIDE = -2;
 
@@ -45,24 +45,34 @@ template <int MODE> __host__ __device__ Pops<ST<MODE>> pops_of(void* const (&a)[
 
 // ------------------------------------------------------ lattice kernels ----
 
+// Fused pull-stream + collide of every node of the lattice, one thread per
+// node of the pitched layout (flat 1-D grid, rows padded to the pitch).
+// Every node is written, so each wavefront stores whole cache lines: nodes
+// that are solid at t_n+1 receive values nobody reads (their slots facing the
+// fluid are rewritten by the next link pass), and newborn nodes are
+// overwritten by the refill kernel that runs after this one.  The stores are
+// non-temporal: B is not read again before the next step.  Only nodes fluid
+// at both time levels (flag 0) are checked for non-finite values.
 template <int MODE>
 __global__ __launch_bounds__(LAT_BLOCK) void k_stream_collide(Pops<ST<MODE>> A, Pops<ST<MODE>> B,
                                                               const uint8_t* __restrict__ flag, LP lp,
                                                               unsigned* status) {
     using S = Store<MODE>;
     using R = typename S::R;
-    const int x = blockIdx.x * LAT_BLOCK + threadIdx.x;
-    const int y = blockIdx.y;
-    if (x >= lp.nx) return;
+    const size_t n0 = (size_t)blockIdx.x * LAT_BLOCK + threadIdx.x;
+    const int y = (int)(n0 / (unsigned)lp.pitch);
+    const int x = (int)(n0 - (size_t)y * lp.pitch);
+    if (x >= lp.nx || y >= lp.ny) return;
     const size_t k = (size_t)y * lp.pitch + x;
-    if (flag[k] != 0) return;
+    const uint8_t fl = flag[k];
     R s[9], t[5];
     pull_node<S>(A, lp, x, y, s, t);
     const CC<R> c(lp);
     R rho, ux, uy, T;
     collide<R>(c, s, t, rho, ux, uy, T);
-    if (!(isfinite(rho) && isfinite(T) && isfinite(ux) && isfinite(uy))) atomicOr(status, ST_NONFINITE);
-    store_node<S>(B, lp, k, s, t);
+    if (fl == 0 && !(isfinite(rho) && isfinite(T) && isfinite(ux) && isfinite(uy)))
+        atomicOr(status, ST_NONFINITE);
+    store_node<S, true>(B, lp, k, s, t);
 }
 
 // Equilibrium of the given macroscopic fields (host layout j*nx + i; NULL
@@ -143,189 +153,283 @@ __global__ __launch_bounds__(LAT_BLOCK) void k_macros(Pops<ST<MODE>> A, const in
 }
 
 // ----------------------------------------------------- particle kernels ----
+// Every particle kernel runs one wavefront per particle (PPB particles per
+// block) so that a particle's work (its window, links, neighbours, newborn
+// nodes) stays inside one wavefront and needs no block-wide barrier.
 
 __device__ __forceinline__ bool in_rows(int y, const LP& lp) { return y >= 0 && y < lp.ny; }
 
-// One slot of the fixed link mapping (Sec. 3): slot -> (direction, lattice
-// line through the window); walks the line and returns the link of that
-// line, if any (at most one per line and direction).  Window of nxw x nyw
-// nodes, values in LDS: -1 fluid, particle index, or OUTSIDE.
-//   directions 1, 3: the nyw rows;  2, 4: the nxw columns;
-//   5, 7 (lines a - b = c) and 6, 8 (lines a + b = c): nxw + nyw - 3 lines
-//   each (the two single-node corner lines cannot hold a link).
-__device__ __forceinline__ bool find_link(const int* __restrict__ win, int nxw, int nyw, int p, int s,
-                                          int& a_out, int& b_out, int& d_out) {
-    int d, l;
-    const int nd = nxw + nyw - 3;
-    if (s < nyw) { d = 1; l = s; }
-    else if (s < nyw + nxw) { d = 2; l = s - nyw; }
-    else if (s < 2 * nyw + nxw) { d = 3; l = s - nyw - nxw; }
-    else if (s < 2 * (nyw + nxw)) { d = 4; l = s - 2 * nyw - nxw; }
-    else {
-        const int r = s - 2 * (nyw + nxw);
-        d = 5 + r / nd;
-        l = r % nd;
-    }
-    const int ex = EXd(d), ey = EYd(d);
-    int a, b, da, db, len;
-    if (ey == 0) { a = 0; b = l; da = 1; db = 0; len = nxw; }          // row b
-    else if (ex == 0) { a = l; b = 0; da = 0; db = 1; len = nyw; }     // column a
-    else if (ex == ey) {                                              // a - b = c
-        const int c = l - (nyw - 2);
-        a = c > 0 ? c : 0;
-        b = a - c;
-        da = 1; db = 1;
-        len = min(nxw - a, nyw - b);
-    } else {                                                          // a + b = c
-        const int c = l + 1;
-        b = c < nyw - 1 ? c : nyw - 1;
-        a = c - b;
-        da = 1; db = -1;
-        len = min(nxw - a, b + 1);
-    }
-    for (int m = 0; m < len; ++m, a += da, b += db) {
-        const int ta = a + ex, tb = b + ey;
-        if (ta < 0 || ta >= nxw || tb < 0 || tb >= nyw) continue;
-        if (win[b * nxw + a] == -1 && win[tb * nxw + ta] == p) {
-            a_out = a;
-            b_out = b;
-            d_out = d;
-            return true;
-        }
-    }
-    return false;
+// Flag bytes are updated with 32-bit atomics on their word (no value is
+// returned, so the update does not stall the issuing wavefront).
+__device__ __forceinline__ void flag_clear_bit(uint8_t* flag, size_t k, unsigned bit) {
+    atomicAnd((unsigned*)(flag + (k & ~(size_t)3)), ~(bit << (8u * (unsigned)(k & 3))));
+}
+__device__ __forceinline__ void flag_set_bit(uint8_t* flag, size_t k, unsigned bit) {
+    atomicOr((unsigned*)(flag + (k & ~(size_t)3)), bit << (8u * (unsigned)(k & 3)));
 }
 
-__global__ __launch_bounds__(PBLOCK) void k_compact(const int32_t* __restrict__ Ocur, int32_t* Onext,
-                                                    uint8_t* flag, const PState* __restrict__ Pc,
-                                                    const PState* __restrict__ Po, uint2* links, int2* seg,
-                                                    unsigned* counter, unsigned* status, LP lp) {
-    extern __shared__ uint2 smem_u2[];
-    __shared__ int wave_cnt[PBLOCK / 64];
-    __shared__ unsigned seg_start, seg_count;
-    const int p = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+// Orders the LDS accesses of the lanes of one wavefront.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The fixed link mapping of Sec. 3: a particle's window of nxw x nyw nodes
+// (x from INT(x_c - r) - 1 to INT(x_c + r) + 1, likewise y) is crossed by
+// lattice lines; every (direction, line) pair owns one slot, and each slot
+// holds at most one link (a line enters a disk once):
+//   directions 1, 3: the nyw rows b;  2, 4: the nxw columns a;
+//   5, 7: the lines a - b = c;  6, 8: the lines a + b = c, nxw + nyw - 3 each
+//   (the two single-node corner lines cannot hold a link).
+// 6 (nxw + nyw) - 12 slots, 12 N - 12 for a square window of edge N.
+__device__ __forceinline__ int link_slot(int d, int a, int b, int nxw, int nyw) {
+    const int nd = nxw + nyw - 3;
+    switch (d) {
+        case 1: return b;
+        case 2: return nyw + a;
+        case 3: return nyw + nxw + b;
+        case 4: return 2 * nyw + nxw + a;
+        case 5: return 2 * (nyw + nxw) + (a - b + nyw - 2);
+        case 6: return 2 * (nyw + nxw) + nd + (a + b - 1);
+        case 7: return 2 * (nyw + nxw) + 2 * nd + (a - b + nyw - 2);
+        default: return 2 * (nyw + nxw) + 3 * nd + (a + b - 1);
+    }
+}
+
+// LDS of one wavefront of k_links: the owner map over the window widened by
+// WMARGIN nodes on every side (the bounce-back stencil reaches two nodes
+// behind a link node), the slot array, then the compacted link list.
+constexpr int WMARGIN = 2;
+__host__ __device__ inline size_t links_win_ints(int nwin) {
+    return (size_t)(nwin + 2 * WMARGIN) * (nwin + 2 * WMARGIN);
+}
+__host__ __device__ inline size_t links_slots(int nwin) { return (size_t)(12 * nwin - 12); }
+__host__ __device__ inline size_t links_wave_lds(int nwin) {
+    return ((links_win_ints(nwin) + links_slots(nwin)) * 4 + 7) / 8 * 8 + links_slots(nwin) * sizeof(uint2);
+}
+
+// One link of the link pass: everything gathered before any arithmetic.
+template <int MODE> struct LinkIn {
+    bool valid, have1, have2;
+    int i, ib, ex, ey;
+    size_t kb;
+    double q, rx, ry, uwx, uwy;
+    double fi, fi1, fi2, fib, fib1, gi, gi1, gib;
+};
+
+template <int MODE>
+__device__ __forceinline__ void link_gather(const Pops<ST<MODE>>& A, uint2 L, const PState& P, const Win& wn,
+                                            const int* win, int ew, const LP& lp, LinkIn<MODE>& o) {
+    using S = Store<MODE>;
+    const int nx = lp.nx, pitch = lp.pitch;
+    const int x = (int)(L.x & 0xffffu), y = (int)(L.x >> 16), i = (int)(L.y & 15u);
+    const int ex = EXd(i), ey = EYd(i);
+    o.i = i;
+    o.ib = OPPd(i);
+    o.ex = ex;
+    o.ey = ey;
+    const int x1 = wrap_x(x - ex, nx), y1 = y - ey;
+    const int x2 = wrap_x(x - 2 * ex, nx), y2 = y - 2 * ey;
+    const bool in1 = in_rows(y1, lp), in2 = in_rows(y2, lp);
+    const size_t k = (size_t)y * pitch + x;
+    const size_t k1 = in1 ? (size_t)y1 * pitch + x1 : k;
+    const size_t k2 = in2 ? (size_t)y2 * pitch + x2 : k;
+    o.fi = (double)S::ld(A.f[i] + k);
+    o.fib = (double)S::ld(A.f[o.ib] + k);
+    o.fi1 = (double)S::ld(A.f[i] + k1);
+    o.fib1 = (double)S::ld(A.f[o.ib] + k1);
+    o.fi2 = (double)S::ld(A.f[i] + k2);
+    if (i <= 4) {
+        o.gi = (double)S::ld(A.g[i] + k);
+        o.gib = (double)S::ld(A.g[o.ib] + k);
+        o.gi1 = (double)S::ld(A.g[i] + k1);
+    }
+    o.kb = (size_t)(y + ey) * pitch + wrap_x(x + ex, nx);
+    // fluid tests of x_f - e_i and x_f - 2 e_i from the widened window
+    const int a0 = wrap_x(x - wn.x0, nx) + WMARGIN, b0 = y - wn.y0 + WMARGIN;
+    o.have1 = in1 && win[(b0 - ey) * ew + a0 - ex] == -1;
+    o.have2 = o.have1 && in2 && win[(b0 - 2 * ey) * ew + a0 - 2 * ex] == -1;
+    const double dx = min_image_x((double)x - P.x, nx);
+    const double dy = (double)y - P.y;
+    o.q = link_q(dx, dy, P.r, i);
+    o.rx = dx + o.q * ex;   // x_w - X_c
+    o.ry = dy + o.q * ey;
+    o.uwx = P.ux - P.om * o.ry;
+    o.uwy = P.uy + P.om * o.rx;
+}
+
+template <int MODE>
+__device__ __forceinline__ void link_apply(const Pops<ST<MODE>>& A, const LinkIn<MODE>& o, const LP& lp,
+                                           double shf, double& fx, double& fy, double& tz) {
+    using S = Store<MODE>;
+    const double w9i = o.i <= 4 ? 1.0 / 9.0 : 1.0 / 36.0;
+    const double wall = 6.0 * w9i * lp.rho0 * (-(o.ex * o.uwx) - o.ey * o.uwy);
+    const double fnew = bouzidi(o.q, o.fi, o.fi1, o.fi2, o.fib, o.fib1, o.have1, o.have2, wall);
+    S::st(A.f[o.ib] + o.kb, (typename S::R)fnew);
+    if (o.i <= 4) {
+        const double gnew = thermal_link(o.q, o.gi, o.gi1, o.gib, o.have1, lp.w5_k, lp.particle_T - lp.T_sh);
+        S::st(A.g[o.ib] + o.kb, (typename S::R)gnew);
+    }
+    // Eq. (13) on full populations (stored value + rest part w rho0)
+    const double Fi = o.fi + w9i * shf, Fb = (double)(typename S::R)fnew + w9i * shf;
+    const double dFx = Fi * (o.ex - o.uwx) - Fb * (-o.ex - o.uwx);
+    const double dFy = Fi * (o.ey - o.uwy) - Fb * (-o.ey - o.uwy);
+    fx += dFx;
+    fy += dFy;
+    tz += o.rx * dFy - o.ry * dFx;   // Eq. (14), z component
+}
+
+// Link collection and link pass, one wavefront per particle:
+//  (a) clear the owner map / solid bit left by t_n-1 over the window of
+//      X^{n-1} (that buffer and bit will describe t_n+1);
+//  (b) load the particle's widened window of the owner map of t_n into LDS;
+//  (c) every fluid node of the window tests its 8 neighbours in parallel; a
+//      neighbour owned by this particle is a link, written into its fixed
+//      slot; the slots are then compacted in slot order (ballot + prefix
+//      count within the wavefront);
+//  (d) one global atomic per block reserves the block's contiguous range of
+//      the link array; each particle's segment is contiguous, in slot order;
+//  (e) link pass (if do_pass): for every link, q, u_w, Bouzidi and thermal
+//      bounce-back into the solid slots of the post-collision state A, and the
+//      momentum exchange summed in FP64 in a fixed order (lane-strided, then
+//      butterfly) into Fh[p].
+template <int MODE>
+__global__ __launch_bounds__(256) void k_links(Pops<ST<MODE>> A, const int32_t* __restrict__ Ocur,
+                                               int32_t* Onext, uint8_t* flag, unsigned clr_bit,
+                                               const PState* __restrict__ Pc, const PState* __restrict__ Po,
+                                               uint2* links, int2* seg, unsigned* counter, double* Fh,
+                                               unsigned* status, LP lp, int ppb, int do_pass) {
+    using S = Store<MODE>;
+    extern __shared__ uint2 smem[];
+    __shared__ unsigned wave_tot[4];
+    __shared__ unsigned block_base;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int p = blockIdx.x * ppb + w;
+    const bool have_p = w < ppb && p < lp.np;
     const int nx = lp.nx, pitch = lp.pitch;
 
-    // Owner map and flags left by t_n-1 (two time levels ago) in the buffer
-    // that will hold t_n+1.
-    const PState po = Po[p];
-    if (particle_ok(po, lp)) {
-        const Win w = window_of(po);
-        if (w.nxw <= lp.nwin && w.nyw <= lp.nwin) {
-            for (int idx = tid; idx < w.nxw * w.nyw; idx += PBLOCK) {
-                const int yy = w.y0 + idx / w.nxw;
+    if (have_p) {
+        const PState po = Po[p];
+        const Win wo = window_of(po);
+        if (particle_ok(po, lp) && wo.nxw <= lp.nwin && wo.nyw <= lp.nwin) {
+            for (int idx = lane; idx < wo.nxw * wo.nyw; idx += 64) {
+                const int b = idx / wo.nxw, a = idx - b * wo.nxw;
+                const int yy = wo.y0 + b;
                 if (!in_rows(yy, lp)) continue;
-                const size_t k = (size_t)yy * pitch + wrap_x(w.x0 + idx % w.nxw, nx);
+                const size_t k = (size_t)yy * pitch + wrap_x(wo.x0 + a, nx);
                 Onext[k] = -1;
-                flag[k] = 0;
+                flag_clear_bit(flag, k, clr_bit);
             }
         }
     }
 
-    const PState P = Pc[p];
-    const Win w = window_of(P);
-    if (!particle_ok(P, lp) || w.nxw > lp.nwin || w.nyw > lp.nwin) {
-        if (tid == 0) {
-            seg[p] = make_int2(0, 0);
-            atomicOr(status, ST_BAD_PARTICLE);
+    const size_t wl = links_wave_lds(lp.nwin) / sizeof(uint2);
+    int* win = (int*)(smem + (size_t)w * wl);
+    unsigned* slot = (unsigned*)(win + links_win_ints(lp.nwin));
+    uint2* lk = smem + (size_t)w * wl + ((links_win_ints(lp.nwin) + links_slots(lp.nwin)) * 4 + 7) / 8;
+    PState P{};
+    Win wn{};
+    bool ok = false;
+    if (have_p) {
+        P = Pc[p];
+        wn = window_of(P);
+        ok = particle_ok(P, lp) && wn.nxw <= lp.nwin && wn.nyw <= lp.nwin;
+        if (!ok && lane == 0) atomicOr(status, ST_BAD_PARTICLE);
+    }
+    const int ew = wn.nxw + 2 * WMARGIN, eh = wn.nyw + 2 * WMARGIN;   // widened window
+    unsigned count = 0;
+    if (ok) {
+        const int nslots = 6 * (wn.nxw + wn.nyw) - 12;
+        for (int base = 0; base < ew * eh; base += 8 * 64) {   // 8 loads in flight per lane
+            int v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int idx = base + u * 64 + lane;
+                const int b = idx / ew, a = idx - b * ew;
+                const int yy = wn.y0 - WMARGIN + b;
+                v[u] = (idx < ew * eh && in_rows(yy, lp))
+                           ? Ocur[(size_t)yy * pitch + wrap_x(wn.x0 - WMARGIN + a, nx)] : OUTSIDE;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int idx = base + u * 64 + lane;
+                if (idx < ew * eh) win[idx] = v[u];
+            }
         }
-        return;
+        for (int s = lane; s < nslots; s += 64) slot[s] = 0xffffffffu;
+        wave_lds_sync();
+        for (int idx = lane; idx < wn.nxw * wn.nyw; idx += 64) {
+            const int b = idx / wn.nxw, a = idx - b * wn.nxw;
+            if (win[(b + WMARGIN) * ew + a + WMARGIN] != -1) continue;
+            const unsigned code = (unsigned)wrap_x(wn.x0 + a, nx) | ((unsigned)(wn.y0 + b) << 16);
+#pragma unroll
+            for (int d = 1; d < 9; ++d) {
+                const int ta = a + EXd(d), tb = b + EYd(d);
+                if (ta < 0 || ta >= wn.nxw || tb < 0 || tb >= wn.nyw) continue;
+                if (win[(tb + WMARGIN) * ew + ta + WMARGIN] == p) slot[link_slot(d, a, b, wn.nxw, wn.nyw)] = code;
+            }
+        }
+        wave_lds_sync();
+        for (int s0 = 0; s0 < nslots; s0 += 64) {
+            const int s = s0 + lane;
+            const unsigned code = s < nslots ? slot[s] : 0xffffffffu;
+            const bool v = code != 0xffffffffu;
+            const unsigned long long m = __ballot(v);
+            if (v) {
+                // the slot tells the direction back: first slot of each direction block
+                int d;
+                const int nd = wn.nxw + wn.nyw - 3, base = 2 * (wn.nyw + wn.nxw);
+                if (s < wn.nyw) d = 1;
+                else if (s < wn.nyw + wn.nxw) d = 2;
+                else if (s < 2 * wn.nyw + wn.nxw) d = 3;
+                else if (s < base) d = 4;
+                else d = 5 + (s - base) / nd;
+                lk[count + __popcll(m & ((1ull << lane) - 1ull))] = make_uint2(code, (unsigned)d | ((unsigned)p << 4));
+            }
+            count += (unsigned)__popcll(m);
+        }
+        wave_lds_sync();
     }
-    int* win = (int*)smem_u2;
-    uint2* lk = smem_u2 + (lp.nwin * lp.nwin + 1) / 2;
-    for (int idx = tid; idx < w.nxw * w.nyw; idx += PBLOCK) {
-        const int yy = w.y0 + idx / w.nxw;
-        win[idx] = in_rows(yy, lp) ? Ocur[(size_t)yy * pitch + wrap_x(w.x0 + idx % w.nxw, nx)] : OUTSIDE;
-    }
+    if (lane == 0) wave_tot[w] = count;
     __syncthreads();
-
-    const int nslots = 2 * (w.nxw + w.nyw) + 4 * (w.nxw + w.nyw - 3);
-    int base = 0;
-    for (int s0 = 0; s0 < nslots; s0 += PBLOCK) {
-        const int s = s0 + tid;
-        int a = 0, b = 0, d = 0;
-        const bool valid = s < nslots && find_link(win, w.nxw, w.nyw, p, s, a, b, d);
-        const unsigned long long m = __ballot(valid);
-        const int pre = __popcll(m & ((1ull << lane) - 1ull));
-        if (lane == 0) wave_cnt[wv] = __popcll(m);
-        __syncthreads();
-        int off = base, tot = 0;
-        for (int i = 0; i < PBLOCK / 64; ++i) {
-            off += i < wv ? wave_cnt[i] : 0;
-            tot += wave_cnt[i];
-        }
-        if (valid) {
-            const unsigned xx = (unsigned)wrap_x(w.x0 + a, nx), yy = (unsigned)(w.y0 + b);
-            lk[off + pre] = make_uint2(xx | (yy << 16), (unsigned)d | ((unsigned)p << 4));
-        }
-        base += tot;
-        __syncthreads();
-    }
-    if (tid == 0) {
-        unsigned start = atomicAdd(counter, (unsigned)base);
-        unsigned cnt = (unsigned)base;
-        if ((unsigned long long)start + cnt > (unsigned long long)lp.link_cap) {
+    if (threadIdx.x == 0) {
+        unsigned tot = 0;
+        for (int i = 0; i < ppb; ++i) tot += wave_tot[i];
+        unsigned base = tot ? atomicAdd(counter, tot) : 0u;
+        if ((unsigned long long)base + tot > (unsigned long long)lp.link_cap) {
             atomicOr(status, ST_LINK_OVERFLOW);
-            cnt = 0;
+            base = 0xffffffffu;
         }
-        seg_start = start;
-        seg_count = cnt;
-        seg[p] = make_int2((int)start, (int)cnt);
+        block_base = base;
     }
     __syncthreads();
-    for (unsigned i = tid; i < seg_count; i += PBLOCK) links[seg_start + i] = lk[i];
-}
+    if (!have_p) return;
+    unsigned start = block_base;
+    if (start == 0xffffffffu) {
+        count = 0;
+        start = 0;
+    }
+    for (int i = 0; i < w; ++i) start += wave_tot[i];
+    for (unsigned i = lane; i < count; i += 64) links[start + i] = lk[i];
+    if (lane == 0) seg[p] = make_int2((int)start, (int)count);
+    if (!do_pass) return;
 
-template <int MODE>
-__global__ __launch_bounds__(256) void k_link_pass(Pops<ST<MODE>> A, const int32_t* __restrict__ Ocur,
-                                                   const PState* __restrict__ Pc, const uint2* __restrict__ links,
-                                                   const int2* __restrict__ seg, double* Fh, LP lp) {
-    using S = Store<MODE>;
-    const int lane = threadIdx.x & 63;
-    const int p = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (p >= lp.np) return;
-    const PState P = Pc[p];
-    const int2 sg = seg[p];
-    const int nx = lp.nx, pitch = lp.pitch;
     const double shf = S::shifted ? lp.rho0 : 0.0;  // rest density carried by the stored f
     double fx = 0.0, fy = 0.0, tz = 0.0;
-    for (int l = lane; l < sg.y; l += 64) {
-        const uint2 L = links[sg.x + l];
-        const int x = (int)(L.x & 0xffffu), y = (int)(L.x >> 16), i = (int)(L.y & 15u);
-        const int ib = OPPd(i), ex = EXd(i), ey = EYd(i);
-        const double dx = min_image_x((double)x - P.x, nx);
-        const double dy = (double)y - P.y;
-        const double q = link_q(dx, dy, P.r, i);
-        const double rx = dx + q * ex, ry = dy + q * ey;   // x_w - X_c
-        const double uwx = P.ux - P.om * ry, uwy = P.uy + P.om * rx;
-        const int x1 = wrap_x(x - ex, nx), y1 = y - ey;
-        const int x2 = wrap_x(x - 2 * ex, nx), y2 = y - 2 * ey;
-        const bool have1 = in_rows(y1, lp) && Ocur[(size_t)y1 * pitch + x1] == -1;
-        const bool have2 = have1 && in_rows(y2, lp) && Ocur[(size_t)y2 * pitch + x2] == -1;
-        const size_t k = (size_t)y * pitch + x;
-        const size_t k1 = have1 ? (size_t)y1 * pitch + x1 : k;
-        const size_t k2 = have2 ? (size_t)y2 * pitch + x2 : k;
-        const double w = i <= 4 ? 1.0 / 9.0 : 1.0 / 36.0;
-        const double fi = (double)S::ld(A.f[i] + k), fib = (double)S::ld(A.f[ib] + k);
-        const double fi1 = (double)S::ld(A.f[i] + k1), fib1 = (double)S::ld(A.f[ib] + k1);
-        const double fi2 = (double)S::ld(A.f[i] + k2);
-        const double wall = 6.0 * w * lp.rho0 * (-(ex * uwx) - ey * uwy);
-        const double fnew = bouzidi(q, fi, fi1, fi2, fib, fib1, have1, have2, wall);
-        const size_t kb = (size_t)(y + ey) * pitch + wrap_x(x + ex, nx);
-        S::st(A.f[ib] + kb, (typename S::R)fnew);
-        if (i <= 4) {
-            const double gi = (double)S::ld(A.g[i] + k), gib = (double)S::ld(A.g[ib] + k);
-            const double gi1 = (double)S::ld(A.g[i] + k1);
-            const double gnew = thermal_link(q, gi, gi1, gib, have1, lp.w5_k, lp.particle_T - lp.T_sh);
-            S::st(A.g[ib] + kb, (typename S::R)gnew);
+    // Two links per lane and iteration: all gathers of both are issued before
+    // either is used.
+    for (unsigned l0 = lane; l0 < count; l0 += 128) {
+        LinkIn<MODE> in[2];
+        const unsigned ls[2] = {l0, l0 + 64};
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            in[u].valid = ls[u] < count;
+            if (in[u].valid) link_gather<MODE>(A, lk[ls[u]], P, wn, win, ew, lp, in[u]);
         }
-        // Eq. (13) on full populations (stored value + rest part w rho0)
-        const double Fi = fi + w * shf, Fb = (double)(typename S::R)fnew + w * shf;
-        const double dFx = Fi * (ex - uwx) - Fb * (-ex - uwx);
-        const double dFy = Fi * (ey - uwy) - Fb * (-ey - uwy);
-        fx += dFx;
-        fy += dFy;
-        tz += rx * dFy - ry * dFx;   // Eq. (14), z component
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+            if (in[u].valid) link_apply<MODE>(A, in[u], lp, shf, fx, fy, tz);
     }
     for (int off = 32; off > 0; off >>= 1) {
         fx += __shfl_xor(fx, off);
@@ -354,35 +458,94 @@ __device__ __forceinline__ void repulsion_pair(const LP& lp, double xp, double y
     fy = mag * (dy / dist);
 }
 
-__global__ __launch_bounds__(64) void k_particles(const PState* __restrict__ Pc, PState* Pn,
-                                                  const double* __restrict__ Fh, unsigned* counter,
+// Uniform cell grid for the neighbour search: cells at least 2 r_max + s
+// wide, BINCAP particles per cell.
+__device__ __forceinline__ int cell_of(const PState& P, const LP& lp) {
+    int cx = (int)(P.x / lp.nx * lp.ncx);
+    int cy = (int)floor((P.y + 0.5) / lp.ny * lp.ncy);
+    cx = min(max(cx, 0), lp.ncx - 1);
+    cy = min(max(cy, 0), lp.ncy - 1);
+    return cy * lp.ncx + cx;
+}
+
+__device__ __forceinline__ void bin_insert(const PState& P, int p, unsigned* bins, unsigned* cnt,
+                                           unsigned* status, const LP& lp) {
+    if (!particle_ok(P, lp)) return;
+    const int c = cell_of(P, lp);
+    const unsigned slot = atomicAdd(&cnt[c], 1u);
+    if (slot < (unsigned)BINCAP) bins[(size_t)c * BINCAP + slot] = (unsigned)p;
+    else atomicOr(status, ST_BIN_OVERFLOW);
+}
+
+__global__ __launch_bounds__(256) void k_bin_init(const PState* __restrict__ P, unsigned* bins, unsigned* cnt,
                                                   unsigned* status, LP lp) {
-    const int p = blockIdx.x, lane = threadIdx.x;
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < lp.np) bin_insert(P[p], p, bins, cnt, status, lp);
+}
+
+// Particle update, one wavefront per particle: neighbours from the cell grid
+// of t_n (lane = one slot of the 3 x 3 cells around the particle), repulsion
+// summed in ascending partner index (the same order as a plain loop over all
+// partners), walls, net weight, Newton-Euler; the new state goes into the
+// cell grid of t_n+1.
+__global__ __launch_bounds__(256) void k_particles(const PState* __restrict__ Pc, PState* Pn,
+                                                   const double* __restrict__ Fh,
+                                                   const unsigned* __restrict__ bins_cur,
+                                                   const unsigned* __restrict__ cnt_cur, unsigned* bins_next,
+                                                   unsigned* cnt_next, unsigned* counter, unsigned* status,
+                                                   LP lp) {
+    const int lane = threadIdx.x & 63;
+    const int p = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (p >= lp.np) return;
     const PState P = Pc[p];
-    const int np = lp.np;
     double Rx = 0.0, Ry = 0.0;
-    if (lp.repulsion) {
-        // partners in ascending index order (chunks of 64, then bits of the ballot)
-        for (int q0 = 0; q0 < np; q0 += 64) {
-            const int q = q0 + lane;
-            bool near = false;
-            if (q < np && q != p) {
-                const PState Q = Pc[q];
-                const double dx = min_image_x(P.x - Q.x, lp.nx);
-                const double dy = P.y - Q.y;
-                near = sqrt(dx * dx + dy * dy) - P.r - Q.r <= lp.rep_range;
-            }
-            unsigned long long m = __ballot(near);
-            while (m) {
-                const int b = __ffsll((long long)m) - 1;
-                m &= m - 1ull;
-                const PState Q = Pc[q0 + b];
-                double fx, fy;
-                repulsion_pair(lp, P.x, P.y, P.r, Q.x, Q.y, Q.r, fx, fy);
-                Rx += fx;
-                Ry += fy;
+    if (lp.repulsion && particle_ok(P, lp)) {
+        const int c0 = cell_of(P, lp);
+        const int cx = c0 % lp.ncx, cy = c0 / lp.ncx;
+        bool near = false;
+        int q = 0x7fffffff;
+        double fx = 0.0, fy = 0.0;
+        if (lane < 9 * BINCAP) {
+            const int j = lane / BINCAP, sl = lane - j * BINCAP;
+            const int dcx = j % 3 - 1, dcy = j / 3 - 1;
+            const int yy = cy + dcy;
+            bool cell_ok = yy >= 0 && yy < lp.ncy;
+            if (lp.ncx == 1 && dcx != 0) cell_ok = false;   // the 3 x-neighbours coincide
+            if (lp.ncx == 2 && dcx == 1) cell_ok = false;
+            if (cell_ok) {
+                int xx = cx + dcx;
+                xx = xx < 0 ? xx + lp.ncx : (xx >= lp.ncx ? xx - lp.ncx : xx);
+                const int c = yy * lp.ncx + xx;
+                if ((unsigned)sl < min(cnt_cur[c], (unsigned)BINCAP)) {
+                    const int qq = (int)bins_cur[(size_t)c * BINCAP + sl];
+                    if (qq != p) {
+                        const PState Q = Pc[qq];
+                        const double dx = min_image_x(P.x - Q.x, lp.nx);
+                        const double dy = P.y - Q.y;
+                        if (sqrt(dx * dx + dy * dy) - P.r - Q.r <= lp.rep_range) {
+                            near = true;
+                            q = qq;
+                            repulsion_pair(lp, P.x, P.y, P.r, Q.x, Q.y, Q.r, fx, fy);
+                        }
+                    }
+                }
             }
         }
+        const unsigned long long m = __ballot(near);
+        int rank = 0;
+        for (unsigned long long mm = m; mm; mm &= mm - 1ull) {
+            const int qb = __shfl(q, __ffsll((long long)mm) - 1);
+            rank += (qb < q) ? 1 : 0;
+        }
+        const int nn = __popcll(m);
+        for (int r = 0; r < nn; ++r) {
+            const unsigned long long sel = __ballot(near && rank == r);
+            const int b = __ffsll((long long)sel) - 1;
+            Rx += __shfl(fx, b);
+            Ry += __shfl(fy, b);
+        }
+    }
+    if (lp.repulsion) {
         double wy = 0.0;
         if (!lp.periodic_y) {
             const double C = kPi * (P.r * P.r) * (lp.rho_ratio - 1.0) * lp.rho0 * lp.gravity;
@@ -424,22 +587,85 @@ __global__ __launch_bounds__(64) void k_particles(const PState* __restrict__ Pc,
     const double ddx = min_image_x(N.x - P.x, lp.nx), ddy = N.y - P.y;
     if (!(ddx * ddx + ddy * ddy <= 0.25)) atomicOr(status, ST_OVERSPEED);
     Pn[p] = N;
+    bin_insert(N, p, bins_next, cnt_next, status, lp);
 }
 
-__global__ __launch_bounds__(PBLOCK) void k_mask_mark(int32_t* O, const PState* __restrict__ Pp, LP lp) {
-    const int p = blockIdx.x;
+// Owner map and solid bit of t_n+1, one wavefront per particle, over the
+// union of the particle's windows at t_n and t_n+1: a node inside the disk at
+// t_n+1 gets owner = the lowest index whose disk holds it (atomic min, exact
+// solid test); a node inside the disk at t_n but not at t_n+1 is a newborn
+// candidate (k_refill keeps it if this particle owned it at t_n and no
+// particle covers it at t_n+1).  Also clears the cell-grid counts read this
+// step.
+__global__ __launch_bounds__(256) void k_mask_mark(int32_t* O, uint8_t* flag, unsigned set_bit,
+                                                   const PState* __restrict__ Pp,
+                                                   const PState* __restrict__ Pprev, unsigned* cand,
+                                                   unsigned* ncand, unsigned* cnt_clear, unsigned* status,
+                                                   LP lp) {
+    if (cnt_clear)
+        for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < lp.ncells; c += gridDim.x * blockDim.x)
+            cnt_clear[c] = 0u;
+    const int lane = threadIdx.x & 63;
+    const int p = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (p >= lp.np) return;
     const PState P = Pp[p];
     if (!particle_ok(P, lp)) return;
-    const Win w = window_of(P);
+    Win w = window_of(P);
     if (w.nxw > lp.nwin || w.nyw > lp.nwin) return;
-    const double r2 = P.r * P.r;
-    for (int idx = threadIdx.x; idx < w.nxw * w.nyw; idx += PBLOCK) {
-        const int yy = w.y0 + idx / w.nxw;
-        if (!in_rows(yy, lp)) continue;
-        const int xx = wrap_x(w.x0 + idx % w.nxw, lp.nx);
-        const double dx = min_image_x((double)xx - P.x, lp.nx);
-        const double dy = (double)yy - P.y;
-        if (dx * dx + dy * dy <= r2) atomicMin((unsigned*)&O[(size_t)yy * lp.pitch + xx], (unsigned)p);
+    int xa = w.x0, xb = w.x0 + w.nxw, ya = w.y0, yb = w.y0 + w.nyw;
+    PState Q{};
+    const bool with_prev = Pprev != nullptr && particle_ok(Pprev[p], lp);
+    if (with_prev) {
+        Q = Pprev[p];
+        Win v = window_of(Q);
+        if (v.x0 - w.x0 > lp.nx / 2) v.x0 -= lp.nx;
+        else if (w.x0 - v.x0 > lp.nx / 2) v.x0 += lp.nx;
+        xa = min(xa, v.x0);
+        xb = max(xb, v.x0 + v.nxw);
+        ya = min(ya, v.y0);
+        yb = max(yb, v.y0 + v.nyw);
+    }
+    const int bw = xb - xa, bh = yb - ya;
+    if (bw > lp.nwin + 2 || bh > lp.nwin + 2) return;
+    const double r2 = P.r * P.r, q2 = Q.r * Q.r;
+    unsigned nc = 0;
+    const unsigned ccap = (unsigned)(4 * lp.nwin);
+    for (int base = 0; base < bw * bh; base += 64) {
+        const int idx = base + lane;
+        bool nb = false;
+        unsigned code = 0;
+        if (idx < bw * bh) {
+            const int b = idx / bw, a = idx - b * bw;
+            const int yy = ya + b;
+            if (in_rows(yy, lp)) {
+                const int xx = wrap_x(xa + a, lp.nx);
+                const double dx = min_image_x((double)xx - P.x, lp.nx);
+                const double dy = (double)yy - P.y;
+                const size_t k = (size_t)yy * lp.pitch + xx;
+                if (dx * dx + dy * dy <= r2) {
+                    atomicMin((unsigned*)&O[k], (unsigned)p);
+                    flag_set_bit(flag, k, set_bit);
+                } else if (with_prev) {
+                    const double qx = min_image_x((double)xx - Q.x, lp.nx);
+                    const double qy = (double)yy - Q.y;
+                    nb = qx * qx + qy * qy <= q2;
+                    code = (unsigned)xx | ((unsigned)yy << 16);
+                }
+            }
+        }
+        const unsigned long long m = __ballot(nb);
+        if (nb) {
+            const unsigned at = nc + (unsigned)__popcll(m & ((1ull << lane) - 1ull));
+            if (at < ccap) cand[(size_t)p * ccap + at] = code;
+        }
+        nc += (unsigned)__popcll(m);
+    }
+    if (lane == 0) {
+        if (nc > ccap) {
+            atomicOr(status, ST_CAND_OVERFLOW);
+            nc = ccap;
+        }
+        if (with_prev) ncand[p] = nc;
     }
 }
 
@@ -451,9 +677,10 @@ __global__ __launch_bounds__(PBLOCK) void k_mask_mark(int32_t* O, const PState* 
 // that u = u_w; g = g^eq(T_w, u_w) (Eq. (17)); then collided into B.
 template <int MODE>
 __device__ void refill_node(const Pops<ST<MODE>>& A, const Pops<ST<MODE>>& B, const int32_t* Ocur,
-                            const int32_t* Onext, const PState& P, int x, int y, const LP& lp) {
+                            const int32_t* Onext, const PState& P, int p, int x, int y, const LP& lp) {
     using S = Store<MODE>;
     using R = typename S::R;
+    const size_t k0 = (size_t)y * lp.pitch + x;
     const double dx = min_image_x((double)x - P.x, lp.nx);
     const double dy = (double)y - P.y;
     int c = 1;
@@ -465,18 +692,26 @@ __device__ void refill_node(const Pops<ST<MODE>>& A, const Pops<ST<MODE>>& B, co
             c = d;
         }
     }
+    // owner tests of the node itself and of the stencil, and the pulls of
+    // every in-lattice stencil node, all issued before any is used
+    int xs[3], ys[3];
+    bool fl[3], inr[3];
     R sm[3][9];
-    int K = 0;
-    for (int m = 1; m <= 3; ++m) {
-        const int ym = y + m * EYd(c);
-        if (!in_rows(ym, lp)) break;
-        const int xm = wrap_x(x + m * EXd(c), lp.nx);
-        const size_t km = (size_t)ym * lp.pitch + xm;
-        if (Ocur[km] != -1 || Onext[km] != -1) break;
-        R tt[5];
-        pull_node<S>(A, lp, xm, ym, sm[m - 1], tt);
-        K = m;
+    const bool mine = Ocur[k0] == p && Onext[k0] == -1;
+    for (int m = 0; m < 3; ++m) {
+        ys[m] = y + (m + 1) * EYd(c);
+        xs[m] = wrap_x(x + (m + 1) * EXd(c), lp.nx);
+        inr[m] = in_rows(ys[m], lp);
+        fl[m] = false;
+        if (inr[m]) {
+            const size_t km = (size_t)ys[m] * lp.pitch + xs[m];
+            fl[m] = Ocur[km] == -1 && Onext[km] == -1;
+            R tt[5];
+            pull_node<S>(A, lp, xs[m], ys[m], sm[m], tt);
+        }
     }
+    if (!mine) return;
+    const int K = !fl[0] ? 0 : (!fl[1] ? 1 : (!fl[2] ? 2 : 3));
     const double uwx = P.ux - P.om * dy, uwy = P.uy + P.om * dx;
     R s[9], t[5];
     if (K == 3) {
@@ -504,34 +739,28 @@ __device__ void refill_node(const Pops<ST<MODE>>& A, const Pops<ST<MODE>>& B, co
     const CC<R> cc(lp);
     R r_, u_, v_, T_;
     collide<R>(cc, s, t, r_, u_, v_, T_);
-    store_node<S>(B, lp, (size_t)y * lp.pitch + x, s, t);
+    store_node<S>(B, lp, k0, s, t);
 }
 
+// Refill of particle p's newborn nodes, one wavefront per particle and one
+// lane per candidate from k_mask_mark; a candidate is refilled if p owned it
+// at t_n and no particle covers it at t_n+1.
 template <int MODE>
-__global__ __launch_bounds__(PBLOCK) void k_refill(Pops<ST<MODE>> A, Pops<ST<MODE>> B,
-                                                   const int32_t* __restrict__ Ocur,
-                                                   const int32_t* __restrict__ Onext, uint8_t* flag,
-                                                   const PState* __restrict__ Pc,
-                                                   const PState* __restrict__ Pn, LP lp) {
-    const int p = blockIdx.x;
-    const PState P0 = Pc[p], P1 = Pn[p];
-    if (!particle_ok(P0, lp) || !particle_ok(P1, lp)) return;
-    const Win w0 = window_of(P0);
-    Win w1 = window_of(P1);
-    if (w1.x0 - w0.x0 > lp.nx / 2) w1.x0 -= lp.nx;
-    else if (w0.x0 - w1.x0 > lp.nx / 2) w1.x0 += lp.nx;
-    const int xa = min(w0.x0, w1.x0), xb = max(w0.x0 + w0.nxw, w1.x0 + w1.nxw);
-    const int ya = min(w0.y0, w1.y0), yb = max(w0.y0 + w0.nyw, w1.y0 + w1.nyw);
-    const int bw = xb - xa, bh = yb - ya;
-    if (bw > lp.nwin + 2 || bh > lp.nwin + 2) return;
-    for (int idx = threadIdx.x; idx < bw * bh; idx += PBLOCK) {
-        const int yy = ya + idx / bw;
-        if (!in_rows(yy, lp)) continue;
-        const int xx = wrap_x(xa + idx % bw, lp.nx);
-        const size_t k = (size_t)yy * lp.pitch + xx;
-        const int32_t on = Ocur[k], onx = Onext[k];
-        flag[k] = (uint8_t)((on >= 0 ? 2 : 0) | (onx >= 0 ? 1 : 0));
-        if (on == p && onx == -1) refill_node<MODE>(A, B, Ocur, Onext, P1, xx, yy, lp);
+__global__ __launch_bounds__(256) void k_refill(Pops<ST<MODE>> A, Pops<ST<MODE>> B,
+                                                const int32_t* __restrict__ Ocur,
+                                                const int32_t* __restrict__ Onext,
+                                                const PState* __restrict__ Pn, const unsigned* __restrict__ cand,
+                                                const unsigned* __restrict__ ncand, LP lp) {
+    const int lane = threadIdx.x & 63;
+    const int p = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (p >= lp.np) return;
+    const unsigned ccap = (unsigned)(4 * lp.nwin);
+    const unsigned n = min(ncand[p], ccap);
+    if (n == 0) return;
+    const PState P1 = Pn[p];
+    for (unsigned i = lane; i < n; i += 64) {
+        const unsigned code = cand[(size_t)p * ccap + i];
+        refill_node<MODE>(A, B, Ocur, Onext, P1, p, (int)(code & 0xffffu), (int)(code >> 16), lp);
     }
 }
 
@@ -553,6 +782,7 @@ __global__ void k_link_q(const PState* __restrict__ Pc, const uint2* __restrict_
 // -------------------------------------------------------------- launchers ----
 
 static dim3 lattice_grid(const LP& lp) { return dim3((lp.nx + LAT_BLOCK - 1) / LAT_BLOCK, lp.ny); }
+static unsigned wave_blocks(int np) { return (unsigned)((np + 3) / 4); }
 
 #define PTLBM_DISPATCH(mode, CALL)                                      \
     switch (mode) {                                                     \
@@ -565,7 +795,8 @@ static dim3 lattice_grid(const LP& lp) { return dim3((lp.nx + LAT_BLOCK - 1) / L
     }
 
 hipError_t launch_stream_collide(const DevState& d, int cur, hipStream_t st) {
-    PTLBM_DISPATCH(d.mode, (k_stream_collide<M><<<lattice_grid(d.lp), LAT_BLOCK, 0, st>>>(
+    const unsigned blocks = (unsigned)(((size_t)d.lp.pitch * d.lp.ny + LAT_BLOCK - 1) / LAT_BLOCK);
+    PTLBM_DISPATCH(d.mode, (k_stream_collide<M><<<blocks, LAT_BLOCK, 0, st>>>(
                                pops_of<M>(d.S[cur]), pops_of<M>(d.S[1 - cur]), d.flag, d.lp, d.status)));
     return hipGetLastError();
 }
@@ -595,43 +826,54 @@ hipError_t launch_macros(const DevState& d, int cur, void* out, hipStream_t st) 
     return hipGetLastError();
 }
 
-static size_t compact_smem(const LP& lp) {
-    const size_t win = ((size_t)lp.nwin * lp.nwin + 1) & ~(size_t)1;
-    return win * sizeof(int) + (size_t)(12 * lp.nwin - 12) * sizeof(uint2);
+int links_particles_per_block(int nwin) {
+    const size_t per = links_wave_lds(nwin);
+    int ppb = (int)(65536 / per);
+    return ppb < 1 ? 1 : (ppb > 4 ? 4 : ppb);
 }
 
-hipError_t launch_compact(const DevState& d, int cur, int ring, hipStream_t st) {
+hipError_t launch_links(const DevState& d, int cur, int ring, bool do_pass, hipStream_t st) {
     if (d.lp.np == 0) return hipSuccess;
-    k_compact<<<d.lp.np, PBLOCK, compact_smem(d.lp), st>>>(d.O[cur], d.O[1 - cur], d.flag, d.P[ring],
-                                                           d.P[ring_old(ring)], d.links, d.seg, d.counter,
-                                                           d.status, d.lp);
+    const int ppb = links_particles_per_block(d.lp.nwin);
+    const unsigned blocks = (unsigned)((d.lp.np + ppb - 1) / ppb);
+    const size_t lds = (size_t)ppb * links_wave_lds(d.lp.nwin);
+    const unsigned clr = 1u << (1 - cur);
+    PTLBM_DISPATCH(d.mode, (k_links<M><<<blocks, 64 * ppb, lds, st>>>(
+                               pops_of<M>(d.S[cur]), d.O[cur], d.O[1 - cur], d.flag, clr, d.P[ring],
+                               d.P[ring_old(ring)], d.links, d.seg, d.counter, d.Fh, d.status, d.lp, ppb,
+                               do_pass ? 1 : 0)));
     return hipGetLastError();
 }
 
-hipError_t launch_link_pass(const DevState& d, int cur, int ring, hipStream_t st) {
+hipError_t launch_particles(const DevState& d, int ring, int bin_parity, hipStream_t st) {
     if (d.lp.np == 0) return hipSuccess;
-    PTLBM_DISPATCH(d.mode, (k_link_pass<M><<<(d.lp.np + 3) / 4, 256, 0, st>>>(
-                               pops_of<M>(d.S[cur]), d.O[cur], d.P[ring], d.links, d.seg, d.Fh, d.lp)));
+    k_particles<<<wave_blocks(d.lp.np), 256, 0, st>>>(d.P[ring], d.P[ring_next(ring)], d.Fh,
+                                                       d.bins[bin_parity], d.bcnt[bin_parity],
+                                                       d.bins[1 - bin_parity], d.bcnt[1 - bin_parity],
+                                                       d.counter, d.status, d.lp);
     return hipGetLastError();
 }
 
-hipError_t launch_particles(const DevState& d, int ring, hipStream_t st) {
+hipError_t launch_bin_init(const DevState& d, const PState* P, int bin_parity, hipStream_t st) {
     if (d.lp.np == 0) return hipSuccess;
-    k_particles<<<d.lp.np, 64, 0, st>>>(d.P[ring], d.P[ring_next(ring)], d.Fh, d.counter, d.status, d.lp);
+    k_bin_init<<<(d.lp.np + 255) / 256, 256, 0, st>>>(P, d.bins[bin_parity], d.bcnt[bin_parity], d.status,
+                                                       d.lp);
     return hipGetLastError();
 }
 
-hipError_t launch_mask_mark(const DevState& d, int owner_idx, const PState* P, hipStream_t st) {
+hipError_t launch_mask_mark(const DevState& d, int owner_idx, const PState* P, const PState* Pprev,
+                            unsigned* cnt_clear, hipStream_t st) {
     if (d.lp.np == 0) return hipSuccess;
-    k_mask_mark<<<d.lp.np, PBLOCK, 0, st>>>(d.O[owner_idx], P, d.lp);
+    k_mask_mark<<<wave_blocks(d.lp.np), 256, 0, st>>>(d.O[owner_idx], d.flag, 1u << owner_idx, P, Pprev,
+                                                       d.cand, d.ncand, cnt_clear, d.status, d.lp);
     return hipGetLastError();
 }
 
 hipError_t launch_refill(const DevState& d, int cur, int ring, hipStream_t st) {
     if (d.lp.np == 0) return hipSuccess;
-    PTLBM_DISPATCH(d.mode, (k_refill<M><<<d.lp.np, PBLOCK, 0, st>>>(
-                               pops_of<M>(d.S[cur]), pops_of<M>(d.S[1 - cur]), d.O[cur], d.O[1 - cur], d.flag,
-                               d.P[ring], d.P[ring_next(ring)], d.lp)));
+    PTLBM_DISPATCH(d.mode, (k_refill<M><<<wave_blocks(d.lp.np), 256, 0, st>>>(
+                               pops_of<M>(d.S[cur]), pops_of<M>(d.S[1 - cur]), d.O[cur], d.O[1 - cur],
+                               d.P[ring_next(ring)], d.cand, d.ncand, d.lp)));
     return hipGetLastError();
 }
 

@@ -91,7 +91,7 @@ def test_small_workload_parity_100_and_200_steps():
         sim.step(n)
         orc.step(n)
         ef = compare_fields(sim.fields(), orc.fields(), u_floor=U_FF)
-        ep = compare_particles(sim.particles(), orc.particles())
+        ep = compare_particles(sim.particles(), orc.particles(), u_floor=U_FF)
         _say("small workload step", target, ef, ep)
         compare_links(sim.links(), orc.links(), q_abs=1e-12)
 
@@ -112,7 +112,7 @@ def test_fast_particles_refill_parity():
         sim.step(10)
         orc.step(10)
         compare_fields(sim.fields(), orc.fields(), u_floor=U_FF)
-        compare_particles(sim.particles(), orc.particles())
+        compare_particles(sim.particles(), orc.particles(), u_floor=U_FF)
     _say("fast particles ok at", orc.steps_done)
 
 
@@ -181,6 +181,6 @@ def test_paper_scale_parity_full_lattice():
     sim.step(2)
     orc.step(2)
     ef = compare_fields(sim.fields(), orc.fields(), u_floor=U_FF)
-    ep = compare_particles(sim.particles(), orc.particles())
+    ep = compare_particles(sim.particles(), orc.particles(), u_floor=U_FF)
     _say("paper scale after 2 steps", ef, ep)
     compare_links(sim.links(), orc.links(), q_abs=1e-12)
