@@ -13,8 +13,7 @@ Prints one JSON line.  Besides the throughput it carries:
   roofline     the fused stream-collide kernel (the dominant one), timed with
                HIP events on the library's stream; achieved = algorithmic
                bytes per launch (every node reads and writes its 9 + 5
-               populations and reads its 1-byte flag) / mean launch time,
-               against 8 TB/s.
+               populations) / mean launch time, against 8 TB/s.
   cpu_baseline the CPU oracle (single thread, FP64) on a bounded sample of
                the same workload, timed on this host.
 """
@@ -129,7 +128,7 @@ def main():
     owner = sim.fields()["owner"]
     n_fluid = int((owner < 0).sum())
     es = STORE_BYTES[args.storage]
-    alg_bytes = nx * ny * (28 * es + 1)
+    alg_bytes = nx * ny * 28 * es
     lat_ms = phases["lattice"]
     achieved = alg_bytes / (lat_ms * 1e-3) / 1e9
     traffic = measured_traffic(args.workload, args.storage)

@@ -112,12 +112,13 @@ typedef struct {
 
 /* Phases reported by lbm_time_phases, in launch order. */
 enum {
-    LBM_PHASE_LINKS = 0,     /* link collection, bounce-back, thermal wall, momentum exchange */
-    LBM_PHASE_PARTICLES = 1, /* repulsion, net weight, Newton-Euler */
-    LBM_PHASE_MASK = 2,      /* solid map at the new positions */
-    LBM_PHASE_LATTICE = 3,   /* fused stream + collide over the lattice */
-    LBM_PHASE_REFILL = 4,    /* refilling of newborn nodes */
-    LBM_NPHASES = 5
+    LBM_PHASE_COLLECT = 0,   /* link collection into the compacted index array */
+    LBM_PHASE_LINKS = 1,     /* bounce-back, thermal wall, momentum exchange per link */
+    LBM_PHASE_PARTICLES = 2, /* per-particle sums, repulsion, net weight, Newton-Euler */
+    LBM_PHASE_MASK = 3,      /* solid map at the new positions */
+    LBM_PHASE_LATTICE = 4,   /* fused stream + collide over the lattice */
+    LBM_PHASE_REFILL = 5,    /* refilling of newborn nodes */
+    LBM_NPHASES = 6
 };
 
 /* Library ABI version (LBM_ABI_VERSION). */

@@ -42,7 +42,7 @@ int window_cap(double max_diameter) { return (int)std::floor(max_diameter) + 4; 
 struct Layout {
     int pitch = 0;
     size_t npitched = 0, array_stride = 0, state_bytes = 0;
-    size_t off_S[2] = {0, 0}, off_O[2] = {0, 0}, off_flag = 0, off_P = 0, off_Fh = 0, off_seg = 0,
+    size_t off_S[2] = {0, 0}, off_O[2] = {0, 0}, off_contrib = 0, off_P = 0, off_Fh = 0, off_seg = 0,
            off_links = 0, off_lscratch = 0, off_counter = 0, off_status = 0, off_bins[2] = {0, 0},
            off_bcnt[2] = {0, 0}, off_cand = 0, off_ncand = 0, total = 0;
     int nwin = 0;
@@ -62,7 +62,6 @@ Layout make_layout(const lbm_params& p) {
     L.off_S[1] = off; off += L.state_bytes;
     L.off_O[0] = off; off = round_up(off + L.npitched * 4, kArrayAlign);
     L.off_O[1] = off; off = round_up(off + L.npitched * 4, kArrayAlign);
-    L.off_flag = off; off = round_up(off + L.npitched, kArrayAlign);
     const size_t cap = (size_t)(p.max_particles > 0 ? p.max_particles : 0);
     L.nwin = window_cap(p.max_diameter > 0 ? p.max_diameter : 2.0);
     L.link_cap = cap * (size_t)(12 * L.nwin - 12);
@@ -70,6 +69,7 @@ Layout make_layout(const lbm_params& p) {
     L.off_Fh = off; off = round_up(off + cap * 4 * sizeof(double), kAlign);
     L.off_seg = off; off = round_up(off + cap * sizeof(int2), kAlign);
     L.off_links = off; off = round_up(off + L.link_cap * sizeof(uint2), kAlign);
+    L.off_contrib = off; off = round_up(off + L.link_cap * 4 * sizeof(double), kAlign);
     L.off_lscratch = off; off = round_up(off + L.link_cap * (3 * sizeof(int32_t) + sizeof(double)), kAlign);
     L.off_counter = off; off = round_up(off + 64, kAlign);
     L.off_status = off; off = round_up(off + 64, kAlign);
@@ -253,7 +253,7 @@ int create_common(const lbm_params* p, void* dev_ptr, size_t bytes, void* stream
         for (int i = 0; i < 14; ++i) d.S[s][i] = h->base + L.off_S[s] + (size_t)i * L.array_stride;
     d.O[0] = (int32_t*)(h->base + L.off_O[0]);
     d.O[1] = (int32_t*)(h->base + L.off_O[1]);
-    d.flag = (uint8_t*)(h->base + L.off_flag);
+    d.contrib = (double4*)(h->base + L.off_contrib);
     const size_t cap = (size_t)(p->max_particles > 0 ? p->max_particles : 0);
     for (int r = 0; r < 3; ++r) d.P[r] = (PState*)(h->base + L.off_P) + r * cap;
     d.Fh = (double*)(h->base + L.off_Fh);
@@ -304,7 +304,9 @@ int enqueue_step(lbm_sim* h, hipEvent_t* ev) {
     };
     const int bp = h->bin_parity;
     mark();
-    HIPCHK(h, launch_links(d, c, r, true, st));
+    HIPCHK(h, launch_links(d, c, r, st));
+    mark();
+    HIPCHK(h, launch_link_pass(d, c, r, st));
     mark();
     HIPCHK(h, launch_particles(d, r, bp, st));
     mark();
@@ -484,7 +486,6 @@ int lbm_set_particles(lbm_handle h, int32_t n, const double* rows7) {
     const size_t nb = h->L.npitched;
     HIPCHK(h, hipMemsetAsync(d.O[0], 0xff, nb * 4, st));
     HIPCHK(h, hipMemsetAsync(d.O[1], 0xff, nb * 4, st));
-    HIPCHK(h, hipMemsetAsync(d.flag, 0, nb, st));
     HIPCHK(h, hipMemsetAsync(d.counter, 0, 64, st));
     HIPCHK(h, hipMemsetAsync(d.status, 0, 64, st));
     if (n > 0) {
@@ -610,7 +611,7 @@ int lbm_read_links(lbm_handle h, int32_t* node, int32_t* dir, int32_t* particle,
     unsigned saved[2];
     HIPCHK(h, hipMemcpyAsync(saved, d.counter, sizeof saved, hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipMemsetAsync(d.counter, 0, sizeof(unsigned), h->stream));
-    HIPCHK(h, launch_links(d, h->cur, h->ring, false, h->stream));
+    HIPCHK(h, launch_links(d, h->cur, h->ring, h->stream));
     unsigned nl = 0;
     HIPCHK(h, hipMemcpyAsync(&nl, d.counter, sizeof nl, hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));

@@ -2,22 +2,23 @@
 // thermal lattice Boltzmann method (Xu & Li, arXiv 2308.16597).
 //
 // Per step, in launch order (cur = time level n, ring = particle slot of t_n):
-//   k_links         one wavefront per particle: clear the owner map and solid
-//                   bit of two steps ago over the old window; collect the
+//   k_links         one wavefront per particle: clear the owner map of two
+//                   steps ago over the old window; collect the
 //                   particle's links from the owner map of t_n into LDS in
 //                   the fixed slot order of Sec. 3 (one slot per lattice line
 //                   and direction), wave ballot + prefix count, one global
-//                   atomic per block to reserve contiguous segments; then the
-//                   link pass: q, wall velocity, Bouzidi bounce-back
-//                   (Eqs. (9)-(10)) and the thermal wall (Eqs. (11)-(12))
-//                   written into the solid slots of the post-collision state,
-//                   momentum exchange (Eqs. (13)-(14)) reduced in FP64 in a
-//                   fixed order.
-//   k_particles     one wavefront per particle: repulsion (Eq. (15)) summed in
-//                   ascending partner order over a cell grid, net weight,
-//                   Newton-Euler update.
-//   k_mask_mark     one wavefront per particle: owner map and solid bit of
-//                   t_n+1 by atomic min; newborn-node candidates.
+//                   atomic per block to reserve contiguous segments.
+//   k_link_pass     one thread per link of the compacted array: q, wall
+//                   velocity, Bouzidi bounce-back (Eqs. (9)-(10)) and the
+//                   thermal wall (Eqs. (11)-(12)) written into the solid
+//                   slots of the post-collision state; the link's momentum
+//                   exchange (Eqs. (13)-(14)) in FP64.
+//   k_particles     one wavefront per particle: FP64 sum of its links'
+//                   momentum exchange in a fixed order, repulsion (Eq. (15))
+//                   summed in ascending partner order over a cell grid, net
+//                   weight, Newton-Euler update.
+//   k_mask_mark     one wavefront per particle: owner map of t_n+1 by atomic
+//                   min; newborn-node candidates.
 //   k_stream_collide  one thread per node: fused pull-stream + D2Q9/D2Q5 MRT
 //                   collision with buoyancy (Sec. 2.1) of the whole lattice.
 //   k_refill        one wavefront per particle: refilling + collision of the
@@ -51,11 +52,14 @@ template <int MODE> __host__ __device__ Pops<ST<MODE>> pops_of(void* const (&a)[
 // that are solid at t_n+1 receive values nobody reads (their slots facing the
 // fluid are rewritten by the next link pass), and newborn nodes are
 // overwritten by the refill kernel that runs after this one.  The stores are
-// non-temporal: B is not read again before the next step.  Only nodes fluid
-// at both time levels (flag 0) are checked for non-finite values.
+// non-temporal: B is not read again before the next step.  A non-finite
+// macroscopic value is an error only at a node fluid at both time levels;
+// the two owner maps are read only for a node whose value is non-finite, so
+// the check costs no traffic while the run is sound.
 template <int MODE>
 __global__ __launch_bounds__(LAT_BLOCK) void k_stream_collide(Pops<ST<MODE>> A, Pops<ST<MODE>> B,
-                                                              const uint8_t* __restrict__ flag, LP lp,
+                                                              const int32_t* __restrict__ O0,
+                                                              const int32_t* __restrict__ O1, LP lp,
                                                               unsigned* status) {
     using S = Store<MODE>;
     using R = typename S::R;
@@ -64,13 +68,12 @@ __global__ __launch_bounds__(LAT_BLOCK) void k_stream_collide(Pops<ST<MODE>> A, 
     const int x = (int)(n0 - (size_t)y * lp.pitch);
     if (x >= lp.nx || y >= lp.ny) return;
     const size_t k = (size_t)y * lp.pitch + x;
-    const uint8_t fl = flag[k];
     R s[9], t[5];
     pull_node<S>(A, lp, x, y, s, t);
     const CC<R> c(lp);
     R rho, ux, uy, T;
     collide<R>(c, s, t, rho, ux, uy, T);
-    if (fl == 0 && !(isfinite(rho) && isfinite(T) && isfinite(ux) && isfinite(uy)))
+    if (!(isfinite(rho) && isfinite(T) && isfinite(ux) && isfinite(uy)) && O0[k] == -1 && O1[k] == -1)
         atomicOr(status, ST_NONFINITE);
     store_node<S, true>(B, lp, k, s, t);
 }
@@ -153,20 +156,11 @@ __global__ __launch_bounds__(LAT_BLOCK) void k_macros(Pops<ST<MODE>> A, const in
 }
 
 // ----------------------------------------------------- particle kernels ----
-// Every particle kernel runs one wavefront per particle (PPB particles per
-// block) so that a particle's work (its window, links, neighbours, newborn
-// nodes) stays inside one wavefront and needs no block-wide barrier.
+// The per-particle kernels run one wavefront per particle (PPB particles per
+// block) so that a particle's window, slots, neighbours and newborn nodes
+// stay inside one wavefront and need no block-wide barrier.
 
 __device__ __forceinline__ bool in_rows(int y, const LP& lp) { return y >= 0 && y < lp.ny; }
-
-// Flag bytes are updated with 32-bit atomics on their word (no value is
-// returned, so the update does not stall the issuing wavefront).
-__device__ __forceinline__ void flag_clear_bit(uint8_t* flag, size_t k, unsigned bit) {
-    atomicAnd((unsigned*)(flag + (k & ~(size_t)3)), ~(bit << (8u * (unsigned)(k & 3))));
-}
-__device__ __forceinline__ void flag_set_bit(uint8_t* flag, size_t k, unsigned bit) {
-    atomicOr((unsigned*)(flag + (k & ~(size_t)3)), bit << (8u * (unsigned)(k & 3)));
-}
 
 // Orders the LDS accesses of the lanes of one wavefront.
 __device__ __forceinline__ void wave_lds_sync() {
@@ -196,111 +190,40 @@ __device__ __forceinline__ int link_slot(int d, int a, int b, int nxw, int nyw) 
         default: return 2 * (nyw + nxw) + 3 * nd + (a + b - 1);
     }
 }
-
-// LDS of one wavefront of k_links: the owner map over the window widened by
-// WMARGIN nodes on every side (the bounce-back stencil reaches two nodes
-// behind a link node), the slot array, then the compacted link list.
-constexpr int WMARGIN = 2;
-__host__ __device__ inline size_t links_win_ints(int nwin) {
-    return (size_t)(nwin + 2 * WMARGIN) * (nwin + 2 * WMARGIN);
+__device__ __forceinline__ int slot_direction(int s, int nxw, int nyw) {
+    const int nd = nxw + nyw - 3, base = 2 * (nyw + nxw);
+    if (s < nyw) return 1;
+    if (s < nyw + nxw) return 2;
+    if (s < 2 * nyw + nxw) return 3;
+    if (s < base) return 4;
+    return 5 + (s - base) / nd;
 }
+
+// LDS of one wavefront of k_links: the owner map over the window, the slot
+// array, then the compacted link list.
+__host__ __device__ inline size_t links_win_ints(int nwin) { return (size_t)nwin * nwin; }
 __host__ __device__ inline size_t links_slots(int nwin) { return (size_t)(12 * nwin - 12); }
+__host__ __device__ inline size_t links_list_offset(int nwin) {
+    return ((links_win_ints(nwin) + links_slots(nwin)) * 4 + 7) / 8 * 8;
+}
 __host__ __device__ inline size_t links_wave_lds(int nwin) {
-    return ((links_win_ints(nwin) + links_slots(nwin)) * 4 + 7) / 8 * 8 + links_slots(nwin) * sizeof(uint2);
+    return links_list_offset(nwin) + links_slots(nwin) * sizeof(uint2);
 }
 
-// One link of the link pass: everything gathered before any arithmetic.
-template <int MODE> struct LinkIn {
-    bool valid, have1, have2;
-    int i, ib, ex, ey;
-    size_t kb;
-    double q, rx, ry, uwx, uwy;
-    double fi, fi1, fi2, fib, fib1, gi, gi1, gib;
-};
-
-template <int MODE>
-__device__ __forceinline__ void link_gather(const Pops<ST<MODE>>& A, uint2 L, const PState& P, const Win& wn,
-                                            const int* win, int ew, const LP& lp, LinkIn<MODE>& o) {
-    using S = Store<MODE>;
-    const int nx = lp.nx, pitch = lp.pitch;
-    const int x = (int)(L.x & 0xffffu), y = (int)(L.x >> 16), i = (int)(L.y & 15u);
-    const int ex = EXd(i), ey = EYd(i);
-    o.i = i;
-    o.ib = OPPd(i);
-    o.ex = ex;
-    o.ey = ey;
-    const int x1 = wrap_x(x - ex, nx), y1 = y - ey;
-    const int x2 = wrap_x(x - 2 * ex, nx), y2 = y - 2 * ey;
-    const bool in1 = in_rows(y1, lp), in2 = in_rows(y2, lp);
-    const size_t k = (size_t)y * pitch + x;
-    const size_t k1 = in1 ? (size_t)y1 * pitch + x1 : k;
-    const size_t k2 = in2 ? (size_t)y2 * pitch + x2 : k;
-    o.fi = (double)S::ld(A.f[i] + k);
-    o.fib = (double)S::ld(A.f[o.ib] + k);
-    o.fi1 = (double)S::ld(A.f[i] + k1);
-    o.fib1 = (double)S::ld(A.f[o.ib] + k1);
-    o.fi2 = (double)S::ld(A.f[i] + k2);
-    if (i <= 4) {
-        o.gi = (double)S::ld(A.g[i] + k);
-        o.gib = (double)S::ld(A.g[o.ib] + k);
-        o.gi1 = (double)S::ld(A.g[i] + k1);
-    }
-    o.kb = (size_t)(y + ey) * pitch + wrap_x(x + ex, nx);
-    // fluid tests of x_f - e_i and x_f - 2 e_i from the widened window
-    const int a0 = wrap_x(x - wn.x0, nx) + WMARGIN, b0 = y - wn.y0 + WMARGIN;
-    o.have1 = in1 && win[(b0 - ey) * ew + a0 - ex] == -1;
-    o.have2 = o.have1 && in2 && win[(b0 - 2 * ey) * ew + a0 - 2 * ex] == -1;
-    const double dx = min_image_x((double)x - P.x, nx);
-    const double dy = (double)y - P.y;
-    o.q = link_q(dx, dy, P.r, i);
-    o.rx = dx + o.q * ex;   // x_w - X_c
-    o.ry = dy + o.q * ey;
-    o.uwx = P.ux - P.om * o.ry;
-    o.uwy = P.uy + P.om * o.rx;
-}
-
-template <int MODE>
-__device__ __forceinline__ void link_apply(const Pops<ST<MODE>>& A, const LinkIn<MODE>& o, const LP& lp,
-                                           double shf, double& fx, double& fy, double& tz) {
-    using S = Store<MODE>;
-    const double w9i = o.i <= 4 ? 1.0 / 9.0 : 1.0 / 36.0;
-    const double wall = 6.0 * w9i * lp.rho0 * (-(o.ex * o.uwx) - o.ey * o.uwy);
-    const double fnew = bouzidi(o.q, o.fi, o.fi1, o.fi2, o.fib, o.fib1, o.have1, o.have2, wall);
-    S::st(A.f[o.ib] + o.kb, (typename S::R)fnew);
-    if (o.i <= 4) {
-        const double gnew = thermal_link(o.q, o.gi, o.gi1, o.gib, o.have1, lp.w5_k, lp.particle_T - lp.T_sh);
-        S::st(A.g[o.ib] + o.kb, (typename S::R)gnew);
-    }
-    // Eq. (13) on full populations (stored value + rest part w rho0)
-    const double Fi = o.fi + w9i * shf, Fb = (double)(typename S::R)fnew + w9i * shf;
-    const double dFx = Fi * (o.ex - o.uwx) - Fb * (-o.ex - o.uwx);
-    const double dFy = Fi * (o.ey - o.uwy) - Fb * (-o.ey - o.uwy);
-    fx += dFx;
-    fy += dFy;
-    tz += o.rx * dFy - o.ry * dFx;   // Eq. (14), z component
-}
-
-// Link collection and link pass, one wavefront per particle:
-//  (a) clear the owner map / solid bit left by t_n-1 over the window of
-//      X^{n-1} (that buffer and bit will describe t_n+1);
-//  (b) load the particle's widened window of the owner map of t_n into LDS;
+// Link collection (Sec. 3), one wavefront per particle:
+//  (a) clear the owner map left by t_n-1 over the window of X^{n-1} (that
+//      buffer will describe t_n+1);
+//  (b) load the window of the owner map of t_n into LDS;
 //  (c) every fluid node of the window tests its 8 neighbours in parallel; a
 //      neighbour owned by this particle is a link, written into its fixed
 //      slot; the slots are then compacted in slot order (ballot + prefix
 //      count within the wavefront);
 //  (d) one global atomic per block reserves the block's contiguous range of
-//      the link array; each particle's segment is contiguous, in slot order;
-//  (e) link pass (if do_pass): for every link, q, u_w, Bouzidi and thermal
-//      bounce-back into the solid slots of the post-collision state A, and the
-//      momentum exchange summed in FP64 in a fixed order (lane-strided, then
-//      butterfly) into Fh[p].
-template <int MODE>
-__global__ __launch_bounds__(256) void k_links(Pops<ST<MODE>> A, const int32_t* __restrict__ Ocur,
-                                               int32_t* Onext, uint8_t* flag, unsigned clr_bit,
-                                               const PState* __restrict__ Pc, const PState* __restrict__ Po,
-                                               uint2* links, int2* seg, unsigned* counter, double* Fh,
-                                               unsigned* status, LP lp, int ppb, int do_pass) {
-    using S = Store<MODE>;
+//      the link array; each particle's segment is contiguous, in slot order.
+__global__ __launch_bounds__(256) void k_links(const int32_t* __restrict__ Ocur, int32_t* Onext,
+                                               const PState* __restrict__ Pc,
+                                               const PState* __restrict__ Po, uint2* links, int2* seg,
+                                               unsigned* counter, unsigned* status, LP lp, int ppb) {
     extern __shared__ uint2 smem[];
     __shared__ unsigned wave_tot[4];
     __shared__ unsigned block_base;
@@ -319,7 +242,6 @@ __global__ __launch_bounds__(256) void k_links(Pops<ST<MODE>> A, const int32_t* 
                 if (!in_rows(yy, lp)) continue;
                 const size_t k = (size_t)yy * pitch + wrap_x(wo.x0 + a, nx);
                 Onext[k] = -1;
-                flag_clear_bit(flag, k, clr_bit);
             }
         }
     }
@@ -327,7 +249,7 @@ __global__ __launch_bounds__(256) void k_links(Pops<ST<MODE>> A, const int32_t* 
     const size_t wl = links_wave_lds(lp.nwin) / sizeof(uint2);
     int* win = (int*)(smem + (size_t)w * wl);
     unsigned* slot = (unsigned*)(win + links_win_ints(lp.nwin));
-    uint2* lk = smem + (size_t)w * wl + ((links_win_ints(lp.nwin) + links_slots(lp.nwin)) * 4 + 7) / 8;
+    uint2* lk = smem + (size_t)w * wl + links_list_offset(lp.nwin) / sizeof(uint2);
     PState P{};
     Win wn{};
     bool ok = false;
@@ -337,37 +259,37 @@ __global__ __launch_bounds__(256) void k_links(Pops<ST<MODE>> A, const int32_t* 
         ok = particle_ok(P, lp) && wn.nxw <= lp.nwin && wn.nyw <= lp.nwin;
         if (!ok && lane == 0) atomicOr(status, ST_BAD_PARTICLE);
     }
-    const int ew = wn.nxw + 2 * WMARGIN, eh = wn.nyw + 2 * WMARGIN;   // widened window
     unsigned count = 0;
     if (ok) {
+        const int nw = wn.nxw * wn.nyw;
         const int nslots = 6 * (wn.nxw + wn.nyw) - 12;
-        for (int base = 0; base < ew * eh; base += 8 * 64) {   // 8 loads in flight per lane
+        for (int base = 0; base < nw; base += 8 * 64) {   // 8 loads in flight per lane
             int v[8];
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const int idx = base + u * 64 + lane;
-                const int b = idx / ew, a = idx - b * ew;
-                const int yy = wn.y0 - WMARGIN + b;
-                v[u] = (idx < ew * eh && in_rows(yy, lp))
-                           ? Ocur[(size_t)yy * pitch + wrap_x(wn.x0 - WMARGIN + a, nx)] : OUTSIDE;
+                const int b = idx / wn.nxw, a = idx - b * wn.nxw;
+                const int yy = wn.y0 + b;
+                v[u] = (idx < nw && in_rows(yy, lp)) ? Ocur[(size_t)yy * pitch + wrap_x(wn.x0 + a, nx)]
+                                                      : OUTSIDE;
             }
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const int idx = base + u * 64 + lane;
-                if (idx < ew * eh) win[idx] = v[u];
+                if (idx < nw) win[idx] = v[u];
             }
         }
         for (int s = lane; s < nslots; s += 64) slot[s] = 0xffffffffu;
         wave_lds_sync();
-        for (int idx = lane; idx < wn.nxw * wn.nyw; idx += 64) {
+        for (int idx = lane; idx < nw; idx += 64) {
             const int b = idx / wn.nxw, a = idx - b * wn.nxw;
-            if (win[(b + WMARGIN) * ew + a + WMARGIN] != -1) continue;
+            if (win[idx] != -1) continue;
             const unsigned code = (unsigned)wrap_x(wn.x0 + a, nx) | ((unsigned)(wn.y0 + b) << 16);
 #pragma unroll
             for (int d = 1; d < 9; ++d) {
                 const int ta = a + EXd(d), tb = b + EYd(d);
                 if (ta < 0 || ta >= wn.nxw || tb < 0 || tb >= wn.nyw) continue;
-                if (win[(tb + WMARGIN) * ew + ta + WMARGIN] == p) slot[link_slot(d, a, b, wn.nxw, wn.nyw)] = code;
+                if (win[tb * wn.nxw + ta] == p) slot[link_slot(d, a, b, wn.nxw, wn.nyw)] = code;
             }
         }
         wave_lds_sync();
@@ -377,15 +299,8 @@ __global__ __launch_bounds__(256) void k_links(Pops<ST<MODE>> A, const int32_t* 
             const bool v = code != 0xffffffffu;
             const unsigned long long m = __ballot(v);
             if (v) {
-                // the slot tells the direction back: first slot of each direction block
-                int d;
-                const int nd = wn.nxw + wn.nyw - 3, base = 2 * (wn.nyw + wn.nxw);
-                if (s < wn.nyw) d = 1;
-                else if (s < wn.nyw + wn.nxw) d = 2;
-                else if (s < 2 * wn.nyw + wn.nxw) d = 3;
-                else if (s < base) d = 4;
-                else d = 5 + (s - base) / nd;
-                lk[count + __popcll(m & ((1ull << lane) - 1ull))] = make_uint2(code, (unsigned)d | ((unsigned)p << 4));
+                const unsigned d = (unsigned)slot_direction(s, wn.nxw, wn.nyw);
+                lk[count + __popcll(m & ((1ull << lane) - 1ull))] = make_uint2(code, d | ((unsigned)p << 4));
             }
             count += (unsigned)__popcll(m);
         }
@@ -413,34 +328,66 @@ __global__ __launch_bounds__(256) void k_links(Pops<ST<MODE>> A, const int32_t* 
     for (int i = 0; i < w; ++i) start += wave_tot[i];
     for (unsigned i = lane; i < count; i += 64) links[start + i] = lk[i];
     if (lane == 0) seg[p] = make_int2((int)start, (int)count);
-    if (!do_pass) return;
+}
 
-    const double shf = S::shifted ? lp.rho0 : 0.0;  // rest density carried by the stored f
-    double fx = 0.0, fy = 0.0, tz = 0.0;
-    // Two links per lane and iteration: all gathers of both are issued before
-    // either is used.
-    for (unsigned l0 = lane; l0 < count; l0 += 128) {
-        LinkIn<MODE> in[2];
-        const unsigned ls[2] = {l0, l0 + 64};
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            in[u].valid = ls[u] < count;
-            if (in[u].valid) link_gather<MODE>(A, lk[ls[u]], P, wn, win, ew, lp, in[u]);
-        }
-#pragma unroll
-        for (int u = 0; u < 2; ++u)
-            if (in[u].valid) link_apply<MODE>(A, in[u], lp, shf, fx, fy, tz);
+// The link pass, one thread per link of the compacted array (Sec. 2.3-2.4):
+// q from the circle, wall point x_w = x_f + q e_i and its rigid-body velocity
+// u_w, Bouzidi bounce-back f_ibar (Eqs. (9)-(10), with the linear and halfway
+// fallbacks) and, for axis links, the thermal wall g_ibar (Eqs. (11)-(12)),
+// both written into the solid slots x_f + e_i of the post-collision state A
+// that the pull of x_f reads; the link's momentum exchange
+// f_i^+ (e_i - u_w) - f_ibar (e_ibar - u_w) and its torque about X_c go to
+// contrib[l] in FP64.  All gathers are issued before any arithmetic.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_link_pass(Pops<ST<MODE>> A, const int32_t* __restrict__ Ocur,
+                                                   const PState* __restrict__ Pc, const uint2* __restrict__ links,
+                                                   const unsigned* __restrict__ counter, double4* contrib, LP lp) {
+    using S = Store<MODE>;
+    const unsigned l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= counter[0]) return;
+    const int nx = lp.nx, pitch = lp.pitch;
+    const uint2 L = links[l];
+    const int x = (int)(L.x & 0xffffu), y = (int)(L.x >> 16), i = (int)(L.y & 15u), p = (int)(L.y >> 4);
+    const int ib = OPPd(i), ex = EXd(i), ey = EYd(i);
+    const int x1 = wrap_x(x - ex, nx), y1 = y - ey;
+    const int x2 = wrap_x(x - 2 * ex, nx), y2 = y - 2 * ey;
+    const bool in1 = in_rows(y1, lp), in2 = in_rows(y2, lp);
+    const size_t k = (size_t)y * pitch + x;
+    const size_t k1 = in1 ? (size_t)y1 * pitch + x1 : k;
+    const size_t k2 = in2 ? (size_t)y2 * pitch + x2 : k;
+    const PState P = Pc[p];
+    const int32_t o1 = Ocur[k1], o2 = Ocur[k2];
+    const double fi = (double)S::ld(A.f[i] + k), fib = (double)S::ld(A.f[ib] + k);
+    const double fi1 = (double)S::ld(A.f[i] + k1), fib1 = (double)S::ld(A.f[ib] + k1);
+    const double fi2 = (double)S::ld(A.f[i] + k2);
+    double gi = 0.0, gib = 0.0, gi1 = 0.0;
+    if (i <= 4) {
+        gi = (double)S::ld(A.g[i] + k);
+        gib = (double)S::ld(A.g[ib] + k);
+        gi1 = (double)S::ld(A.g[i] + k1);
     }
-    for (int off = 32; off > 0; off >>= 1) {
-        fx += __shfl_xor(fx, off);
-        fy += __shfl_xor(fy, off);
-        tz += __shfl_xor(tz, off);
+    const bool have1 = in1 && o1 == -1;
+    const bool have2 = have1 && in2 && o2 == -1;
+    const double dx = min_image_x((double)x - P.x, nx);
+    const double dy = (double)y - P.y;
+    const double q = link_q(dx, dy, P.r, i);
+    const double rx = dx + q * ex, ry = dy + q * ey;   // x_w - X_c
+    const double uwx = P.ux - P.om * ry, uwy = P.uy + P.om * rx;
+    const double w9i = i <= 4 ? 1.0 / 9.0 : 1.0 / 36.0;
+    const double wall = 6.0 * w9i * lp.rho0 * (-(ex * uwx) - ey * uwy);
+    const double fnew = bouzidi(q, fi, fi1, fi2, fib, fib1, have1, have2, wall);
+    const size_t kb = (size_t)(y + ey) * pitch + wrap_x(x + ex, nx);
+    S::st(A.f[ib] + kb, (typename S::R)fnew);
+    if (i <= 4) {
+        const double gnew = thermal_link(q, gi, gi1, gib, have1, lp.w5_k, lp.particle_T - lp.T_sh);
+        S::st(A.g[ib] + kb, (typename S::R)gnew);
     }
-    if (lane == 0) {
-        Fh[4 * p + 0] = fx;
-        Fh[4 * p + 1] = fy;
-        Fh[4 * p + 2] = tz;
-    }
+    // Eq. (13) on full populations (stored value + rest part w rho0)
+    const double shf = S::shifted ? lp.rho0 : 0.0;
+    const double Fi = fi + w9i * shf, Fb = (double)(typename S::R)fnew + w9i * shf;
+    const double dFx = Fi * (ex - uwx) - Fb * (-ex - uwx);
+    const double dFy = Fi * (ey - uwy) - Fb * (-ey - uwy);
+    contrib[l] = make_double4(dFx, dFy, rx * dFy - ry * dFx, 0.0);   // Eq. (14), z component
 }
 
 // Spring repulsion of Eq. (15) on particle (xp, yp, rp) from (xq, yq, rq):
@@ -483,13 +430,16 @@ __global__ __launch_bounds__(256) void k_bin_init(const PState* __restrict__ P, 
     if (p < lp.np) bin_insert(P[p], p, bins, cnt, status, lp);
 }
 
-// Particle update, one wavefront per particle: neighbours from the cell grid
-// of t_n (lane = one slot of the 3 x 3 cells around the particle), repulsion
-// summed in ascending partner index (the same order as a plain loop over all
-// partners), walls, net weight, Newton-Euler; the new state goes into the
-// cell grid of t_n+1.
+// Particle update, one wavefront per particle (Sec. 2.2, 2.4):
+//  - the momentum exchange of the particle's links, summed in FP64 over its
+//    segment in a fixed order (lane-strided, then a butterfly), into Fh[p];
+//  - repulsion: partners from the cell grid of t_n (lane = one slot of the
+//    3 x 3 cells around the particle), summed in ascending partner index (the
+//    order of a plain loop over all partners); walls; net weight;
+//  - Newton-Euler; the new state goes into the cell grid of t_n+1.
 __global__ __launch_bounds__(256) void k_particles(const PState* __restrict__ Pc, PState* Pn,
-                                                   const double* __restrict__ Fh,
+                                                   const int2* __restrict__ seg,
+                                                   const double4* __restrict__ contrib, double* Fh,
                                                    const unsigned* __restrict__ bins_cur,
                                                    const unsigned* __restrict__ cnt_cur, unsigned* bins_next,
                                                    unsigned* cnt_next, unsigned* counter, unsigned* status,
@@ -498,6 +448,19 @@ __global__ __launch_bounds__(256) void k_particles(const PState* __restrict__ Pc
     const int p = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (p >= lp.np) return;
     const PState P = Pc[p];
+    const int2 sg = seg[p];
+    double hx = 0.0, hy = 0.0, hz = 0.0;
+    for (int l = lane; l < sg.y; l += 64) {
+        const double4 c = contrib[sg.x + l];
+        hx += c.x;
+        hy += c.y;
+        hz += c.z;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        hx += __shfl_xor(hx, off);
+        hy += __shfl_xor(hy, off);
+        hz += __shfl_xor(hz, off);
+    }
     double Rx = 0.0, Ry = 0.0;
     if (lp.repulsion && particle_ok(P, lp)) {
         const int c0 = cell_of(P, lp);
@@ -568,10 +531,13 @@ __global__ __launch_bounds__(256) void k_particles(const PState* __restrict__ Pc
         counter[1] = counter[0];
         counter[0] = 0u;
     }
+    Fh[4 * p + 0] = hx;
+    Fh[4 * p + 1] = hy;
+    Fh[4 * p + 2] = hz;
     const double Fg = -(lp.rho_ratio - 1.0) * lp.rho0 * kPi * P.r * P.r * lp.gravity;
-    const double Fx = Fh[4 * p + 0] + Rx;
-    const double Fy = (Fh[4 * p + 1] + Ry) + Fg;
-    const double Tz = Fh[4 * p + 2];
+    const double Fx = hx + Rx;
+    const double Fy = (hy + Ry) + Fg;
+    const double Tz = hz;
     // Newton-Euler (Sec. 2.2): explicit velocities, trapezoidal positions.
     const double mass = lp.rho_ratio * lp.rho0 * kPi * P.r * P.r;
     const double inertia = 0.5 * mass * P.r * P.r;
@@ -590,15 +556,14 @@ __global__ __launch_bounds__(256) void k_particles(const PState* __restrict__ Pc
     bin_insert(N, p, bins_next, cnt_next, status, lp);
 }
 
-// Owner map and solid bit of t_n+1, one wavefront per particle, over the
+// Owner map of t_n+1, one wavefront per particle, over the
 // union of the particle's windows at t_n and t_n+1: a node inside the disk at
 // t_n+1 gets owner = the lowest index whose disk holds it (atomic min, exact
 // solid test); a node inside the disk at t_n but not at t_n+1 is a newborn
 // candidate (k_refill keeps it if this particle owned it at t_n and no
 // particle covers it at t_n+1).  Also clears the cell-grid counts read this
 // step.
-__global__ __launch_bounds__(256) void k_mask_mark(int32_t* O, uint8_t* flag, unsigned set_bit,
-                                                   const PState* __restrict__ Pp,
+__global__ __launch_bounds__(256) void k_mask_mark(int32_t* O, const PState* __restrict__ Pp,
                                                    const PState* __restrict__ Pprev, unsigned* cand,
                                                    unsigned* ncand, unsigned* cnt_clear, unsigned* status,
                                                    LP lp) {
@@ -644,7 +609,6 @@ __global__ __launch_bounds__(256) void k_mask_mark(int32_t* O, uint8_t* flag, un
                 const size_t k = (size_t)yy * lp.pitch + xx;
                 if (dx * dx + dy * dy <= r2) {
                     atomicMin((unsigned*)&O[k], (unsigned)p);
-                    flag_set_bit(flag, k, set_bit);
                 } else if (with_prev) {
                     const double qx = min_image_x((double)xx - Q.x, lp.nx);
                     const double qy = (double)yy - Q.y;
@@ -669,12 +633,13 @@ __global__ __launch_bounds__(256) void k_mask_mark(int32_t* O, uint8_t* flag, un
     }
 }
 
-// Refilling of the newborn node (x, y) of particle P (state at t_n+1),
+// Refilling of the newborn node (x, y) of particle p (state P at t_n+1),
 // Sec. 2.5: e_c maximises n . e_c (n parallel to x - X_c; ties to the lowest
 // index); pre-collision f at x + m e_c (m = 1..3, nodes fluid at t_n and
 // t_n+1) rebuilt by pulling from A; Eq. (16) extrapolation (lower order when
 // fewer points are fluid, equilibrium at rho0 with none); momentum set so
-// that u = u_w; g = g^eq(T_w, u_w) (Eq. (17)); then collided into B.
+// that u = u_w; g = g^eq(T_w, u_w) (Eq. (17)); then collided into B.  The
+// node is skipped unless p owned it at t_n and it is fluid at t_n+1.
 template <int MODE>
 __device__ void refill_node(const Pops<ST<MODE>>& A, const Pops<ST<MODE>>& B, const int32_t* Ocur,
                             const int32_t* Onext, const PState& P, int p, int x, int y, const LP& lp) {
@@ -692,18 +657,17 @@ __device__ void refill_node(const Pops<ST<MODE>>& A, const Pops<ST<MODE>>& B, co
             c = d;
         }
     }
-    // owner tests of the node itself and of the stencil, and the pulls of
-    // every in-lattice stencil node, all issued before any is used
+    // owner tests of the node and of the stencil, and the pulls of every
+    // in-lattice stencil node, all issued before any is used
     int xs[3], ys[3];
-    bool fl[3], inr[3];
+    bool fl[3];
     R sm[3][9];
     const bool mine = Ocur[k0] == p && Onext[k0] == -1;
     for (int m = 0; m < 3; ++m) {
         ys[m] = y + (m + 1) * EYd(c);
         xs[m] = wrap_x(x + (m + 1) * EXd(c), lp.nx);
-        inr[m] = in_rows(ys[m], lp);
         fl[m] = false;
-        if (inr[m]) {
+        if (in_rows(ys[m], lp)) {
             const size_t km = (size_t)ys[m] * lp.pitch + xs[m];
             fl[m] = Ocur[km] == -1 && Onext[km] == -1;
             R tt[5];
@@ -743,8 +707,7 @@ __device__ void refill_node(const Pops<ST<MODE>>& A, const Pops<ST<MODE>>& B, co
 }
 
 // Refill of particle p's newborn nodes, one wavefront per particle and one
-// lane per candidate from k_mask_mark; a candidate is refilled if p owned it
-// at t_n and no particle covers it at t_n+1.
+// lane per candidate from k_mask_mark.
 template <int MODE>
 __global__ __launch_bounds__(256) void k_refill(Pops<ST<MODE>> A, Pops<ST<MODE>> B,
                                                 const int32_t* __restrict__ Ocur,
@@ -797,7 +760,8 @@ static unsigned wave_blocks(int np) { return (unsigned)((np + 3) / 4); }
 hipError_t launch_stream_collide(const DevState& d, int cur, hipStream_t st) {
     const unsigned blocks = (unsigned)(((size_t)d.lp.pitch * d.lp.ny + LAT_BLOCK - 1) / LAT_BLOCK);
     PTLBM_DISPATCH(d.mode, (k_stream_collide<M><<<blocks, LAT_BLOCK, 0, st>>>(
-                               pops_of<M>(d.S[cur]), pops_of<M>(d.S[1 - cur]), d.flag, d.lp, d.status)));
+                               pops_of<M>(d.S[cur]), pops_of<M>(d.S[1 - cur]), d.O[0], d.O[1], d.lp,
+                               d.status)));
     return hipGetLastError();
 }
 
@@ -832,22 +796,27 @@ int links_particles_per_block(int nwin) {
     return ppb < 1 ? 1 : (ppb > 4 ? 4 : ppb);
 }
 
-hipError_t launch_links(const DevState& d, int cur, int ring, bool do_pass, hipStream_t st) {
+hipError_t launch_links(const DevState& d, int cur, int ring, hipStream_t st) {
     if (d.lp.np == 0) return hipSuccess;
     const int ppb = links_particles_per_block(d.lp.nwin);
     const unsigned blocks = (unsigned)((d.lp.np + ppb - 1) / ppb);
     const size_t lds = (size_t)ppb * links_wave_lds(d.lp.nwin);
-    const unsigned clr = 1u << (1 - cur);
-    PTLBM_DISPATCH(d.mode, (k_links<M><<<blocks, 64 * ppb, lds, st>>>(
-                               pops_of<M>(d.S[cur]), d.O[cur], d.O[1 - cur], d.flag, clr, d.P[ring],
-                               d.P[ring_old(ring)], d.links, d.seg, d.counter, d.Fh, d.status, d.lp, ppb,
-                               do_pass ? 1 : 0)));
+    k_links<<<blocks, 64 * ppb, lds, st>>>(d.O[cur], d.O[1 - cur], d.P[ring],
+                                           d.P[ring_old(ring)], d.links, d.seg, d.counter, d.status, d.lp, ppb);
+    return hipGetLastError();
+}
+
+hipError_t launch_link_pass(const DevState& d, int cur, int ring, hipStream_t st) {
+    if (d.lp.np == 0 || d.lp.link_cap == 0) return hipSuccess;
+    const unsigned blocks = (unsigned)((d.lp.link_cap + 255) / 256);
+    PTLBM_DISPATCH(d.mode, (k_link_pass<M><<<blocks, 256, 0, st>>>(pops_of<M>(d.S[cur]), d.O[cur], d.P[ring],
+                                                                  d.links, d.counter, d.contrib, d.lp)));
     return hipGetLastError();
 }
 
 hipError_t launch_particles(const DevState& d, int ring, int bin_parity, hipStream_t st) {
     if (d.lp.np == 0) return hipSuccess;
-    k_particles<<<wave_blocks(d.lp.np), 256, 0, st>>>(d.P[ring], d.P[ring_next(ring)], d.Fh,
+    k_particles<<<wave_blocks(d.lp.np), 256, 0, st>>>(d.P[ring], d.P[ring_next(ring)], d.seg, d.contrib, d.Fh,
                                                        d.bins[bin_parity], d.bcnt[bin_parity],
                                                        d.bins[1 - bin_parity], d.bcnt[1 - bin_parity],
                                                        d.counter, d.status, d.lp);
@@ -864,8 +833,8 @@ hipError_t launch_bin_init(const DevState& d, const PState* P, int bin_parity, h
 hipError_t launch_mask_mark(const DevState& d, int owner_idx, const PState* P, const PState* Pprev,
                             unsigned* cnt_clear, hipStream_t st) {
     if (d.lp.np == 0) return hipSuccess;
-    k_mask_mark<<<wave_blocks(d.lp.np), 256, 0, st>>>(d.O[owner_idx], d.flag, 1u << owner_idx, P, Pprev,
-                                                       d.cand, d.ncand, cnt_clear, d.status, d.lp);
+    k_mask_mark<<<wave_blocks(d.lp.np), 256, 0, st>>>(d.O[owner_idx], P, Pprev, d.cand,
+                                                       d.ncand, cnt_clear, d.status, d.lp);
     return hipGetLastError();
 }
 

@@ -15,9 +15,9 @@ struct DevState {
     int mode;
     void* S[2][14];              // population arrays of the two time levels
     int32_t* O[2];               // owner maps
-    uint8_t* flag;               // bit c: solid in owner map O[c]; 0 = fluid at t_n and t_n+1
     PState* P[3];                // particle ring (old, current, next rotate)
     double* Fh;                  // per-particle momentum-exchange force/torque (x, y, z, pad)
+    double4* contrib;            // per-link momentum exchange (Fx, Fy, Tz, pad)
     uint2* links;                // compacted link array
     int2* seg;                   // per-particle {start, count}
     unsigned* counter;           // [0] link counter, [1] links of the last step
@@ -41,7 +41,8 @@ hipError_t launch_stream_collide(const DevState& d, int cur, hipStream_t st);
 hipError_t launch_init(const DevState& d, int cur, const void* rho, const void* ux, const void* uy,
                        const void* T, bool fields_f64, double rho_u, double T_u, hipStream_t st);
 hipError_t launch_macros(const DevState& d, int cur, void* out, hipStream_t st);
-hipError_t launch_links(const DevState& d, int cur, int ring, bool do_pass, hipStream_t st);
+hipError_t launch_links(const DevState& d, int cur, int ring, hipStream_t st);
+hipError_t launch_link_pass(const DevState& d, int cur, int ring, hipStream_t st);
 hipError_t launch_particles(const DevState& d, int ring, int bin_parity, hipStream_t st);
 hipError_t launch_bin_init(const DevState& d, const PState* P, int bin_parity, hipStream_t st);
 hipError_t launch_mask_mark(const DevState& d, int owner_idx, const PState* P, const PState* Pprev,

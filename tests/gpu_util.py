@@ -94,3 +94,30 @@ def compare_links(lg, lo, q_ulps=2, q_abs=None):
         else:
             assert dq.max() <= q_abs, dq.max()
     return len(a["node"]), dq.max() if len(dq) else 0.0
+
+
+def nusselt_from_fields(T, owner, wall_T, dT=1.0):
+    """Wall Nusselt numbers (bottom, top): one-sided gradient between each wall
+    (half a spacing away) and its adjacent fluid row, scaled by H / dT."""
+    H = T.shape[0]
+    out = []
+    for w, j in ((0, 0), (1, H - 1)):
+        row = T[j][owner[j] < 0]
+        out.append(((row - wall_T[w]) / 0.5).mean() * H / dT)
+    return tuple(out)
+
+
+def form_errors(fg, fo, pg, po):
+    """Error of a reduced-precision run against the FP64 oracle: L2-relative
+    velocity and temperature over nodes fluid in both, largest particle
+    displacement (lattice units), Nusselt numbers."""
+    both = (fg["owner"] < 0) & (fo["owner"] < 0)
+    du = np.hypot(fg["ux"][both] - fo["ux"][both], fg["uy"][both] - fo["uy"][both])
+    u = np.hypot(fo["ux"][both], fo["uy"][both])
+    eu = np.sqrt((du ** 2).sum() / (u ** 2).sum())
+    eT = np.sqrt(((fg["T"][both] - fo["T"][both]) ** 2).sum() / (fo["T"][both] ** 2).sum())
+    dx = pg[:, 0] - po[:, 0]
+    dx = np.where(dx > 128, dx - 256, np.where(dx < -128, dx + 256, dx))
+    dX = np.hypot(dx, pg[:, 1] - po[:, 1]).max()
+    return dict(eps_u=float(eu), eps_T=float(eT), max_dX=float(dX),
+                owner_mismatch=int((fg["owner"] != fo["owner"]).sum()))
