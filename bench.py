@@ -16,6 +16,12 @@ Prints one JSON line.  Besides the throughput it carries:
                populations) / mean launch time, against 8 TB/s.
   cpu_baseline the CPU oracle (single thread, FP64) on a bounded sample of
                the same workload, timed on this host.
+  serving      256 seeded requests (lattices 128..1024 on a side, aspect 1
+               or 2, 5..400 particles of diameter 8..24, Ra 1e5..1e8, 500..5000
+               steps, BF16 storage) served from a 2 GiB device budget: first
+               all at t = 0 (closed loop, giving the capacity), then with
+               Poisson arrivals at 0.8 x that capacity; p50/p99 latency
+               (completion - arrival, queueing included), requests/s, MLUPS.
 """
 import argparse
 import hashlib
@@ -24,6 +30,8 @@ import os
 import re
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -85,6 +93,44 @@ def cpu_baseline(workload, steps):
                        f"particles (FP64, one thread): {dt:.1f} s")
 
 
+def serving(n_req, budget_gib, chunk):
+    import lbm_inputs
+    from paper_2308_16597_amd import serve
+    reqs = lbm_inputs.serving_requests(n_req, seed=4)
+    srv = serve.Server(int(budget_gib * (1 << 30)), storage="shift_bf16", chunk=chunk)
+    t0 = time.perf_counter()
+    prog = lambda k, n: log(f"[bench] serving: {k}/{n} requests done")  # noqa: E731
+    closed = srv.run(reqs, np.zeros(n_req), prog)
+    closed_sum = serve.summarize(closed, time.perf_counter() - t0)
+    log(f"[bench] serving closed loop: {closed_sum}")
+    lam = 0.8 * closed_sum["req_per_s"]
+    arr = lbm_inputs.poisson_arrivals(n_req, lam, seed=4)
+    t0 = time.perf_counter()
+    opened = srv.run(reqs, arr, prog)
+    s = serve.summarize(opened, time.perf_counter() - t0)
+    log(f"[bench] serving open loop at {lam:.2f} req/s: {s}")
+    return dict(requests=n_req, budget_gib=budget_gib, storage="shift_bf16", chunk_steps=chunk,
+                closed_loop=dict(wall_s=round(closed_sum["wall_s"], 3),
+                                 req_per_s=round(closed_sum["req_per_s"], 3),
+                                 mlups=round(closed_sum["mlups"], 1), failed=closed_sum["failed"]),
+                arrival_rate_req_per_s=round(lam, 3),
+                p50_s=round(s["p50_s"], 4), p99_s=round(s["p99_s"], 4),
+                req_per_s=round(s["req_per_s"], 3), mlups=round(s["mlups"], 1),
+                completed=s["completed"], failed=s["failed"], ra_capped=s["ra_capped"])
+
+
+def copy_probe(nbytes, reps=5):
+    """Plain device-to-device copies of a known size: the reference that the
+    hardware byte counters of the stream-collide kernel are scaled by."""
+    import torch
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"[bench] copy probe: {reps} copies of {a.numel() * 8} bytes")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -95,6 +141,12 @@ def main():
     ap.add_argument("--phase-steps", type=int, default=100)
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="only run plain copies of this many bytes (counter calibration)")
+    ap.add_argument("--serve-requests", type=int, default=256)
+    ap.add_argument("--serve-budget-gib", type=float, default=2.0)
+    ap.add_argument("--serve-chunk", type=int, default=120)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -102,6 +154,9 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
     from paper_2308_16597_amd import lbm, params
 
     w = params.WORKLOADS[args.workload]
@@ -171,6 +226,8 @@ def main():
     }
     sim.close()
     del sim
+    if not args.no_serve:
+        out["serving"] = serving(args.serve_requests, args.serve_budget_gib, args.serve_chunk)
     if not args.no_cpu_baseline:
         log(f"[bench] cpu baseline: oracle, {args.cpu_steps} steps")
         out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_steps)

@@ -180,6 +180,26 @@ int lbm_set_equilibrium(lbm_handle h, const double* rho, const double* ux, const
 /* Enqueue nsteps steps on the handle's stream and return. */
 int lbm_step(lbm_handle h, int32_t nsteps);
 
+/* Advance count runs together, run i by nsteps[i] steps, for serving many
+ * independent simulations on one GPU (the method of Secs. 2-3 applied to
+ * each run; nothing couples the runs).  Every step kernel is launched once
+ * per step as one grid over all runs that still have steps left (a run
+ * table in device memory), and whole 6-step cycles of an unchanged set of
+ * runs are replayed from a captured HIP graph.  A run computes the same bits
+ * as with lbm_step.
+ *   hs       count distinct handles of one storage mode
+ *   nsteps   count step counts >= 0
+ *   stream   HIP stream for the batched work, or NULL for hs[0]'s stream;
+ *            it is ordered after, and each handle's stream before, the
+ *            work already enqueued on the other.
+ * Returns without waiting.  The library keeps device run tables and
+ * graphs for the last 16 sets of runs; they are freed when a member handle
+ * is destroyed or gets new particles.  Errors are reported on hs[0]
+ * (LBM_EINVAL for a null or repeated handle, a negative count or mixed
+ * storage modes, LBM_EDEVICE for a failed launch or capture); device errors
+ * of a run surface at its next waiting call. */
+int lbm_step_many(lbm_handle* hs, int32_t count, const int32_t* nsteps, void* stream);
+
 /* Wait for the stream; report deferred device errors. */
 int lbm_sync(lbm_handle h);
 

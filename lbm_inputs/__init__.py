@@ -138,3 +138,48 @@ def random_state(n, seed, lo=0.0, hi=1.0):
     """n uniform doubles in [lo, hi) from SplitMix64."""
     rng = SplitMix64(seed)
     return np.array([lo + (hi - lo) * rng.uniform() for _ in range(n)])
+
+
+def _uniform_int(rng, lo, hi):
+    """Integer uniform on [lo, hi] from one draw."""
+    return lo + min(int(rng.uniform() * (hi - lo + 1)), hi - lo)
+
+
+def serving_requests(n=256, seed=4, L_range=(128, 1024), np_range=(5, 400), d_range=(8, 24),
+                     Ra_range=(1e5, 1e8), steps_range=(500, 5000), max_fill=0.2):
+    """A seeded mix of independent simulation requests for the serving form.
+
+    Per request, in draw order: edge L = round(exp(U[ln L_lo, ln L_hi])); aspect
+    A = 1 if the next draw is < 1/2 else 2, with nx = L, ny = A L; diameter d
+    uniform integer in d_range; particle count uniform integer in np_range,
+    then lowered to the largest count whose disks cover at most max_fill of the
+    lattice; Ra = exp(U[ln Ra_lo, ln Ra_hi]); step count uniform integer in
+    steps_range.  Each request also carries the seed of its particle placement
+    (seed * 100003 + index).
+    """
+    rng = SplitMix64(seed)
+    out = []
+    for i in range(n):
+        L = int(round(math.exp(math.log(L_range[0]) + rng.uniform() *
+                               (math.log(L_range[1]) - math.log(L_range[0])))))
+        A = 1 if rng.uniform() < 0.5 else 2
+        d = float(_uniform_int(rng, int(d_range[0]), int(d_range[1])))
+        n_p = _uniform_int(rng, np_range[0], np_range[1])
+        n_fill = int(max_fill * L * A * L / (math.pi * d * d / 4.0))
+        n_p = max(0, min(n_p, n_fill))
+        Ra = math.exp(math.log(Ra_range[0]) + rng.uniform() * (math.log(Ra_range[1]) - math.log(Ra_range[0])))
+        steps = _uniform_int(rng, steps_range[0], steps_range[1])
+        out.append(dict(rid=i, nx=L, ny=A * L, d=d, n=n_p, Ra=Ra, steps=steps,
+                        seed=seed * 100003 + i))
+    return out
+
+
+def poisson_arrivals(n, rate, seed):
+    """Arrival times (seconds, from 0) of a Poisson process of the given rate:
+    cumulative sums of exponential gaps -ln(1 - U) / rate."""
+    rng = SplitMix64(seed)
+    t, out = 0.0, []
+    for _ in range(n):
+        t += -math.log(1.0 - rng.uniform()) / rate
+        out.append(t)
+    return np.array(out)

@@ -10,10 +10,11 @@
 #include <string>
 #include <vector>
 
-#include "launch.h"
-#include "lbm.h"
+#include "sim.h"
 
 using namespace ptlbm;
+
+static_assert(LBM_NPHASES == SK_COUNT, "one timed phase per step kernel");
 
 namespace {
 
@@ -38,17 +39,6 @@ size_t elem_size(int mode) {
 
 // Largest window edge for a diameter: INT(x + r) - INT(x - r) + 3 <= floor(2r) + 4.
 int window_cap(double max_diameter) { return (int)std::floor(max_diameter) + 4; }
-
-struct Layout {
-    int pitch = 0;
-    size_t npitched = 0, array_stride = 0, state_bytes = 0;
-    size_t off_S[2] = {0, 0}, off_O[2] = {0, 0}, off_contrib = 0, off_P = 0, off_Fh = 0, off_seg = 0,
-           off_links = 0, off_lscratch = 0, off_counter = 0, off_status = 0, off_bins[2] = {0, 0},
-           off_bcnt[2] = {0, 0}, off_cand = 0, off_ncand = 0, total = 0;
-    int nwin = 0;
-    size_t link_cap = 0;
-    int ncx = 1, ncy = 1;
-};
 
 Layout make_layout(const lbm_params& p) {
     Layout L;
@@ -90,24 +80,7 @@ Layout make_layout(const lbm_params& p) {
 
 }  // namespace
 
-struct lbm_sim {
-    lbm_params p{};
-    Layout L;
-    DevState d{};
-    hipStream_t stream = nullptr;
-    bool own_stream = false;
-    char* base = nullptr;
-    bool own_mem = false;
-    int cur = 0;    // time level holding the current (post-collision) state
-    int ring = 0;   // particle slot of the current time level
-    int bin_parity = 0;  // cell grid holding the particles of the current time level
-    int np = 0;
-    int64_t steps = 0;
-    std::string err;
-    std::vector<double> host_fields;
-};
-
-namespace {
+namespace ptlbm {
 
 int fail(lbm_sim* h, int code, const char* fmt, ...) {
     char buf[512];
@@ -124,11 +97,9 @@ int hip_fail(lbm_sim* h, hipError_t e, const char* what) {
     return fail(h, LBM_EDEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
-#define HIPCHK(h, expr)                                   \
-    do {                                                  \
-        hipError_t e_ = (expr);                           \
-        if (e_ != hipSuccess) return hip_fail(h, e_, #expr); \
-    } while (0)
+}  // namespace ptlbm
+
+namespace {
 
 bool validate(const lbm_params* p, std::string& why) {
     char buf[256];
@@ -293,33 +264,60 @@ int check_status(lbm_sim* h) {
     return fail(h, LBM_EUNSTABLE, "%s", m.c_str());
 }
 
-int enqueue_step(lbm_sim* h, hipEvent_t* ev) {
+}  // namespace
+
+namespace ptlbm {
+
+RunStep make_runstep(const lbm_sim* h, int c, int r, int bp) {
     const DevState& d = h->d;
-    hipStream_t st = h->stream;
-    const int c = h->cur, r = h->ring;
-    int ph = 0;
-    auto mark = [&]() {
-        if (ev) (void)hipEventRecord(ev[ph], st);
-        ++ph;
-    };
-    const int bp = h->bin_parity;
-    mark();
-    HIPCHK(h, launch_links(d, c, r, st));
-    mark();
-    HIPCHK(h, launch_link_pass(d, c, r, st));
-    mark();
-    HIPCHK(h, launch_particles(d, r, bp, st));
-    mark();
-    HIPCHK(h, launch_mask_mark(d, 1 - c, d.P[ring_next(r)], d.P[r], d.bcnt[bp], st));
-    mark();
-    HIPCHK(h, launch_stream_collide(d, c, st));
-    mark();
-    HIPCHK(h, launch_refill(d, c, r, st));
-    mark();
-    h->cur = 1 - c;
-    h->ring = ring_next(r);
-    h->bin_parity = 1 - bp;
+    RunStep R{};
+    R.lp = d.lp;
+    for (int i = 0; i < 14; ++i) {
+        R.A[i] = d.S[c][i];
+        R.B[i] = d.S[1 - c][i];
+    }
+    R.Ocur = d.O[c];
+    R.Onext = d.O[1 - c];
+    R.Pold = d.P[ring_old(r)];
+    R.Pc = d.P[r];
+    R.Pn = d.P[ring_next(r)];
+    R.Fh = d.Fh;
+    R.contrib = d.contrib;
+    R.links = d.links;
+    R.seg = d.seg;
+    R.counter = d.counter;
+    R.status = d.status;
+    R.bins_cur = d.bins[bp];
+    R.cnt_cur = d.bcnt[bp];
+    R.bins_next = d.bins[1 - bp];
+    R.cnt_next = d.bcnt[1 - bp];
+    R.cand = d.cand;
+    R.ncand = d.ncand;
+    return R;
+}
+
+RunStep current_runstep(const lbm_sim* h) { return make_runstep(h, h->cur, h->ring, h->bin_parity); }
+
+void advance_state(lbm_sim* h) {
+    h->cur = 1 - h->cur;
+    h->ring = ring_next(h->ring);
+    h->bin_parity = 1 - h->bin_parity;
     h->steps += 1;
+}
+
+}  // namespace ptlbm
+
+namespace {
+
+int enqueue_step(lbm_sim* h, hipEvent_t* ev) {
+    hipStream_t st = h->stream;
+    const RunStep R = current_runstep(h);
+    for (int k = 0; k < SK_COUNT; ++k) {
+        if (ev) HIPCHK(h, hipEventRecord(ev[k], st));
+        HIPCHK(h, launch_step(k, R, h->d.mode, st));
+    }
+    if (ev) HIPCHK(h, hipEventRecord(ev[SK_COUNT], st));
+    advance_state(h);
     return LBM_OK;
 }
 
@@ -371,6 +369,7 @@ int lbm_create_in_arena(const lbm_params* p, void* dev_ptr, size_t bytes, void* 
 
 void lbm_destroy(lbm_handle h) {
     if (!h) return;
+    forget_batches(h);
     if (h->stream) (void)hipStreamSynchronize(h->stream);
     if (h->own_mem && h->base) (void)hipFree(h->base);
     if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
@@ -478,7 +477,9 @@ int lbm_set_particles(lbm_handle h, int32_t n, const double* rows7) {
     DevState& d = h->d;
     hipStream_t st = h->stream;
     HIPCHK(h, hipStreamSynchronize(st));
+    forget_batches(h);
     h->np = n;
+    h->generation += 1;
     d.lp.np = n;
     h->cur = 0;
     h->ring = 0;
@@ -496,7 +497,8 @@ int lbm_set_particles(lbm_handle h, int32_t n, const double* rows7) {
         for (int b = 0; b < 2; ++b)
             HIPCHK(h, hipMemsetAsync(d.bcnt[b], 0, sizeof(unsigned) * (size_t)d.lp.ncells, st));
         HIPCHK(h, hipMemsetAsync(d.ncand, 0, sizeof(unsigned) * n, st));
-        HIPCHK(h, launch_mask_mark(d, 0, d.P[0], nullptr, nullptr, st));
+        // owner map of t_0 into O[0] from the particles in ring slot 0
+        HIPCHK(h, launch_mask_setup(make_runstep(h, 1, 2, 0), st));
         HIPCHK(h, launch_bin_init(d, d.P[0], 0, st));
     }
     HIPCHK(h, launch_init(d, 0, nullptr, nullptr, nullptr, nullptr, true, h->p.rho0, h->p.T_fluid0, st));
@@ -611,7 +613,7 @@ int lbm_read_links(lbm_handle h, int32_t* node, int32_t* dir, int32_t* particle,
     unsigned saved[2];
     HIPCHK(h, hipMemcpyAsync(saved, d.counter, sizeof saved, hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipMemsetAsync(d.counter, 0, sizeof(unsigned), h->stream));
-    HIPCHK(h, launch_links(d, h->cur, h->ring, h->stream));
+    HIPCHK(h, launch_step(SK_LINKS, current_runstep(h), d.mode, h->stream));
     unsigned nl = 0;
     HIPCHK(h, hipMemcpyAsync(&nl, d.counter, sizeof nl, hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));

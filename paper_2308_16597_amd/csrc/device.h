@@ -15,6 +15,12 @@
 
 namespace ptlbm {
 
+// Device-memory pointers typed as such: every access through them compiles
+// to a global (not flat) memory instruction, also when the pointer itself
+// was read from a run table in memory rather than from kernel arguments.
+#define PT_GLOBAL __attribute__((address_space(1)))
+template <class T> __device__ __forceinline__ PT_GLOBAL T* gl(T* p) { return (PT_GLOBAL T*)p; }
+
 // --------------------------------------------------------------- storage ----
 // Populations are kept as deviations from the rest state inside the kernels:
 //   s_i = f_i - w_i rho0,   t_k = g_k - w_k T_sh.
@@ -34,38 +40,38 @@ __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
 template <int MODE> struct Store;
 template <> struct Store<LBM_STORE_F64> {
     using T = double; using R = double; static constexpr bool shifted = false;
-    __device__ static R ld(const T* p) { return *p; }
-    __device__ static void st(T* p, R v) { *p = v; }
-    __device__ static void st_nt(T* p, R v) { __builtin_nontemporal_store(v, p); }
+    __device__ static R ld(const PT_GLOBAL T* p) { return *p; }
+    __device__ static void st(PT_GLOBAL T* p, R v) { *p = v; }
+    __device__ static void st_nt(PT_GLOBAL T* p, R v) { __builtin_nontemporal_store(v, p); }
 };
 template <> struct Store<LBM_STORE_F32> {
     using T = float; using R = float; static constexpr bool shifted = false;
-    __device__ static R ld(const T* p) { return *p; }
-    __device__ static void st(T* p, R v) { *p = v; }
-    __device__ static void st_nt(T* p, R v) { __builtin_nontemporal_store(v, p); }
+    __device__ static R ld(const PT_GLOBAL T* p) { return *p; }
+    __device__ static void st(PT_GLOBAL T* p, R v) { *p = v; }
+    __device__ static void st_nt(PT_GLOBAL T* p, R v) { __builtin_nontemporal_store(v, p); }
 };
 template <> struct Store<LBM_STORE_SHIFT_F32> {
     using T = float; using R = float; static constexpr bool shifted = true;
-    __device__ static R ld(const T* p) { return *p; }
-    __device__ static void st(T* p, R v) { *p = v; }
-    __device__ static void st_nt(T* p, R v) { __builtin_nontemporal_store(v, p); }
+    __device__ static R ld(const PT_GLOBAL T* p) { return *p; }
+    __device__ static void st(PT_GLOBAL T* p, R v) { *p = v; }
+    __device__ static void st_nt(PT_GLOBAL T* p, R v) { __builtin_nontemporal_store(v, p); }
 };
 template <> struct Store<LBM_STORE_SHIFT_F16> {
     using T = _Float16; using R = float; static constexpr bool shifted = true;
-    __device__ static R ld(const T* p) { return (float)*p; }
-    __device__ static void st(T* p, R v) { *p = (_Float16)v; }
-    __device__ static void st_nt(T* p, R v) { __builtin_nontemporal_store((_Float16)v, p); }
+    __device__ static R ld(const PT_GLOBAL T* p) { return (float)*p; }
+    __device__ static void st(PT_GLOBAL T* p, R v) { *p = (_Float16)v; }
+    __device__ static void st_nt(PT_GLOBAL T* p, R v) { __builtin_nontemporal_store((_Float16)v, p); }
 };
 template <> struct Store<LBM_STORE_SHIFT_BF16> {
     using T = uint16_t; using R = float; static constexpr bool shifted = true;
-    __device__ static R ld(const T* p) { return bf16_to_f32(*p); }
-    __device__ static void st(T* p, R v) { *p = f32_to_bf16_rne(v); }
-    __device__ static void st_nt(T* p, R v) { __builtin_nontemporal_store(f32_to_bf16_rne(v), p); }
+    __device__ static R ld(const PT_GLOBAL T* p) { return bf16_to_f32(*p); }
+    __device__ static void st(PT_GLOBAL T* p, R v) { *p = f32_to_bf16_rne(v); }
+    __device__ static void st_nt(PT_GLOBAL T* p, R v) { __builtin_nontemporal_store(f32_to_bf16_rne(v), p); }
 };
 
 template <class T> struct Pops {
-    T* f[9];
-    T* g[5];
+    PT_GLOBAL T* f[9];
+    PT_GLOBAL T* g[5];
 };
 
 // Lattice constants handed to every kernel (host-filled, FP64).
@@ -296,6 +302,48 @@ __device__ __forceinline__ double min_image_x(double d, int nx) {
 struct PState {   // one particle, FP64
     double x, y, r, ux, uy, th, om, pad;
 };
+
+// Whole-record global-memory accesses of the small structs kept in device
+// arrays (their copy operations do not bind to address-space-qualified
+// objects, so they go field by field; adjacent fields merge into wide
+// accesses).
+__device__ __forceinline__ PState ld_state(const PState* p) {
+    const PT_GLOBAL double* q = (const PT_GLOBAL double*)p;
+    return PState{q[0], q[1], q[2], q[3], q[4], q[5], q[6], q[7]};
+}
+__device__ __forceinline__ void st_state(PState* p, const PState& v) {
+    PT_GLOBAL double* q = (PT_GLOBAL double*)p;
+    q[0] = v.x; q[1] = v.y; q[2] = v.r; q[3] = v.ux; q[4] = v.uy; q[5] = v.th; q[6] = v.om; q[7] = v.pad;
+}
+__device__ __forceinline__ uint2 ld_u2(const uint2* p) {
+    const PT_GLOBAL unsigned* q = (const PT_GLOBAL unsigned*)p;
+    return make_uint2(q[0], q[1]);
+}
+__device__ __forceinline__ void st_u2(uint2* p, uint2 v) {
+    PT_GLOBAL unsigned* q = (PT_GLOBAL unsigned*)p;
+    q[0] = v.x;
+    q[1] = v.y;
+}
+__device__ __forceinline__ int2 ld_i2(const int2* p) {
+    const PT_GLOBAL int* q = (const PT_GLOBAL int*)p;
+    return make_int2(q[0], q[1]);
+}
+__device__ __forceinline__ void st_i2(int2* p, int2 v) {
+    PT_GLOBAL int* q = (PT_GLOBAL int*)p;
+    q[0] = v.x;
+    q[1] = v.y;
+}
+__device__ __forceinline__ double4 ld_d4(const double4* p) {
+    const PT_GLOBAL double* q = (const PT_GLOBAL double*)p;
+    return make_double4(q[0], q[1], q[2], q[3]);
+}
+__device__ __forceinline__ void st_d4(double4* p, double4 v) {
+    PT_GLOBAL double* q = (PT_GLOBAL double*)p;
+    q[0] = v.x;
+    q[1] = v.y;
+    q[2] = v.z;
+    q[3] = v.w;
+}
 
 // Window of a particle (Sec. 3): x from INT(x_c - r) - 1 to INT(x_c + r) + 1
 // and likewise in y, INT read as floor.

@@ -39,8 +39,8 @@ template <int MODE> using ST = typename Store<MODE>::T;
 
 template <int MODE> __host__ __device__ Pops<ST<MODE>> pops_of(void* const (&a)[14]) {
     Pops<ST<MODE>> p;
-    for (int i = 0; i < 9; ++i) p.f[i] = (ST<MODE>*)a[i];
-    for (int i = 0; i < 5; ++i) p.g[i] = (ST<MODE>*)a[9 + i];
+    for (int i = 0; i < 9; ++i) p.f[i] = (PT_GLOBAL ST<MODE>*)a[i];
+    for (int i = 0; i < 5; ++i) p.g[i] = (PT_GLOBAL ST<MODE>*)a[9 + i];
     return p;
 }
 
@@ -57,13 +57,12 @@ template <int MODE> __host__ __device__ Pops<ST<MODE>> pops_of(void* const (&a)[
 // the two owner maps are read only for a node whose value is non-finite, so
 // the check costs no traffic while the run is sound.
 template <int MODE>
-__global__ __launch_bounds__(LAT_BLOCK) void k_stream_collide(Pops<ST<MODE>> A, Pops<ST<MODE>> B,
-                                                              const int32_t* __restrict__ O0,
-                                                              const int32_t* __restrict__ O1, LP lp,
-                                                              unsigned* status) {
+__device__ __forceinline__ void stream_collide_body(const RunStep& rs, unsigned bid) {
     using S = Store<MODE>;
     using R = typename S::R;
-    const size_t n0 = (size_t)blockIdx.x * LAT_BLOCK + threadIdx.x;
+    const LP& lp = rs.lp;
+    const Pops<ST<MODE>> A = pops_of<MODE>(rs.A), B = pops_of<MODE>(rs.B);
+    const size_t n0 = (size_t)bid * LAT_BLOCK + threadIdx.x;
     const int y = (int)(n0 / (unsigned)lp.pitch);
     const int x = (int)(n0 - (size_t)y * lp.pitch);
     if (x >= lp.nx || y >= lp.ny) return;
@@ -73,8 +72,14 @@ __global__ __launch_bounds__(LAT_BLOCK) void k_stream_collide(Pops<ST<MODE>> A, 
     const CC<R> c(lp);
     R rho, ux, uy, T;
     collide<R>(c, s, t, rho, ux, uy, T);
-    if (!(isfinite(rho) && isfinite(T) && isfinite(ux) && isfinite(uy)) && O0[k] == -1 && O1[k] == -1)
-        atomicOr(status, ST_NONFINITE);
+    if (!(isfinite(rho) && isfinite(T) && isfinite(ux) && isfinite(uy)) && gl(rs.Ocur)[k] == -1 &&
+        gl(rs.Onext)[k] == -1) {
+        // one report per wavefront, none once the bit is set: a run that
+        // has gone non-finite must not serialise on its status word
+        const unsigned long long m = __ballot(1);
+        if ((threadIdx.x & 63) == (unsigned)(__ffsll((long long)m) - 1) && !(gl(rs.status)[0] & ST_NONFINITE))
+            atomicOr(rs.status, ST_NONFINITE);
+    }
     store_node<S, true>(B, lp, k, s, t);
 }
 
@@ -220,20 +225,26 @@ __host__ __device__ inline size_t links_wave_lds(int nwin) {
 //      count within the wavefront);
 //  (d) one global atomic per block reserves the block's contiguous range of
 //      the link array; each particle's segment is contiguous, in slot order.
-__global__ __launch_bounds__(256) void k_links(const int32_t* __restrict__ Ocur, int32_t* Onext,
-                                               const PState* __restrict__ Pc,
-                                               const PState* __restrict__ Po, uint2* links, int2* seg,
-                                               unsigned* counter, unsigned* status, LP lp, int ppb) {
+__device__ __forceinline__ void links_body(const RunStep& rs, unsigned bid, int ppb) {
     extern __shared__ uint2 smem[];
     __shared__ unsigned wave_tot[4];
     __shared__ unsigned block_base;
+    const LP& lp = rs.lp;
+    const PT_GLOBAL int32_t* __restrict__ Ocur = gl(rs.Ocur);
+    PT_GLOBAL int32_t* Onext = gl(rs.Onext);
+    const PState* __restrict__ Pc = rs.Pc;
+    const PState* __restrict__ Po = rs.Pold;
+    uint2* links = rs.links;
+    int2* seg = rs.seg;
+    unsigned* counter = rs.counter;
+    unsigned* status = rs.status;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int p = blockIdx.x * ppb + w;
+    const int p = (int)bid * ppb + w;
     const bool have_p = w < ppb && p < lp.np;
     const int nx = lp.nx, pitch = lp.pitch;
 
     if (have_p) {
-        const PState po = Po[p];
+        const PState po = ld_state(Po + p);
         const Win wo = window_of(po);
         if (particle_ok(po, lp) && wo.nxw <= lp.nwin && wo.nyw <= lp.nwin) {
             for (int idx = lane; idx < wo.nxw * wo.nyw; idx += 64) {
@@ -254,7 +265,7 @@ __global__ __launch_bounds__(256) void k_links(const int32_t* __restrict__ Ocur,
     Win wn{};
     bool ok = false;
     if (have_p) {
-        P = Pc[p];
+        P = ld_state(Pc + p);
         wn = window_of(P);
         ok = particle_ok(P, lp) && wn.nxw <= lp.nwin && wn.nyw <= lp.nwin;
         if (!ok && lane == 0) atomicOr(status, ST_BAD_PARTICLE);
@@ -326,8 +337,8 @@ __global__ __launch_bounds__(256) void k_links(const int32_t* __restrict__ Ocur,
         start = 0;
     }
     for (int i = 0; i < w; ++i) start += wave_tot[i];
-    for (unsigned i = lane; i < count; i += 64) links[start + i] = lk[i];
-    if (lane == 0) seg[p] = make_int2((int)start, (int)count);
+    for (unsigned i = lane; i < count; i += 64) st_u2(links + start + i, lk[i]);
+    if (lane == 0) st_i2(seg + p, make_int2((int)start, (int)count));
 }
 
 // The link pass, one thread per link of the compacted array (Sec. 2.3-2.4):
@@ -339,14 +350,15 @@ __global__ __launch_bounds__(256) void k_links(const int32_t* __restrict__ Ocur,
 // f_i^+ (e_i - u_w) - f_ibar (e_ibar - u_w) and its torque about X_c go to
 // contrib[l] in FP64.  All gathers are issued before any arithmetic.
 template <int MODE>
-__global__ __launch_bounds__(256) void k_link_pass(Pops<ST<MODE>> A, const int32_t* __restrict__ Ocur,
-                                                   const PState* __restrict__ Pc, const uint2* __restrict__ links,
-                                                   const unsigned* __restrict__ counter, double4* contrib, LP lp) {
+__device__ __forceinline__ void link_pass_body(const RunStep& rs, unsigned bid) {
     using S = Store<MODE>;
-    const unsigned l = blockIdx.x * blockDim.x + threadIdx.x;
-    if (l >= counter[0]) return;
+    const LP& lp = rs.lp;
+    const unsigned l = bid * 256u + threadIdx.x;
+    if (l >= gl(rs.counter)[0]) return;
+    const Pops<ST<MODE>> A = pops_of<MODE>(rs.A);
+    const PT_GLOBAL int32_t* __restrict__ Ocur = gl(rs.Ocur);
     const int nx = lp.nx, pitch = lp.pitch;
-    const uint2 L = links[l];
+    const uint2 L = ld_u2(rs.links + l);
     const int x = (int)(L.x & 0xffffu), y = (int)(L.x >> 16), i = (int)(L.y & 15u), p = (int)(L.y >> 4);
     const int ib = OPPd(i), ex = EXd(i), ey = EYd(i);
     const int x1 = wrap_x(x - ex, nx), y1 = y - ey;
@@ -355,7 +367,7 @@ __global__ __launch_bounds__(256) void k_link_pass(Pops<ST<MODE>> A, const int32
     const size_t k = (size_t)y * pitch + x;
     const size_t k1 = in1 ? (size_t)y1 * pitch + x1 : k;
     const size_t k2 = in2 ? (size_t)y2 * pitch + x2 : k;
-    const PState P = Pc[p];
+    const PState P = ld_state(rs.Pc + p);
     const int32_t o1 = Ocur[k1], o2 = Ocur[k2];
     const double fi = (double)S::ld(A.f[i] + k), fib = (double)S::ld(A.f[ib] + k);
     const double fi1 = (double)S::ld(A.f[i] + k1), fib1 = (double)S::ld(A.f[ib] + k1);
@@ -387,7 +399,7 @@ __global__ __launch_bounds__(256) void k_link_pass(Pops<ST<MODE>> A, const int32
     const double Fi = fi + w9i * shf, Fb = (double)(typename S::R)fnew + w9i * shf;
     const double dFx = Fi * (ex - uwx) - Fb * (-ex - uwx);
     const double dFy = Fi * (ey - uwy) - Fb * (-ey - uwy);
-    contrib[l] = make_double4(dFx, dFy, rx * dFy - ry * dFx, 0.0);   // Eq. (14), z component
+    st_d4(rs.contrib + l, make_double4(dFx, dFy, rx * dFy - ry * dFx, 0.0));   // Eq. (14), z component
 }
 
 // Spring repulsion of Eq. (15) on particle (xp, yp, rp) from (xq, yq, rq):
@@ -437,21 +449,20 @@ __global__ __launch_bounds__(256) void k_bin_init(const PState* __restrict__ P, 
 //    3 x 3 cells around the particle), summed in ascending partner index (the
 //    order of a plain loop over all partners); walls; net weight;
 //  - Newton-Euler; the new state goes into the cell grid of t_n+1.
-__global__ __launch_bounds__(256) void k_particles(const PState* __restrict__ Pc, PState* Pn,
-                                                   const int2* __restrict__ seg,
-                                                   const double4* __restrict__ contrib, double* Fh,
-                                                   const unsigned* __restrict__ bins_cur,
-                                                   const unsigned* __restrict__ cnt_cur, unsigned* bins_next,
-                                                   unsigned* cnt_next, unsigned* counter, unsigned* status,
-                                                   LP lp) {
+__device__ __forceinline__ void particles_body(const RunStep& rs, unsigned bid) {
+    const LP& lp = rs.lp;
+    const PState* __restrict__ Pc = rs.Pc;
+    const PT_GLOBAL unsigned* __restrict__ bins_cur = gl(rs.bins_cur);
+    const PT_GLOBAL unsigned* __restrict__ cnt_cur = gl(rs.cnt_cur);
+    unsigned* status = rs.status;
     const int lane = threadIdx.x & 63;
-    const int p = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int p = (int)bid * 4 + (threadIdx.x >> 6);
     if (p >= lp.np) return;
-    const PState P = Pc[p];
-    const int2 sg = seg[p];
+    const PState P = ld_state(Pc + p);
+    const int2 sg = ld_i2(rs.seg + p);
     double hx = 0.0, hy = 0.0, hz = 0.0;
     for (int l = lane; l < sg.y; l += 64) {
-        const double4 c = contrib[sg.x + l];
+        const double4 c = ld_d4(rs.contrib + sg.x + l);
         hx += c.x;
         hy += c.y;
         hz += c.z;
@@ -482,7 +493,7 @@ __global__ __launch_bounds__(256) void k_particles(const PState* __restrict__ Pc
                 if ((unsigned)sl < min(cnt_cur[c], (unsigned)BINCAP)) {
                     const int qq = (int)bins_cur[(size_t)c * BINCAP + sl];
                     if (qq != p) {
-                        const PState Q = Pc[qq];
+                        const PState Q = ld_state(Pc + qq);
                         const double dx = min_image_x(P.x - Q.x, lp.nx);
                         const double dy = P.y - Q.y;
                         if (sqrt(dx * dx + dy * dy) - P.r - Q.r <= lp.rep_range) {
@@ -528,9 +539,10 @@ __global__ __launch_bounds__(256) void k_particles(const PState* __restrict__ Pc
     }
     if (lane != 0) return;
     if (p == 0) {
-        counter[1] = counter[0];
-        counter[0] = 0u;
+        rs.counter[1] = rs.counter[0];
+        rs.counter[0] = 0u;
     }
+    PT_GLOBAL double* Fh = gl(rs.Fh);
     Fh[4 * p + 0] = hx;
     Fh[4 * p + 1] = hy;
     Fh[4 * p + 2] = hz;
@@ -552,8 +564,8 @@ __global__ __launch_bounds__(256) void k_particles(const PState* __restrict__ Pc
     else if (N.x >= lp.nx) N.x -= lp.nx;
     const double ddx = min_image_x(N.x - P.x, lp.nx), ddy = N.y - P.y;
     if (!(ddx * ddx + ddy * ddy <= 0.25)) atomicOr(status, ST_OVERSPEED);
-    Pn[p] = N;
-    bin_insert(N, p, bins_next, cnt_next, status, lp);
+    st_state(rs.Pn + p, N);
+    bin_insert(N, p, rs.bins_next, rs.cnt_next, status, lp);
 }
 
 // Owner map of t_n+1, one wavefront per particle, over the
@@ -563,25 +575,30 @@ __global__ __launch_bounds__(256) void k_particles(const PState* __restrict__ Pc
 // candidate (k_refill keeps it if this particle owned it at t_n and no
 // particle covers it at t_n+1).  Also clears the cell-grid counts read this
 // step.
-__global__ __launch_bounds__(256) void k_mask_mark(int32_t* O, const PState* __restrict__ Pp,
-                                                   const PState* __restrict__ Pprev, unsigned* cand,
-                                                   unsigned* ncand, unsigned* cnt_clear, unsigned* status,
-                                                   LP lp) {
-    if (cnt_clear)
-        for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < lp.ncells; c += gridDim.x * blockDim.x)
-            cnt_clear[c] = 0u;
+__device__ __forceinline__ void mask_body(const RunStep& rs, unsigned bid) {
+    const LP& lp = rs.lp;
+    int32_t* O = rs.Onext;
+    const PState* __restrict__ Pp = rs.Pn;
+    const PState* __restrict__ Pprev = rs.Pc;
+    PT_GLOBAL unsigned* cand = gl(rs.cand);
+    PT_GLOBAL unsigned* ncand = gl(rs.ncand);
+    unsigned* status = rs.status;
+    if (rs.cnt_cur) {
+        const int nthreads = (int)(((unsigned)lp.np + 3u) / 4u * 256u);
+        for (int c = (int)bid * 256 + threadIdx.x; c < lp.ncells; c += nthreads) gl(rs.cnt_cur)[c] = 0u;
+    }
     const int lane = threadIdx.x & 63;
-    const int p = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int p = (int)bid * 4 + (threadIdx.x >> 6);
     if (p >= lp.np) return;
-    const PState P = Pp[p];
+    const PState P = ld_state(Pp + p);
     if (!particle_ok(P, lp)) return;
     Win w = window_of(P);
     if (w.nxw > lp.nwin || w.nyw > lp.nwin) return;
     int xa = w.x0, xb = w.x0 + w.nxw, ya = w.y0, yb = w.y0 + w.nyw;
     PState Q{};
-    const bool with_prev = Pprev != nullptr && particle_ok(Pprev[p], lp);
+    const bool with_prev = Pprev != nullptr && particle_ok(ld_state(Pprev + p), lp);
     if (with_prev) {
-        Q = Pprev[p];
+        Q = ld_state(Pprev + p);
         Win v = window_of(Q);
         if (v.x0 - w.x0 > lp.nx / 2) v.x0 -= lp.nx;
         else if (w.x0 - v.x0 > lp.nx / 2) v.x0 += lp.nx;
@@ -641,8 +658,9 @@ __global__ __launch_bounds__(256) void k_mask_mark(int32_t* O, const PState* __r
 // that u = u_w; g = g^eq(T_w, u_w) (Eq. (17)); then collided into B.  The
 // node is skipped unless p owned it at t_n and it is fluid at t_n+1.
 template <int MODE>
-__device__ void refill_node(const Pops<ST<MODE>>& A, const Pops<ST<MODE>>& B, const int32_t* Ocur,
-                            const int32_t* Onext, const PState& P, int p, int x, int y, const LP& lp) {
+__device__ void refill_node(const Pops<ST<MODE>>& A, const Pops<ST<MODE>>& B, const PT_GLOBAL int32_t* Ocur,
+                            const PT_GLOBAL int32_t* Onext, const PState& P, int p, int x, int y,
+                            const LP& lp) {
     using S = Store<MODE>;
     using R = typename S::R;
     const size_t k0 = (size_t)y * lp.pitch + x;
@@ -709,22 +727,76 @@ __device__ void refill_node(const Pops<ST<MODE>>& A, const Pops<ST<MODE>>& B, co
 // Refill of particle p's newborn nodes, one wavefront per particle and one
 // lane per candidate from k_mask_mark.
 template <int MODE>
-__global__ __launch_bounds__(256) void k_refill(Pops<ST<MODE>> A, Pops<ST<MODE>> B,
-                                                const int32_t* __restrict__ Ocur,
-                                                const int32_t* __restrict__ Onext,
-                                                const PState* __restrict__ Pn, const unsigned* __restrict__ cand,
-                                                const unsigned* __restrict__ ncand, LP lp) {
+__device__ __forceinline__ void refill_body(const RunStep& rs, unsigned bid) {
+    const LP& lp = rs.lp;
     const int lane = threadIdx.x & 63;
-    const int p = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int p = (int)bid * 4 + (threadIdx.x >> 6);
     if (p >= lp.np) return;
     const unsigned ccap = (unsigned)(4 * lp.nwin);
-    const unsigned n = min(ncand[p], ccap);
+    const unsigned n = min(gl(rs.ncand)[p], ccap);
     if (n == 0) return;
-    const PState P1 = Pn[p];
+    const Pops<ST<MODE>> A = pops_of<MODE>(rs.A), B = pops_of<MODE>(rs.B);
+    const PState P1 = ld_state(rs.Pn + p);
     for (unsigned i = lane; i < n; i += 64) {
-        const unsigned code = cand[(size_t)p * ccap + i];
-        refill_node<MODE>(A, B, Ocur, Onext, P1, p, (int)(code & 0xffffu), (int)(code >> 16), lp);
+        const unsigned code = gl(rs.cand)[(size_t)p * ccap + i];
+        refill_node<MODE>(A, B, gl(rs.Ocur), gl(rs.Onext), P1, p, (int)(code & 0xffffu), (int)(code >> 16), lp);
     }
+}
+
+// ------------------------------------------------------- step kernels ----
+// Each step kernel exists twice: for one run (its RunStep passed by value,
+// read from the kernel-argument segment) and batched over several runs (one
+// grid; block b works on block bmap[b].y of run bmap[b].x, whose RunStep is
+// tab[bmap[b].x]).  Both call the same body, so a run computes the same bits
+// alone and in a batch.
+
+template <int MODE>
+__global__ __launch_bounds__(LAT_BLOCK) void k_stream_collide(RunStep rs) {
+    stream_collide_body<MODE>(rs, blockIdx.x);
+}
+template <int MODE>
+__global__ __launch_bounds__(LAT_BLOCK) void k_stream_collide_b(const RunStep* __restrict__ tab,
+                                                                const uint2* __restrict__ bmap) {
+    const uint2 m = bmap[blockIdx.x];
+    stream_collide_body<MODE>(tab[m.x], m.y);
+}
+
+__global__ __launch_bounds__(256) void k_links(RunStep rs, int ppb) { links_body(rs, blockIdx.x, ppb); }
+__global__ __launch_bounds__(256) void k_links_b(const RunStep* __restrict__ tab, const uint2* __restrict__ bmap,
+                                                 int ppb) {
+    const uint2 m = bmap[blockIdx.x];
+    links_body(tab[m.x], m.y, ppb);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_link_pass(RunStep rs) { link_pass_body<MODE>(rs, blockIdx.x); }
+template <int MODE>
+__global__ __launch_bounds__(256) void k_link_pass_b(const RunStep* __restrict__ tab,
+                                                     const uint2* __restrict__ bmap) {
+    const uint2 m = bmap[blockIdx.x];
+    link_pass_body<MODE>(tab[m.x], m.y);
+}
+
+__global__ __launch_bounds__(256) void k_particles(RunStep rs) { particles_body(rs, blockIdx.x); }
+__global__ __launch_bounds__(256) void k_particles_b(const RunStep* __restrict__ tab,
+                                                     const uint2* __restrict__ bmap) {
+    const uint2 m = bmap[blockIdx.x];
+    particles_body(tab[m.x], m.y);
+}
+
+__global__ __launch_bounds__(256) void k_mask_mark(RunStep rs) { mask_body(rs, blockIdx.x); }
+__global__ __launch_bounds__(256) void k_mask_mark_b(const RunStep* __restrict__ tab,
+                                                     const uint2* __restrict__ bmap) {
+    const uint2 m = bmap[blockIdx.x];
+    mask_body(tab[m.x], m.y);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_refill(RunStep rs) { refill_body<MODE>(rs, blockIdx.x); }
+template <int MODE>
+__global__ __launch_bounds__(256) void k_refill_b(const RunStep* __restrict__ tab, const uint2* __restrict__ bmap) {
+    const uint2 m = bmap[blockIdx.x];
+    refill_body<MODE>(tab[m.x], m.y);
 }
 
 __global__ void k_link_q(const PState* __restrict__ Pc, const uint2* __restrict__ links, int n, int32_t* node,
@@ -745,7 +817,6 @@ __global__ void k_link_q(const PState* __restrict__ Pc, const uint2* __restrict_
 // -------------------------------------------------------------- launchers ----
 
 static dim3 lattice_grid(const LP& lp) { return dim3((lp.nx + LAT_BLOCK - 1) / LAT_BLOCK, lp.ny); }
-static unsigned wave_blocks(int np) { return (unsigned)((np + 3) / 4); }
 
 #define PTLBM_DISPATCH(mode, CALL)                                      \
     switch (mode) {                                                     \
@@ -756,14 +827,6 @@ static unsigned wave_blocks(int np) { return (unsigned)((np + 3) / 4); }
         case LBM_STORE_SHIFT_BF16: { constexpr int M = LBM_STORE_SHIFT_BF16; CALL; } break; \
         default: return hipErrorInvalidValue;                           \
     }
-
-hipError_t launch_stream_collide(const DevState& d, int cur, hipStream_t st) {
-    const unsigned blocks = (unsigned)(((size_t)d.lp.pitch * d.lp.ny + LAT_BLOCK - 1) / LAT_BLOCK);
-    PTLBM_DISPATCH(d.mode, (k_stream_collide<M><<<blocks, LAT_BLOCK, 0, st>>>(
-                               pops_of<M>(d.S[cur]), pops_of<M>(d.S[1 - cur]), d.O[0], d.O[1], d.lp,
-                               d.status)));
-    return hipGetLastError();
-}
 
 hipError_t launch_init(const DevState& d, int cur, const void* rho, const void* ux, const void* uy,
                        const void* T, bool f64, double rho_u, double T_u, hipStream_t st) {
@@ -796,30 +859,62 @@ int links_particles_per_block(int nwin) {
     return ppb < 1 ? 1 : (ppb > 4 ? 4 : ppb);
 }
 
-hipError_t launch_links(const DevState& d, int cur, int ring, hipStream_t st) {
-    if (d.lp.np == 0) return hipSuccess;
-    const int ppb = links_particles_per_block(d.lp.nwin);
-    const unsigned blocks = (unsigned)((d.lp.np + ppb - 1) / ppb);
-    const size_t lds = (size_t)ppb * links_wave_lds(d.lp.nwin);
-    k_links<<<blocks, 64 * ppb, lds, st>>>(d.O[cur], d.O[1 - cur], d.P[ring],
-                                           d.P[ring_old(ring)], d.links, d.seg, d.counter, d.status, d.lp, ppb);
+size_t links_block_lds(int nwin, int ppb) { return (size_t)ppb * links_wave_lds(nwin); }
+
+unsigned run_blocks(int c, const LP& lp, int ppb) {
+    switch (c) {
+        case GC_LINKS: return lp.np > 0 ? (unsigned)((lp.np + ppb - 1) / ppb) : 0u;
+        case GC_PASS:   // a particle has at most 12 nwin - 12 links
+            return lp.np > 0 ? (unsigned)(((size_t)lp.np * (12 * lp.nwin - 12) + 255) / 256) : 0u;
+        case GC_WAVE: return (unsigned)((lp.np + 3) / 4);
+        default: return (unsigned)(((size_t)lp.pitch * lp.ny + LAT_BLOCK - 1) / LAT_BLOCK);
+    }
+}
+
+hipError_t launch_step(int k, const RunStep& R, int mode, hipStream_t st) {
+    const int ppb = links_particles_per_block(R.lp.nwin);
+    const unsigned nb = run_blocks(grid_class(k), R.lp, ppb);
+    if (nb == 0) return hipSuccess;
+    switch (k) {
+        case SK_LINKS:
+            k_links<<<nb, 64 * ppb, links_block_lds(R.lp.nwin, ppb), st>>>(R, ppb);
+            break;
+        case SK_PASS: PTLBM_DISPATCH(mode, (k_link_pass<M><<<nb, 256, 0, st>>>(R))); break;
+        case SK_PARTICLES: k_particles<<<nb, 256, 0, st>>>(R); break;
+        case SK_MASK: k_mask_mark<<<nb, 256, 0, st>>>(R); break;
+        case SK_LATTICE: PTLBM_DISPATCH(mode, (k_stream_collide<M><<<nb, LAT_BLOCK, 0, st>>>(R))); break;
+        case SK_REFILL: PTLBM_DISPATCH(mode, (k_refill<M><<<nb, 256, 0, st>>>(R))); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_link_pass(const DevState& d, int cur, int ring, hipStream_t st) {
-    if (d.lp.np == 0 || d.lp.link_cap == 0) return hipSuccess;
-    const unsigned blocks = (unsigned)((d.lp.link_cap + 255) / 256);
-    PTLBM_DISPATCH(d.mode, (k_link_pass<M><<<blocks, 256, 0, st>>>(pops_of<M>(d.S[cur]), d.O[cur], d.P[ring],
-                                                                  d.links, d.counter, d.contrib, d.lp)));
+hipError_t launch_step_batch(int k, const BatchLaunch& b, hipStream_t st) {
+    const int c = grid_class(k);
+    const unsigned nb = b.nblk[c];
+    if (nb == 0) return hipSuccess;
+    const uint2* bm = b.bmap[c];
+    switch (k) {
+        case SK_LINKS: k_links_b<<<nb, 64 * b.ppb, b.lds, st>>>(b.tab, bm, b.ppb); break;
+        case SK_PASS: PTLBM_DISPATCH(b.mode, (k_link_pass_b<M><<<nb, 256, 0, st>>>(b.tab, bm))); break;
+        case SK_PARTICLES: k_particles_b<<<nb, 256, 0, st>>>(b.tab, bm); break;
+        case SK_MASK: k_mask_mark_b<<<nb, 256, 0, st>>>(b.tab, bm); break;
+        case SK_LATTICE:
+            PTLBM_DISPATCH(b.mode, (k_stream_collide_b<M><<<nb, LAT_BLOCK, 0, st>>>(b.tab, bm)));
+            break;
+        case SK_REFILL: PTLBM_DISPATCH(b.mode, (k_refill_b<M><<<nb, 256, 0, st>>>(b.tab, bm))); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_particles(const DevState& d, int ring, int bin_parity, hipStream_t st) {
-    if (d.lp.np == 0) return hipSuccess;
-    k_particles<<<wave_blocks(d.lp.np), 256, 0, st>>>(d.P[ring], d.P[ring_next(ring)], d.seg, d.contrib, d.Fh,
-                                                       d.bins[bin_parity], d.bcnt[bin_parity],
-                                                       d.bins[1 - bin_parity], d.bcnt[1 - bin_parity],
-                                                       d.counter, d.status, d.lp);
+hipError_t launch_mask_setup(const RunStep& R, hipStream_t st) {
+    RunStep S = R;
+    S.Pc = nullptr;       // no previous time level: no newborn candidates
+    S.cnt_cur = nullptr;  // no cell counts to clear
+    const unsigned nb = run_blocks(GC_WAVE, S.lp, 1);
+    if (nb == 0) return hipSuccess;
+    k_mask_mark<<<nb, 256, 0, st>>>(S);
     return hipGetLastError();
 }
 
@@ -827,22 +922,6 @@ hipError_t launch_bin_init(const DevState& d, const PState* P, int bin_parity, h
     if (d.lp.np == 0) return hipSuccess;
     k_bin_init<<<(d.lp.np + 255) / 256, 256, 0, st>>>(P, d.bins[bin_parity], d.bcnt[bin_parity], d.status,
                                                        d.lp);
-    return hipGetLastError();
-}
-
-hipError_t launch_mask_mark(const DevState& d, int owner_idx, const PState* P, const PState* Pprev,
-                            unsigned* cnt_clear, hipStream_t st) {
-    if (d.lp.np == 0) return hipSuccess;
-    k_mask_mark<<<wave_blocks(d.lp.np), 256, 0, st>>>(d.O[owner_idx], P, Pprev, d.cand,
-                                                       d.ncand, cnt_clear, d.status, d.lp);
-    return hipGetLastError();
-}
-
-hipError_t launch_refill(const DevState& d, int cur, int ring, hipStream_t st) {
-    if (d.lp.np == 0) return hipSuccess;
-    PTLBM_DISPATCH(d.mode, (k_refill<M><<<wave_blocks(d.lp.np), 256, 0, st>>>(
-                               pops_of<M>(d.S[cur]), pops_of<M>(d.S[1 - cur]), d.O[cur], d.O[1 - cur],
-                               d.P[ring_next(ring)], d.cand, d.ncand, d.lp)));
     return hipGetLastError();
 }
 

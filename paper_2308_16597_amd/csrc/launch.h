@@ -28,6 +28,53 @@ struct DevState {
     unsigned* ncand;             // candidates per particle
 };
 
+// Everything the step kernels need of one run at one step: its lattice
+// constants and its buffers resolved for the time level (cur), the particle
+// ring slot and the cell-grid parity of that step.  Passed by value to a
+// single-run launch; an array of them (one per run) drives a batched launch.
+struct RunStep {
+    LP lp;
+    void* A[14];                 // post-collision state of t_n
+    void* B[14];                 // state of t_n+1 being written
+    int32_t* Ocur;               // owner map of t_n
+    int32_t* Onext;              // owner map of t_n+1 (holds t_n-1 until cleared)
+    const PState* Pold;          // particles at t_n-1
+    const PState* Pc;            // particles at t_n
+    PState* Pn;                  // particles at t_n+1
+    double* Fh;
+    double4* contrib;
+    uint2* links;
+    int2* seg;
+    unsigned* counter;
+    unsigned* status;
+    const unsigned* bins_cur;
+    unsigned* cnt_cur;           // read by k_particles, cleared by k_mask_mark
+    unsigned* bins_next;
+    unsigned* cnt_next;
+    unsigned* cand;
+    unsigned* ncand;
+};
+
+// The six step kernels, in launch order.
+enum StepKernel { SK_LINKS = 0, SK_PASS, SK_PARTICLES, SK_MASK, SK_LATTICE, SK_REFILL, SK_COUNT };
+// Grid classes of the step kernels: how many blocks one run needs.
+enum GridClass { GC_LINKS = 0, GC_PASS, GC_WAVE, GC_LAT, GC_COUNT };
+inline GridClass grid_class(int k) {
+    return k == SK_LINKS ? GC_LINKS : k == SK_PASS ? GC_PASS : k == SK_LATTICE ? GC_LAT : GC_WAVE;
+}
+
+// A batched launch: one grid over several runs.  bmap[c][b] = {run, block
+// of that run} for block b of a class-c kernel; tab holds one RunStep per
+// run for the step being launched.
+struct BatchLaunch {
+    const RunStep* tab;
+    const uint2* bmap[GC_COUNT];
+    unsigned nblk[GC_COUNT];
+    int ppb;                     // particles per block of the link collection
+    size_t lds;                  // its dynamic LDS bytes
+    int mode;
+};
+
 enum StatusBits : unsigned {
     ST_NONFINITE = 1u,      // non-finite macroscopic value
     ST_OVERSPEED = 2u,      // particle moved more than 0.5 per step
@@ -37,17 +84,21 @@ enum StatusBits : unsigned {
     ST_CAND_OVERFLOW = 32u, // more newborn nodes for one particle than its candidate list holds
 };
 
-hipError_t launch_stream_collide(const DevState& d, int cur, hipStream_t st);
+// Blocks one run needs for a kernel of class c (ppb: particles per block of
+// the link collection).
+unsigned run_blocks(int c, const LP& lp, int ppb);
+int links_particles_per_block(int nwin);
+size_t links_block_lds(int nwin, int ppb);
+
+hipError_t launch_step(int k, const RunStep& R, int mode, hipStream_t st);
+hipError_t launch_step_batch(int k, const BatchLaunch& b, hipStream_t st);
+// Owner map of R.Pn into R.Onext with no previous time level (set-up).
+hipError_t launch_mask_setup(const RunStep& R, hipStream_t st);
+
 hipError_t launch_init(const DevState& d, int cur, const void* rho, const void* ux, const void* uy,
                        const void* T, bool fields_f64, double rho_u, double T_u, hipStream_t st);
 hipError_t launch_macros(const DevState& d, int cur, void* out, hipStream_t st);
-hipError_t launch_links(const DevState& d, int cur, int ring, hipStream_t st);
-hipError_t launch_link_pass(const DevState& d, int cur, int ring, hipStream_t st);
-hipError_t launch_particles(const DevState& d, int ring, int bin_parity, hipStream_t st);
 hipError_t launch_bin_init(const DevState& d, const PState* P, int bin_parity, hipStream_t st);
-hipError_t launch_mask_mark(const DevState& d, int owner_idx, const PState* P, const PState* Pprev,
-                            unsigned* cnt_clear, hipStream_t st);
-hipError_t launch_refill(const DevState& d, int cur, int ring, hipStream_t st);
 hipError_t launch_link_q(const DevState& d, int ring, int nlinks, int32_t* node, int32_t* dir,
                          int32_t* part, double* q, hipStream_t st);
 

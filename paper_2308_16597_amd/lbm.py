@@ -71,6 +71,7 @@ def _load():
     L.lbm_set_particles.argtypes = [vp, _i, vp]
     L.lbm_set_equilibrium.argtypes = [vp, vp, vp, vp, vp]
     L.lbm_step.argtypes = [vp, _i]
+    L.lbm_step_many.argtypes = [vp, _i, vp, vp]
     L.lbm_sync.argtypes = [vp]
     L.lbm_read_fields.argtypes = [vp, vp, vp, vp, vp, vp]
     L.lbm_read_particles.argtypes = [vp, vp, P(_i)]
@@ -170,6 +171,19 @@ def lbm_step(h, n):
     _check(_lib.lbm_step(h, int(n)), h)
 
 
+def lbm_step_many(handles, nsteps, stream=None):
+    """Advance handles[i] by nsteps[i] steps in batched launches."""
+    n = len(handles)
+    if n == 0:
+        return
+    hs = (ctypes.c_void_p * n)(*[h.value if isinstance(h, ctypes.c_void_p) else h for h in handles])
+    ns = np.ascontiguousarray(nsteps, dtype=np.int32)
+    if ns.shape != (n,):
+        raise ValueError("one step count per handle")
+    rc = _lib.lbm_step_many(ctypes.cast(hs, ctypes.c_void_p), n, _ptr(ns), stream)
+    _check(rc, handles[0])
+
+
 def lbm_sync(h):
     _check(_lib.lbm_sync(h), h)
 
@@ -216,6 +230,11 @@ def lbm_stats(h):
 
 # --- convenience wrapper -----------------------------------------------------
 
+def step_many(sims, nsteps, stream=None):
+    """Advance sims[i] by nsteps[i] steps together (batched launches)."""
+    lbm_step_many([s.handle for s in sims], nsteps, stream)
+
+
 class Sim:
     """One simulation on the GPU.
 
@@ -224,7 +243,7 @@ class Sim:
     allocates with hipMalloc and creates its own stream.
     """
 
-    def __init__(self, params=None, torch_memory=True, **overrides):
+    def __init__(self, params=None, torch_memory=True, arena=None, stream=None, **overrides):
         self.params = params if params is not None else lbm_params_default(**overrides)
         if params is not None and overrides:
             for k, v in overrides.items():
@@ -232,7 +251,11 @@ class Sim:
         self.nx, self.ny = self.params.nx, self.params.ny
         self._arena = None
         self._h = None
-        if torch_memory:
+        if arena is not None:
+            # a caller-owned slice (device pointer, bytes) of a larger buffer
+            self._h = lbm_create_in_arena(self.params, int(arena[0]), int(arena[1]),
+                                          ctypes.c_void_p(stream) if stream else None)
+        elif torch_memory:
             import torch
             nbytes = lbm_bytes_required(self.params)
             if nbytes == 0:
@@ -268,6 +291,10 @@ class Sim:
 
     def step(self, n=1):
         lbm_step(self._h, n)
+
+    @property
+    def handle(self):
+        return self._h
 
     def sync(self):
         lbm_sync(self._h)

@@ -64,3 +64,12 @@ def test_rsa_seed_reports_infeasible_packing():
     with pytest.raises(lbm.LbmError) as e:
         lbm.lbm_rsa_seed(32, 32, 40, 10.0, 1.0, 1)
     assert e.value.rc == lbm.LBM_ESEED
+
+
+def test_step_many_rejects_empty_run_lists_on_the_host():
+    f = lbm._lib.lbm_step_many
+    assert f(None, 0, None, None) == lbm.LBM_EINVAL
+    hs = (ctypes.c_void_p * 2)(None, None)
+    ns = np.zeros(2, dtype=np.int32)
+    assert f(ctypes.cast(hs, ctypes.c_void_p), 2, ns.ctypes.data, None) == lbm.LBM_EINVAL
+    assert "null handle" in lbm.lbm_last_error(None)
