@@ -110,14 +110,16 @@ typedef struct {
     double max_diameter;   /* largest particle diameter the buffers are sized for */
 } lbm_params;
 
-/* Phases reported by lbm_time_phases, in launch order. */
+/* Phases reported by lbm_time_phases, in the order of a sequential step.
+ * The links a step uses are collected at the end of the step before it (and
+ * by lbm_set_particles for the first). */
 enum {
-    LBM_PHASE_COLLECT = 0,   /* link collection into the compacted index array */
-    LBM_PHASE_LINKS = 1,     /* bounce-back, thermal wall, momentum exchange per link */
-    LBM_PHASE_PARTICLES = 2, /* per-particle sums, repulsion, net weight, Newton-Euler */
-    LBM_PHASE_MASK = 3,      /* solid map at the new positions */
-    LBM_PHASE_LATTICE = 4,   /* fused stream + collide over the lattice */
-    LBM_PHASE_REFILL = 5,    /* refilling of newborn nodes */
+    LBM_PHASE_LINKS = 0,     /* bounce-back, thermal wall, momentum exchange per link */
+    LBM_PHASE_PARTICLES = 1, /* per-particle sums, repulsion, net weight, Newton-Euler */
+    LBM_PHASE_MASK = 2,      /* solid map at the new positions */
+    LBM_PHASE_LATTICE = 3,   /* fused stream + collide over the lattice */
+    LBM_PHASE_REFILL = 4,    /* refilling of newborn nodes */
+    LBM_PHASE_COLLECT = 5,   /* link collection of the next step into the compacted array */
     LBM_NPHASES = 6
 };
 
@@ -177,7 +179,10 @@ int lbm_set_particles(lbm_handle h, int32_t n, const double* rows7);
 int lbm_set_equilibrium(lbm_handle h, const double* rho, const double* ux, const double* uy,
                         const double* T);
 
-/* Enqueue nsteps steps on the handle's stream and return. */
+/* Enqueue nsteps steps on the handle's stream and return.  Within a step,
+ * the particle update, the owner map of t_n+1 and the link collection of
+ * t_n+1 run on a second stream of the library's, concurrently with the
+ * lattice update; each step ends joined on the handle's stream. */
 int lbm_step(lbm_handle h, int32_t nsteps);
 
 /* Advance count runs together, run i by nsteps[i] steps, for serving many
@@ -213,17 +218,22 @@ int lbm_read_fields(lbm_handle h, double* rho, double* ux, double* uy, double* T
  * rows10 may be NULL to query *n only. */
 int lbm_read_particles(lbm_handle h, double* rows10, int32_t* n);
 
-/* Collect the fluid-particle links of the current state (Sec. 3) and copy
- * them out: node index j*nx + i of the fluid node, direction 1..8, particle,
+/* The fluid-particle links of the current state (Sec. 3), as the library
+ * collected them for the next step, copied out: node index j*nx + i of the fluid node, direction 1..8, particle,
  * and the link fraction q of Sec. 2.3.  The order of the links is
  * unspecified.  With every output NULL only *n_out is set; otherwise cap
  * must be >= the number of links. */
 int lbm_read_links(lbm_handle h, int32_t* node, int32_t* dir, int32_t* particle, double* q,
                    int64_t cap, int64_t* n_out);
 
-/* Run nsteps steps with HIP events around each phase and return the mean
- * device time per step of each phase in ms_out[LBM_NPHASES] and, in
- * ms_out[LBM_NPHASES], the mean time of a whole step.  Waits. */
+/* Timing: run nsteps steps with the phases one after another and HIP
+ * events around each, then nsteps steps as lbm_step runs them (particle
+ * phases concurrent with the lattice phase) with events around the lattice
+ * kernel.  ms_out[LBM_NPHASES + 3] receives the mean device time per step
+ * of each phase in sequence (ms_out[0 .. LBM_NPHASES-1]), of a sequential
+ * step (ms_out[LBM_NPHASES]), of the lattice kernel within overlapped steps
+ * (ms_out[LBM_NPHASES+1]) and of an overlapped step (ms_out[LBM_NPHASES+2]).
+ * Advances the run by 2 nsteps steps.  Waits. */
 int lbm_time_phases(lbm_handle h, int32_t nsteps, double* ms_out);
 
 /* Counters: out[0] steps done, out[1] links of the last step, out[2]

@@ -217,6 +217,15 @@ int create_common(const lbm_params* p, void* dev_ptr, size_t bytes, void* stream
         }
         h->own_stream = true;
     }
+    {
+        hipError_t e = hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_side, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            lbm_destroy(h);
+            return fail(nullptr, LBM_EDEVICE, "side stream / events: %s", hipGetErrorString(e));
+        }
+    }
     DevState& d = h->d;
     d.mode = p->storage;
     const Layout& L = h->L;
@@ -297,6 +306,9 @@ RunStep make_runstep(const lbm_sim* h, int c, int r, int bp) {
 }
 
 RunStep current_runstep(const lbm_sim* h) { return make_runstep(h, h->cur, h->ring, h->bin_parity); }
+RunStep next_runstep(const lbm_sim* h) {
+    return make_runstep(h, 1 - h->cur, ring_next(h->ring), 1 - h->bin_parity);
+}
 
 void advance_state(lbm_sim* h) {
     h->cur = 1 - h->cur;
@@ -309,14 +321,39 @@ void advance_state(lbm_sim* h) {
 
 namespace {
 
-int enqueue_step(lbm_sim* h, hipEvent_t* ev) {
+// One step.  With timing events: the six kernels in sequence on the
+// handle's stream, an event before each.  Otherwise the particle kernels
+// (update, owner map of t_n+1, links of t_n+1) run on the side stream while
+// the lattice kernel runs on the main one, with one wait on each side (an
+// event operation costs the main stream a few microseconds of idle time):
+//   main: link pass -> [fork] -> lattice -> wait(side) -> refill
+//   side: wait(fork) -> particles -> mask -> links of t_n+1 -> [side]
+int enqueue_step(lbm_sim* h, hipEvent_t* ev, hipEvent_t* lat = nullptr) {
     hipStream_t st = h->stream;
     const RunStep R = current_runstep(h);
-    for (int k = 0; k < SK_COUNT; ++k) {
-        if (ev) HIPCHK(h, hipEventRecord(ev[k], st));
-        HIPCHK(h, launch_step(k, R, h->d.mode, st));
+    const RunStep Rn = next_runstep(h);
+    const int mode = h->d.mode;
+    if (ev || h->np == 0) {
+        for (int k = 0; k < SK_COUNT; ++k) {
+            if (ev) HIPCHK(h, hipEventRecord(ev[k], st));
+            HIPCHK(h, launch_step(k, k == SK_COLLECT ? Rn : R, mode, st));
+        }
+        if (ev) HIPCHK(h, hipEventRecord(ev[SK_COUNT], st));
+    } else {
+        hipStream_t sd = h->side;
+        HIPCHK(h, launch_step(SK_PASS, R, mode, st));
+        HIPCHK(h, hipEventRecord(h->ev_fork, st));
+        HIPCHK(h, hipStreamWaitEvent(sd, h->ev_fork, 0));
+        HIPCHK(h, launch_step(SK_PARTICLES, R, mode, sd));
+        HIPCHK(h, launch_step(SK_MASK, R, mode, sd));
+        HIPCHK(h, launch_step(SK_COLLECT, Rn, mode, sd));
+        HIPCHK(h, hipEventRecord(h->ev_side, sd));
+        if (lat) HIPCHK(h, hipEventRecord(lat[0], st));
+        HIPCHK(h, launch_step(SK_LATTICE, R, mode, st));
+        if (lat) HIPCHK(h, hipEventRecord(lat[1], st));
+        HIPCHK(h, hipStreamWaitEvent(st, h->ev_side, 0));
+        HIPCHK(h, launch_step(SK_REFILL, R, mode, st));
     }
-    if (ev) HIPCHK(h, hipEventRecord(ev[SK_COUNT], st));
     advance_state(h);
     return LBM_OK;
 }
@@ -371,7 +408,11 @@ void lbm_destroy(lbm_handle h) {
     if (!h) return;
     forget_batches(h);
     if (h->stream) (void)hipStreamSynchronize(h->stream);
+    if (h->side) (void)hipStreamSynchronize(h->side);
     if (h->own_mem && h->base) (void)hipFree(h->base);
+    for (hipEvent_t e : {h->ev_fork, h->ev_side})
+        if (e) (void)hipEventDestroy(e);
+    if (h->side) (void)hipStreamDestroy(h->side);
     if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
     delete h;
 }
@@ -500,6 +541,7 @@ int lbm_set_particles(lbm_handle h, int32_t n, const double* rows7) {
         // owner map of t_0 into O[0] from the particles in ring slot 0
         HIPCHK(h, launch_mask_setup(make_runstep(h, 1, 2, 0), st));
         HIPCHK(h, launch_bin_init(d, d.P[0], 0, st));
+        HIPCHK(h, launch_step(SK_COLLECT, current_runstep(h), d.mode, st));   // links of t_0
     }
     HIPCHK(h, launch_init(d, 0, nullptr, nullptr, nullptr, nullptr, true, h->p.rho0, h->p.T_fluid0, st));
     HIPCHK(h, hipStreamSynchronize(st));
@@ -608,17 +650,11 @@ int lbm_read_links(lbm_handle h, int32_t* node, int32_t* dir, int32_t* particle,
     if (n_out) *n_out = 0;
     if (h->np == 0) return LBM_OK;
     DevState& d = h->d;
-    // The collection reads the owner map of the current time level; its
-    // clearing of the stale map is idempotent and the next step repeats it.
-    unsigned saved[2];
-    HIPCHK(h, hipMemcpyAsync(saved, d.counter, sizeof saved, hipMemcpyDeviceToHost, h->stream));
-    HIPCHK(h, hipMemsetAsync(d.counter, 0, sizeof(unsigned), h->stream));
-    HIPCHK(h, launch_step(SK_LINKS, current_runstep(h), d.mode, h->stream));
+    // the links of the current state were collected at the end of the last
+    // step (or by lbm_set_particles); counter[0] holds their number
     unsigned nl = 0;
     HIPCHK(h, hipMemcpyAsync(&nl, d.counter, sizeof nl, hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
-    rc = check_status(h);
-    if (rc != LBM_OK) return rc;
     if (n_out) *n_out = nl;
     char* ls = h->base + h->L.off_lscratch;
     int32_t* dn = (int32_t*)ls;
@@ -633,7 +669,6 @@ int lbm_read_links(lbm_handle h, int32_t* node, int32_t* dir, int32_t* particle,
         if (particle) HIPCHK(h, hipMemcpyAsync(particle, dp, nl * 4, hipMemcpyDeviceToHost, h->stream));
         if (q) HIPCHK(h, hipMemcpyAsync(q, dq, nl * 8, hipMemcpyDeviceToHost, h->stream));
     }
-    HIPCHK(h, hipMemcpyAsync(d.counter, saved, sizeof saved, hipMemcpyHostToDevice, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
     return LBM_OK;
 }
@@ -664,6 +699,29 @@ int lbm_time_phases(lbm_handle h, int32_t nsteps, double* ms_out) {
     for (auto& e : ev) (void)hipEventDestroy(e);
     if (rc != LBM_OK) return rc;
     for (int ph = 0; ph <= LBM_NPHASES; ++ph) ms_out[ph] = acc[ph] / nsteps;
+    // the same number of steps as lbm_step runs them (particle kernels
+    // concurrent with the lattice kernel), the lattice kernel bracketed
+    std::vector<hipEvent_t> le(2 * (size_t)nsteps + 2, nullptr);
+    for (auto& e : le)
+        if (rc == LBM_OK && hipEventCreate(&e) != hipSuccess) rc = fail(h, LBM_EDEVICE, "hipEventCreate");
+    if (rc == LBM_OK && hipEventRecord(le[0], h->stream) != hipSuccess) rc = fail(h, LBM_EDEVICE, "hipEventRecord");
+    for (int32_t s = 0; s < nsteps && rc == LBM_OK; ++s) rc = enqueue_step(h, nullptr, &le[2 + 2 * (size_t)s]);
+    if (rc == LBM_OK && hipEventRecord(le[1], h->stream) != hipSuccess) rc = fail(h, LBM_EDEVICE, "hipEventRecord");
+    if (rc == LBM_OK && hipEventSynchronize(le[1]) != hipSuccess) rc = fail(h, LBM_EDEVICE, "hipEventSynchronize");
+    if (rc == LBM_OK) {
+        double lat = 0.0;
+        float ms = 0.f;
+        for (int32_t s = 0; s < nsteps; ++s) {
+            (void)hipEventElapsedTime(&ms, le[2 + 2 * (size_t)s], le[3 + 2 * (size_t)s]);
+            lat += ms;
+        }
+        (void)hipEventElapsedTime(&ms, le[0], le[1]);
+        ms_out[LBM_NPHASES + 1] = h->np > 0 ? lat / nsteps : ms_out[LBM_PHASE_LATTICE];
+        ms_out[LBM_NPHASES + 2] = ms / nsteps;
+    }
+    for (auto& e : le)
+        if (e) (void)hipEventDestroy(e);
+    if (rc != LBM_OK) return rc;
     return check_status(h);
 }
 

@@ -1,19 +1,15 @@
 // kernels.hip -- the gfx950 kernels of one step of the particle-resolved
 // thermal lattice Boltzmann method (Xu & Li, arXiv 2308.16597).
 //
-// Per step, in launch order (cur = time level n, ring = particle slot of t_n):
-//   k_links         one wavefront per particle: clear the owner map of two
-//                   steps ago over the old window; collect the
-//                   particle's links from the owner map of t_n into LDS in
-//                   the fixed slot order of Sec. 3 (one slot per lattice line
-//                   and direction), wave ballot + prefix count, one global
-//                   atomic per block to reserve contiguous segments.
+// One step n -> n+1 (cur = time level n, ring = particle slot of t_n); the
+// links of t_n were collected at the end of the step before:
 //   k_link_pass     one thread per link of the compacted array: q, wall
 //                   velocity, Bouzidi bounce-back (Eqs. (9)-(10)) and the
 //                   thermal wall (Eqs. (11)-(12)) written into the solid
 //                   slots of the post-collision state; the link's momentum
 //                   exchange (Eqs. (13)-(14)) in FP64.
-//   k_particles     one wavefront per particle: FP64 sum of its links'
+//   k_particles     one wavefront per particle: clear its t_n-1 marks in the
+//                   owner-map buffer of t_n+1; FP64 sum of its links'
 //                   momentum exchange in a fixed order, repulsion (Eq. (15))
 //                   summed in ascending partner order over a cell grid, net
 //                   weight, Newton-Euler update.
@@ -23,6 +19,14 @@
 //                   collision with buoyancy (Sec. 2.1) of the whole lattice.
 //   k_refill        one wavefront per particle: refilling + collision of the
 //                   newborn nodes (Sec. 2.5), over the lattice kernel's output.
+//   k_links         one wavefront per particle: the links of t_n+1 from its
+//                   owner map, collected into LDS in the fixed slot order of
+//                   Sec. 3 (one slot per lattice line and direction), wave
+//                   ballot + prefix count, one global atomic per block to
+//                   reserve contiguous segments.
+// k_particles, k_mask_mark and k_links touch nothing k_stream_collide reads
+// or writes, so a single run launches them on a second stream, concurrent
+// with the lattice kernel.
 // Built with -ffp-contract=off: the solid test and link fractions must round
 // exactly as the CPU oracle rounds them.
 #include <hip/hip_runtime.h>
@@ -53,9 +57,11 @@ template <int MODE> __host__ __device__ Pops<ST<MODE>> pops_of(void* const (&a)[
 // fluid are rewritten by the next link pass), and newborn nodes are
 // overwritten by the refill kernel that runs after this one.  The stores are
 // non-temporal: B is not read again before the next step.  A non-finite
-// macroscopic value is an error only at a node fluid at both time levels;
-// the two owner maps are read only for a node whose value is non-finite, so
-// the check costs no traffic while the run is sound.
+// macroscopic value is an error at a node fluid at t_n (a node solid at t_n
+// pulls from inside the particle); the owner map is read only for a node
+// whose value is non-finite, so the check costs no traffic while the run is
+// sound.  The kernel reads nothing that the particle kernels of the same
+// step write, so those may run concurrently with it.
 template <int MODE>
 __device__ __forceinline__ void stream_collide_body(const RunStep& rs, unsigned bid) {
     using S = Store<MODE>;
@@ -72,8 +78,7 @@ __device__ __forceinline__ void stream_collide_body(const RunStep& rs, unsigned 
     const CC<R> c(lp);
     R rho, ux, uy, T;
     collide<R>(c, s, t, rho, ux, uy, T);
-    if (!(isfinite(rho) && isfinite(T) && isfinite(ux) && isfinite(uy)) && gl(rs.Ocur)[k] == -1 &&
-        gl(rs.Onext)[k] == -1) {
+    if (!(isfinite(rho) && isfinite(T) && isfinite(ux) && isfinite(uy)) && gl(rs.Ocur)[k] == -1) {
         // one report per wavefront, none once the bit is set: a run that
         // has gone non-finite must not serialise on its status word
         const unsigned long long m = __ballot(1);
@@ -215,15 +220,14 @@ __host__ __device__ inline size_t links_wave_lds(int nwin) {
     return links_list_offset(nwin) + links_slots(nwin) * sizeof(uint2);
 }
 
-// Link collection (Sec. 3), one wavefront per particle:
-//  (a) clear the owner map left by t_n-1 over the window of X^{n-1} (that
-//      buffer will describe t_n+1);
-//  (b) load the window of the owner map of t_n into LDS;
-//  (c) every fluid node of the window tests its 8 neighbours in parallel; a
+// Link collection (Sec. 3) from the owner map of t_n, one wavefront per
+// particle (it runs at the end of the step before, once that map is built):
+//  (a) load the window of the owner map of t_n into LDS;
+//  (b) every fluid node of the window tests its 8 neighbours in parallel; a
 //      neighbour owned by this particle is a link, written into its fixed
 //      slot; the slots are then compacted in slot order (ballot + prefix
 //      count within the wavefront);
-//  (d) one global atomic per block reserves the block's contiguous range of
+//  (c) one global atomic per block reserves the block's contiguous range of
 //      the link array; each particle's segment is contiguous, in slot order.
 __device__ __forceinline__ void links_body(const RunStep& rs, unsigned bid, int ppb) {
     extern __shared__ uint2 smem[];
@@ -231,9 +235,7 @@ __device__ __forceinline__ void links_body(const RunStep& rs, unsigned bid, int 
     __shared__ unsigned block_base;
     const LP& lp = rs.lp;
     const PT_GLOBAL int32_t* __restrict__ Ocur = gl(rs.Ocur);
-    PT_GLOBAL int32_t* Onext = gl(rs.Onext);
     const PState* __restrict__ Pc = rs.Pc;
-    const PState* __restrict__ Po = rs.Pold;
     uint2* links = rs.links;
     int2* seg = rs.seg;
     unsigned* counter = rs.counter;
@@ -242,20 +244,6 @@ __device__ __forceinline__ void links_body(const RunStep& rs, unsigned bid, int 
     const int p = (int)bid * ppb + w;
     const bool have_p = w < ppb && p < lp.np;
     const int nx = lp.nx, pitch = lp.pitch;
-
-    if (have_p) {
-        const PState po = ld_state(Po + p);
-        const Win wo = window_of(po);
-        if (particle_ok(po, lp) && wo.nxw <= lp.nwin && wo.nyw <= lp.nwin) {
-            for (int idx = lane; idx < wo.nxw * wo.nyw; idx += 64) {
-                const int b = idx / wo.nxw, a = idx - b * wo.nxw;
-                const int yy = wo.y0 + b;
-                if (!in_rows(yy, lp)) continue;
-                const size_t k = (size_t)yy * pitch + wrap_x(wo.x0 + a, nx);
-                Onext[k] = -1;
-            }
-        }
-    }
 
     const size_t wl = links_wave_lds(lp.nwin) / sizeof(uint2);
     int* win = (int*)(smem + (size_t)w * wl);
@@ -355,7 +343,10 @@ __device__ __forceinline__ void link_pass_body(const RunStep& rs, unsigned bid) 
     const LP& lp = rs.lp;
     const unsigned l = bid * 256u + threadIdx.x;
     if (l >= gl(rs.counter)[0]) return;
-    const Pops<ST<MODE>> A = pops_of<MODE>(rs.A);
+    // population arrays picked straight from the run's pointer table (a
+    // local copy indexed by the link direction would live in scratch)
+    auto F = [&](int a) { return (const PT_GLOBAL ST<MODE>*)rs.A[a]; };
+    auto Fw = [&](int a) { return (PT_GLOBAL ST<MODE>*)rs.A[a]; };
     const PT_GLOBAL int32_t* __restrict__ Ocur = gl(rs.Ocur);
     const int nx = lp.nx, pitch = lp.pitch;
     const uint2 L = ld_u2(rs.links + l);
@@ -369,14 +360,14 @@ __device__ __forceinline__ void link_pass_body(const RunStep& rs, unsigned bid) 
     const size_t k2 = in2 ? (size_t)y2 * pitch + x2 : k;
     const PState P = ld_state(rs.Pc + p);
     const int32_t o1 = Ocur[k1], o2 = Ocur[k2];
-    const double fi = (double)S::ld(A.f[i] + k), fib = (double)S::ld(A.f[ib] + k);
-    const double fi1 = (double)S::ld(A.f[i] + k1), fib1 = (double)S::ld(A.f[ib] + k1);
-    const double fi2 = (double)S::ld(A.f[i] + k2);
+    const double fi = (double)S::ld(F(i) + k), fib = (double)S::ld(F(ib) + k);
+    const double fi1 = (double)S::ld(F(i) + k1), fib1 = (double)S::ld(F(ib) + k1);
+    const double fi2 = (double)S::ld(F(i) + k2);
     double gi = 0.0, gib = 0.0, gi1 = 0.0;
     if (i <= 4) {
-        gi = (double)S::ld(A.g[i] + k);
-        gib = (double)S::ld(A.g[ib] + k);
-        gi1 = (double)S::ld(A.g[i] + k1);
+        gi = (double)S::ld(F(9 + i) + k);
+        gib = (double)S::ld(F(9 + ib) + k);
+        gi1 = (double)S::ld(F(9 + i) + k1);
     }
     const bool have1 = in1 && o1 == -1;
     const bool have2 = have1 && in2 && o2 == -1;
@@ -389,10 +380,10 @@ __device__ __forceinline__ void link_pass_body(const RunStep& rs, unsigned bid) 
     const double wall = 6.0 * w9i * lp.rho0 * (-(ex * uwx) - ey * uwy);
     const double fnew = bouzidi(q, fi, fi1, fi2, fib, fib1, have1, have2, wall);
     const size_t kb = (size_t)(y + ey) * pitch + wrap_x(x + ex, nx);
-    S::st(A.f[ib] + kb, (typename S::R)fnew);
+    S::st(Fw(ib) + kb, (typename S::R)fnew);
     if (i <= 4) {
         const double gnew = thermal_link(q, gi, gi1, gib, have1, lp.w5_k, lp.particle_T - lp.T_sh);
-        S::st(A.g[ib] + kb, (typename S::R)gnew);
+        S::st(Fw(9 + ib) + kb, (typename S::R)gnew);
     }
     // Eq. (13) on full populations (stored value + rest part w rho0)
     const double shf = S::shifted ? lp.rho0 : 0.0;
@@ -458,6 +449,18 @@ __device__ __forceinline__ void particles_body(const RunStep& rs, unsigned bid) 
     const int lane = threadIdx.x & 63;
     const int p = (int)bid * 4 + (threadIdx.x >> 6);
     if (p >= lp.np) return;
+    {   // the owner-map buffer that will hold t_n+1 still holds t_n-1: clear
+        // this particle's marks there (its window at t_n-1)
+        const PState po = ld_state(rs.Pold + p);
+        const Win wo = window_of(po);
+        PT_GLOBAL int32_t* Onext = gl(rs.Onext);
+        if (particle_ok(po, lp) && wo.nxw <= lp.nwin && wo.nyw <= lp.nwin)
+            for (int idx = lane; idx < wo.nxw * wo.nyw; idx += 64) {
+                const int b = idx / wo.nxw, a = idx - b * wo.nxw;
+                const int yy = wo.y0 + b;
+                if (in_rows(yy, lp)) Onext[(size_t)yy * lp.pitch + wrap_x(wo.x0 + a, lp.nx)] = -1;
+            }
+    }
     const PState P = ld_state(Pc + p);
     const int2 sg = ld_i2(rs.seg + p);
     double hx = 0.0, hy = 0.0, hz = 0.0;
@@ -876,7 +879,7 @@ hipError_t launch_step(int k, const RunStep& R, int mode, hipStream_t st) {
     const unsigned nb = run_blocks(grid_class(k), R.lp, ppb);
     if (nb == 0) return hipSuccess;
     switch (k) {
-        case SK_LINKS:
+        case SK_COLLECT:   // R: the RunStep of the step whose links are collected
             k_links<<<nb, 64 * ppb, links_block_lds(R.lp.nwin, ppb), st>>>(R, ppb);
             break;
         case SK_PASS: PTLBM_DISPATCH(mode, (k_link_pass<M><<<nb, 256, 0, st>>>(R))); break;
@@ -895,7 +898,7 @@ hipError_t launch_step_batch(int k, const BatchLaunch& b, hipStream_t st) {
     if (nb == 0) return hipSuccess;
     const uint2* bm = b.bmap[c];
     switch (k) {
-        case SK_LINKS: k_links_b<<<nb, 64 * b.ppb, b.lds, st>>>(b.tab, bm, b.ppb); break;
+        case SK_COLLECT: k_links_b<<<nb, 64 * b.ppb, b.lds, st>>>(b.tab_next, bm, b.ppb); break;
         case SK_PASS: PTLBM_DISPATCH(b.mode, (k_link_pass_b<M><<<nb, 256, 0, st>>>(b.tab, bm))); break;
         case SK_PARTICLES: k_particles_b<<<nb, 256, 0, st>>>(b.tab, bm); break;
         case SK_MASK: k_mask_mark_b<<<nb, 256, 0, st>>>(b.tab, bm); break;

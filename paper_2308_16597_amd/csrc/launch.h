@@ -55,19 +55,22 @@ struct RunStep {
     unsigned* ncand;
 };
 
-// The six step kernels, in launch order.
-enum StepKernel { SK_LINKS = 0, SK_PASS, SK_PARTICLES, SK_MASK, SK_LATTICE, SK_REFILL, SK_COUNT };
+// The six step kernels, in the order of a sequential step; SK_COLLECT
+// gathers the links of the next step and takes the next step's RunStep.
+enum StepKernel { SK_PASS = 0, SK_PARTICLES, SK_MASK, SK_LATTICE, SK_REFILL, SK_COLLECT, SK_COUNT };
 // Grid classes of the step kernels: how many blocks one run needs.
 enum GridClass { GC_LINKS = 0, GC_PASS, GC_WAVE, GC_LAT, GC_COUNT };
 inline GridClass grid_class(int k) {
-    return k == SK_LINKS ? GC_LINKS : k == SK_PASS ? GC_PASS : k == SK_LATTICE ? GC_LAT : GC_WAVE;
+    return k == SK_COLLECT ? GC_LINKS : k == SK_PASS ? GC_PASS : k == SK_LATTICE ? GC_LAT : GC_WAVE;
 }
 
 // A batched launch: one grid over several runs.  bmap[c][b] = {run, block
 // of that run} for block b of a class-c kernel; tab holds one RunStep per
-// run for the step being launched.
+// run for the step being launched, tab_next those of the step after it
+// (for SK_COLLECT).
 struct BatchLaunch {
     const RunStep* tab;
+    const RunStep* tab_next;
     const uint2* bmap[GC_COUNT];
     unsigned nblk[GC_COUNT];
     int ppb;                     // particles per block of the link collection

@@ -111,6 +111,7 @@ int build(Batch& b, lbm_sim* const* runs, int n, lbm_sim* herr) {
     for (int j = 0; j < kCycle; ++j) {
         BatchLaunch& L = b.bl[j];
         L.tab = (const RunStep*)(b.dev + j * tab_bytes);
+        L.tab_next = (const RunStep*)(b.dev + ((j + 1) % kCycle) * tab_bytes);
         for (int c = 0; c < GC_COUNT; ++c) {
             L.bmap[c] = (const uint2*)(b.dev + off_bm[c]);
             L.nblk[c] = (unsigned)bm[c].size();
@@ -128,8 +129,11 @@ int upload(Batch& b, hipStream_t S, lbm_sim* herr) {
     return LBM_OK;
 }
 
+// Kernel k of the step at cycle position j (the link collection takes the
+// RunStep of the step after it).
 hipError_t launch_pos(const Batch& b, int j, int k, hipStream_t S) {
-    return b.single ? launch_step(k, b.one[j], b.mode, S) : launch_step_batch(k, b.bl[j], S);
+    if (!b.single) return launch_step_batch(k, b.bl[j], S);
+    return launch_step(k, b.one[k == SK_COLLECT ? (j + 1) % kCycle : j], b.mode, S);
 }
 
 int capture(Batch& b, hipStream_t S, lbm_sim* herr) {

@@ -33,6 +33,8 @@ struct lbm_sim {
     ptlbm::DevState d{};
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    hipStream_t side = nullptr;  // particle kernels, concurrent with the lattice kernel
+    hipEvent_t ev_fork = nullptr, ev_side = nullptr;
     char* base = nullptr;
     bool own_mem = false;
     int cur = 0;         // time level holding the current (post-collision) state
@@ -55,6 +57,7 @@ int hip_fail(lbm_sim* h, hipError_t e, const char* what);
 // parity bp; the current step of h; the state after one more step.
 RunStep make_runstep(const lbm_sim* h, int c, int r, int bp);
 RunStep current_runstep(const lbm_sim* h);
+RunStep next_runstep(const lbm_sim* h);
 void advance_state(lbm_sim* h);
 // Step-cycle position of h: the state repeats every 6 steps.
 inline int state_index(int cur, int ring, int bp) { return cur * 6 + ring * 2 + bp; }

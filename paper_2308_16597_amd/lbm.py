@@ -27,7 +27,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "lbm.h")
 
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_ESEED, LBM_EUNSTABLE, LBM_ESTATE = 0, -1, -2, -3, -4, -5, -6
 STORE = {"f64": 0, "f32": 1, "shift_f32": 2, "shift_f16": 3, "shift_bf16": 4}
-PHASES = ("collect", "links", "particles", "mask", "lattice", "refill")
+PHASES = ("links", "particles", "mask", "lattice", "refill", "collect")
 
 _d, _i = ctypes.c_double, ctypes.c_int32
 
@@ -216,9 +216,9 @@ def lbm_read_links(h):
 
 
 def lbm_time_phases(h, nsteps):
-    out = np.zeros(len(PHASES) + 1)
+    out = np.zeros(len(PHASES) + 3)
     _check(_lib.lbm_time_phases(h, int(nsteps), _ptr(out)), h)
-    return dict(zip(PHASES + ("step",), out.tolist()))
+    return dict(zip(PHASES + ("step", "lattice_overlapped", "step_overlapped"), out.tolist()))
 
 
 def lbm_stats(h):
