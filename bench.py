@@ -44,7 +44,7 @@ STORE_BYTES = {"f64": 8, "f32": 4, "shift_f32": 4, "shift_f16": 2, "shift_bf16":
 STORE_DTYPE = {"f64": "f64", "f32": "f32", "shift_f32": "f32", "shift_f16": "f32 (f16 storage)",
                "shift_bf16": "f32 (bf16 storage)"}
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2308_16597_amd", "csrc", f)
-                  for f in ("kernels.hip", "device.h")]
+                  for f in ("lattice.hip", "lattice.h", "launch.h")]
 
 
 def log(*a):

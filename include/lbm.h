@@ -5,8 +5,9 @@
  * (arXiv 2308.16597).
  *
  * One step (Sec. 2 and Sec. 3 of the paper) is:
- *   1. collect the fluid-particle links into a compacted index array
- *      (the paper's extended indirect addressing, Sec. 3);
+ *   1. collect the fluid-particle links into an index array, each
+ *      particle's links packed at the front of its own segment of
+ *      12 N - 12 entries (the paper's extended indirect addressing, Sec. 3);
  *   2. at every link: interpolated moving-wall bounce-back (Sec. 2.3,
  *      Eqs. (9)-(10)), the thermal curved-wall condition (Eqs. (11)-(12)) and
  *      the momentum-exchange force and torque (Sec. 2.4, Eqs. (13)-(14));
@@ -119,7 +120,7 @@ enum {
     LBM_PHASE_MASK = 2,      /* solid map at the new positions */
     LBM_PHASE_LATTICE = 3,   /* fused stream + collide over the lattice */
     LBM_PHASE_REFILL = 4,    /* refilling of newborn nodes */
-    LBM_PHASE_COLLECT = 5,   /* link collection of the next step into the compacted array */
+    LBM_PHASE_COLLECT = 5,   /* link collection of the next step into the index array */
     LBM_NPHASES = 6
 };
 
@@ -236,8 +237,9 @@ int lbm_read_links(lbm_handle h, int32_t* node, int32_t* dir, int32_t* particle,
  * Advances the run by 2 nsteps steps.  Waits. */
 int lbm_time_phases(lbm_handle h, int32_t nsteps, double* ms_out);
 
-/* Counters: out[0] steps done, out[1] links of the last step, out[2]
- * particles, out[3] lattice nodes, out[4] device bytes held. */
+/* Counters: out[0] steps done, out[1] links of the current state (those
+ * the next step uses), out[2] particles, out[3] lattice nodes, out[4]
+ * device bytes held.  Waits. */
 int lbm_stats(lbm_handle h, double* out5);
 
 #ifdef __cplusplus

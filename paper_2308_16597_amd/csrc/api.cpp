@@ -1,6 +1,7 @@
 // api.cpp -- the C ABI declared in include/lbm.h: parameter validation,
 // device memory layout, particle seeding, step sequencing and read-back.
-// All arithmetic of the method runs in the kernels of kernels.hip.
+// All arithmetic of the method runs in the kernels of lattice.hip and
+// particles.hip.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -61,7 +62,6 @@ Layout make_layout(const lbm_params& p) {
     L.off_links = off; off = round_up(off + L.link_cap * sizeof(uint2), kAlign);
     L.off_contrib = off; off = round_up(off + L.link_cap * 4 * sizeof(double), kAlign);
     L.off_lscratch = off; off = round_up(off + L.link_cap * (3 * sizeof(int32_t) + sizeof(double)), kAlign);
-    L.off_counter = off; off = round_up(off + 64, kAlign);
     L.off_status = off; off = round_up(off + 64, kAlign);
     // neighbour-search cells at least 2 r_max + s wide
     const double cell = (p.max_diameter > 0 ? p.max_diameter : 2.0) + (p.rep_range > 0 ? p.rep_range : 0.0);
@@ -239,7 +239,6 @@ int create_common(const lbm_params* p, void* dev_ptr, size_t bytes, void* stream
     d.Fh = (double*)(h->base + L.off_Fh);
     d.seg = (int2*)(h->base + L.off_seg);
     d.links = (uint2*)(h->base + L.off_links);
-    d.counter = (unsigned*)(h->base + L.off_counter);
     d.status = (unsigned*)(h->base + L.off_status);
     for (int b = 0; b < 2; ++b) {
         d.bins[b] = (unsigned*)(h->base + L.off_bins[b]);
@@ -266,7 +265,7 @@ int check_status(lbm_sim* h) {
     std::string m = "device reported:";
     if (st & ST_NONFINITE) m += " non-finite populations;";
     if (st & ST_OVERSPEED) m += " a particle moved more than 0.5 in one step;";
-    if (st & ST_LINK_OVERFLOW) m += " link array overflow;";
+    if (st & ST_LINK_OVERFLOW) m += " more links for one particle than its segment holds;";
     if (st & ST_BAD_PARTICLE) m += " particle state not finite or outside the lattice;";
     if (st & ST_BIN_OVERFLOW) m += " more than 7 particles in one neighbour-search cell;";
     if (st & ST_CAND_OVERFLOW) m += " too many newborn nodes for one particle in one step;";
@@ -294,7 +293,6 @@ RunStep make_runstep(const lbm_sim* h, int c, int r, int bp) {
     R.contrib = d.contrib;
     R.links = d.links;
     R.seg = d.seg;
-    R.counter = d.counter;
     R.status = d.status;
     R.bins_cur = d.bins[bp];
     R.cnt_cur = d.bcnt[bp];
@@ -360,6 +358,42 @@ int enqueue_step(lbm_sim* h, hipEvent_t* ev, hipEvent_t* lat = nullptr) {
 
 void* scratch_of(lbm_sim* h) { return h->d.S[1 - h->cur][0]; }
 
+void drop_cycle_graph(lbm_sim* h) {
+    if (h->cycle_graph) (void)hipGraphExecDestroy(h->cycle_graph);
+    h->cycle_graph = nullptr;
+    h->cycle_state = -1;
+}
+
+// Capture six overlapped steps from the current state into h->cycle_graph
+// (nothing runs; the state is restored afterwards).
+int capture_cycle(lbm_sim* h) {
+    drop_cycle_graph(h);
+    const int cur = h->cur, ring = h->ring, bp = h->bin_parity;
+    const int64_t steps = h->steps;
+    HIPCHK(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeRelaxed));
+    int rc = LBM_OK;
+    for (int j = 0; j < 6 && rc == LBM_OK; ++j) rc = enqueue_step(h, nullptr);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(h->stream, &g);
+    h->cur = cur;
+    h->ring = ring;
+    h->bin_parity = bp;
+    h->steps = steps;
+    if (rc != LBM_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&h->cycle_graph, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        h->cycle_graph = nullptr;
+        return hip_fail(h, e, "capture of the step cycle");
+    }
+    h->cycle_state = state_index(cur, ring, bp);
+    h->cycle_generation = h->generation;
+    return LBM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -409,6 +443,7 @@ void lbm_destroy(lbm_handle h) {
     forget_batches(h);
     if (h->stream) (void)hipStreamSynchronize(h->stream);
     if (h->side) (void)hipStreamSynchronize(h->side);
+    drop_cycle_graph(h);
     if (h->own_mem && h->base) (void)hipFree(h->base);
     for (hipEvent_t e : {h->ev_fork, h->ev_side})
         if (e) (void)hipEventDestroy(e);
@@ -528,7 +563,6 @@ int lbm_set_particles(lbm_handle h, int32_t n, const double* rows7) {
     const size_t nb = h->L.npitched;
     HIPCHK(h, hipMemsetAsync(d.O[0], 0xff, nb * 4, st));
     HIPCHK(h, hipMemsetAsync(d.O[1], 0xff, nb * 4, st));
-    HIPCHK(h, hipMemsetAsync(d.counter, 0, 64, st));
     HIPCHK(h, hipMemsetAsync(d.status, 0, 64, st));
     if (n > 0) {
         for (int r = 0; r < 3; ++r)
@@ -579,7 +613,23 @@ int lbm_set_equilibrium(lbm_handle h, const double* rho, const double* ux, const
 int lbm_step(lbm_handle h, int32_t nsteps) {
     if (!h) return LBM_EINVAL;
     if (nsteps < 0) return fail(h, LBM_EINVAL, "negative step count");
-    for (int32_t s = 0; s < nsteps; ++s) {
+    int32_t s = 0;
+    // whole 6-step cycles (the step state repeats every 6 steps) replay a
+    // captured graph of the overlapped schedule once there are two of them
+    // or the graph for this state already exists
+    const int state = state_index(h->cur, h->ring, h->bin_parity);
+    const bool have = h->cycle_graph && h->cycle_state == state && h->cycle_generation == h->generation;
+    if (nsteps >= 12 || (have && nsteps >= 6)) {
+        if (!have) {
+            int rc = capture_cycle(h);
+            if (rc != LBM_OK) return rc;
+        }
+        for (; nsteps - s >= 6; s += 6) {
+            HIPCHK(h, hipGraphLaunch(h->cycle_graph, h->stream));
+            h->steps += 6;   // six steps return the state to where it was
+        }
+    }
+    for (; s < nsteps; ++s) {
         int rc = enqueue_step(h, nullptr);
         if (rc != LBM_OK) return rc;
     }
@@ -615,10 +665,13 @@ int lbm_read_fields(lbm_handle h, double* rho, double* ux, double* uy, double* T
             for (size_t k = 0; k < n; ++k) outs[c][k] = tmp[k];
         }
     }
-    if (owner)
-        HIPCHK(h, hipMemcpy2DAsync(owner, (size_t)h->p.nx * 4, h->d.O[h->cur], (size_t)h->L.pitch * 4,
-                                   (size_t)h->p.nx * 4, h->p.ny, hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
+    // the owner map row by row out of the pitched layout, as a blocking copy
+    // (the asynchronous 2-D copy into pageable memory came back as zeros
+    // under a profiler)
+    if (owner)
+        HIPCHK(h, hipMemcpy2D(owner, (size_t)h->p.nx * 4, h->d.O[h->cur], (size_t)h->L.pitch * 4,
+                              (size_t)h->p.nx * 4, h->p.ny, hipMemcpyDeviceToHost));
     return rc;
 }
 
@@ -651,26 +704,39 @@ int lbm_read_links(lbm_handle h, int32_t* node, int32_t* dir, int32_t* particle,
     if (h->np == 0) return LBM_OK;
     DevState& d = h->d;
     // the links of the current state were collected at the end of the last
-    // step (or by lbm_set_particles); counter[0] holds their number
-    unsigned nl = 0;
-    HIPCHK(h, hipMemcpyAsync(&nl, d.counter, sizeof nl, hipMemcpyDeviceToHost, h->stream));
+    // step (or by lbm_set_particles), each particle's at the front of its
+    // own segment; gather them into one list on the host
+    const size_t per = (size_t)(12 * h->L.nwin - 12), np = (size_t)h->np;
+    std::vector<int2> seg(np);
+    HIPCHK(h, hipMemcpyAsync(seg.data(), d.seg, np * sizeof(int2), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
-    if (n_out) *n_out = nl;
+    size_t nl = 0;
+    for (const int2& sg : seg) nl += (size_t)sg.y;
+    if (n_out) *n_out = (int64_t)nl;
+    if (!(node || dir || particle || q) || nl == 0) return LBM_OK;
+    if ((int64_t)nl > cap) return fail(h, LBM_EINVAL, "cap %lld < %zu links", (long long)cap, nl);
+    std::vector<uint2> all(np * per), list;
+    list.reserve(nl);
+    HIPCHK(h, hipMemcpyAsync(all.data(), d.links, all.size() * sizeof(uint2), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    for (size_t p = 0; p < np; ++p)
+        for (int i = 0; i < seg[p].y; ++i) list.push_back(all[(size_t)seg[p].x + i]);
+    // the per-link records of the last link pass are free between steps:
+    // they hold the gathered list for the q kernel
+    uint2* dl = (uint2*)d.contrib;
     char* ls = h->base + h->L.off_lscratch;
     int32_t* dn = (int32_t*)ls;
     int32_t* dd = dn + nl;
     int32_t* dp = dd + nl;
-    double* dq = (double*)(ls + round_up((size_t)nl * 12, 8));
-    if (node || dir || particle || q) {
-        if ((int64_t)nl > cap) return fail(h, LBM_EINVAL, "cap %lld < %u links", (long long)cap, nl);
-        HIPCHK(h, launch_link_q(d, h->ring, (int)nl, dn, dd, dp, dq, h->stream));
-        if (node) HIPCHK(h, hipMemcpyAsync(node, dn, nl * 4, hipMemcpyDeviceToHost, h->stream));
-        if (dir) HIPCHK(h, hipMemcpyAsync(dir, dd, nl * 4, hipMemcpyDeviceToHost, h->stream));
-        if (particle) HIPCHK(h, hipMemcpyAsync(particle, dp, nl * 4, hipMemcpyDeviceToHost, h->stream));
-        if (q) HIPCHK(h, hipMemcpyAsync(q, dq, nl * 8, hipMemcpyDeviceToHost, h->stream));
-    }
+    double* dq = (double*)(ls + round_up(nl * 12, 8));
+    HIPCHK(h, hipMemcpyAsync(dl, list.data(), nl * sizeof(uint2), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, launch_link_q(d, h->ring, dl, (int)nl, dn, dd, dp, dq, h->stream));
+    if (node) HIPCHK(h, hipMemcpyAsync(node, dn, nl * 4, hipMemcpyDeviceToHost, h->stream));
+    if (dir) HIPCHK(h, hipMemcpyAsync(dir, dd, nl * 4, hipMemcpyDeviceToHost, h->stream));
+    if (particle) HIPCHK(h, hipMemcpyAsync(particle, dp, nl * 4, hipMemcpyDeviceToHost, h->stream));
+    if (q) HIPCHK(h, hipMemcpyAsync(q, dq, nl * 8, hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
-    return LBM_OK;
+    return check_status(h);
 }
 
 int lbm_time_phases(lbm_handle h, int32_t nsteps, double* ms_out) {
@@ -727,11 +793,15 @@ int lbm_time_phases(lbm_handle h, int32_t nsteps, double* ms_out) {
 
 int lbm_stats(lbm_handle h, double* out5) {
     if (!h || !out5) return LBM_EINVAL;
-    unsigned c[2] = {0, 0};
-    HIPCHK(h, hipMemcpyAsync(c, h->d.counter, sizeof c, hipMemcpyDeviceToHost, h->stream));
+    std::vector<int2> seg((size_t)h->np);
+    if (h->np > 0)
+        HIPCHK(h, hipMemcpyAsync(seg.data(), h->d.seg, seg.size() * sizeof(int2), hipMemcpyDeviceToHost,
+                                 h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
+    double nl = 0.0;
+    for (const int2& sg : seg) nl += sg.y;
     out5[0] = (double)h->steps;
-    out5[1] = (double)c[1];
+    out5[1] = nl;
     out5[2] = (double)h->np;
     out5[3] = (double)h->p.nx * h->p.ny;
     out5[4] = (double)h->L.total;

@@ -1,6 +1,7 @@
-// device.h -- device-side building blocks of the gfx950 path: storage
-// policies, the fused D2Q9 + D2Q5 MRT collision in deviation variables, the
-// pull step with flat walls, and the particle-boundary schemes.
+// lattice.h -- device-side building blocks of the lattice update: storage
+// policies, the fused D2Q9 + D2Q5 MRT collision in deviation variables and
+// the pull step with flat walls; also the lattice constants every kernel
+// takes and the helpers shared by the kernel files.
 //
 // Method: Xu & Li, arXiv 2308.16597, Sec. 2 (equations cited at each piece).
 // Readings of points the paper leaves open are the same as in the library's
@@ -88,10 +89,6 @@ struct LP {
     int link_cap;
     int ncx, ncy, ncells;              // neighbour-search cell grid
 };
-
-// Particles per cell of the neighbour-search grid (cells are at least
-// 2 r_max + s wide, so a cell of non-overlapping disks holds at most 4).
-constexpr int BINCAP = 7;
 
 // Collision constants in the compute type.
 template <class R> struct CC {
@@ -287,133 +284,27 @@ __device__ __forceinline__ void store_node(const Pops<typename S::T>& B, const L
     }
 }
 
-// ------------------------------------------------------------- geometry ----
-// The exact solid test shared by every kernel that builds or reads the
-// solid map: dx = (i - X) with the minimum image along the periodic x axis,
-// dy = j - Y, inside when dx*dx + dy*dy <= r*r (no fused multiply-add: the
-// translation unit is compiled with -ffp-contract=off).
-__device__ __forceinline__ double min_image_x(double d, int nx) {
-    const double h = 0.5 * nx;
-    if (d > h) return d - nx;
-    if (d < -h) return d + nx;
-    return d;
+// -------------------------------------------------- shared by the kernels ----
+constexpr int LAT_BLOCK = 256;
+
+template <int MODE> using ST = typename Store<MODE>::T;
+
+template <int MODE> __host__ __device__ Pops<ST<MODE>> pops_of(void* const (&a)[14]) {
+    Pops<ST<MODE>> p;
+    for (int i = 0; i < 9; ++i) p.f[i] = (PT_GLOBAL ST<MODE>*)a[i];
+    for (int i = 0; i < 5; ++i) p.g[i] = (PT_GLOBAL ST<MODE>*)a[9 + i];
+    return p;
 }
 
-struct PState {   // one particle, FP64
-    double x, y, r, ux, uy, th, om, pad;
-};
-
-// Whole-record global-memory accesses of the small structs kept in device
-// arrays (their copy operations do not bind to address-space-qualified
-// objects, so they go field by field; adjacent fields merge into wide
-// accesses).
-__device__ __forceinline__ PState ld_state(const PState* p) {
-    const PT_GLOBAL double* q = (const PT_GLOBAL double*)p;
-    return PState{q[0], q[1], q[2], q[3], q[4], q[5], q[6], q[7]};
-}
-__device__ __forceinline__ void st_state(PState* p, const PState& v) {
-    PT_GLOBAL double* q = (PT_GLOBAL double*)p;
-    q[0] = v.x; q[1] = v.y; q[2] = v.r; q[3] = v.ux; q[4] = v.uy; q[5] = v.th; q[6] = v.om; q[7] = v.pad;
-}
-__device__ __forceinline__ uint2 ld_u2(const uint2* p) {
-    const PT_GLOBAL unsigned* q = (const PT_GLOBAL unsigned*)p;
-    return make_uint2(q[0], q[1]);
-}
-__device__ __forceinline__ void st_u2(uint2* p, uint2 v) {
-    PT_GLOBAL unsigned* q = (PT_GLOBAL unsigned*)p;
-    q[0] = v.x;
-    q[1] = v.y;
-}
-__device__ __forceinline__ int2 ld_i2(const int2* p) {
-    const PT_GLOBAL int* q = (const PT_GLOBAL int*)p;
-    return make_int2(q[0], q[1]);
-}
-__device__ __forceinline__ void st_i2(int2* p, int2 v) {
-    PT_GLOBAL int* q = (PT_GLOBAL int*)p;
-    q[0] = v.x;
-    q[1] = v.y;
-}
-__device__ __forceinline__ double4 ld_d4(const double4* p) {
-    const PT_GLOBAL double* q = (const PT_GLOBAL double*)p;
-    return make_double4(q[0], q[1], q[2], q[3]);
-}
-__device__ __forceinline__ void st_d4(double4* p, double4 v) {
-    PT_GLOBAL double* q = (PT_GLOBAL double*)p;
-    q[0] = v.x;
-    q[1] = v.y;
-    q[2] = v.z;
-    q[3] = v.w;
-}
-
-// Window of a particle (Sec. 3): x from INT(x_c - r) - 1 to INT(x_c + r) + 1
-// and likewise in y, INT read as floor.
-struct Win {
-    int x0, y0, nxw, nyw;
-};
-__device__ __forceinline__ Win window_of(const PState& P) {
-    Win w;
-    const int xa = (int)floor(P.x - P.r), xb = (int)floor(P.x + P.r);
-    const int ya = (int)floor(P.y - P.r), yb = (int)floor(P.y + P.r);
-    w.x0 = xa - 1;
-    w.y0 = ya - 1;
-    w.nxw = xb - xa + 3;
-    w.nyw = yb - ya + 3;
-    return w;
-}
-// A particle whose state is not finite or far outside the lattice is not
-// processed (its kernels would address outside the buffers); the step
-// reports it through the status word.
-__device__ __forceinline__ bool particle_ok(const PState& P, const LP& lp) {
-    return isfinite(P.x) && isfinite(P.y) && isfinite(P.r) && P.x >= -lp.nx && P.x <= 2.0 * lp.nx &&
-           P.y >= -(double)lp.ny && P.y <= 2.0 * lp.ny;
-}
-__device__ __forceinline__ int wrap_x(int x, int nx) {
-    x %= nx;
-    return x < 0 ? x + nx : x;
-}
-
-// Link fraction q of Sec. 2.3 for the circle: the nearer root of
-// |d + t e_i|^2 = r^2, clamped to [0, 1].
-__device__ __forceinline__ double link_q(double dx, double dy, double r, int i) {
-    const double ex = EXd(i), ey = EYd(i);
-    const double a = ex * ex + ey * ey;
-    const double b = dx * ex + dy * ey;
-    const double c = (dx * dx + dy * dy) - r * r;
-    double disc = b * b - a * c;
-    if (disc < 0.0) disc = 0.0;
-    double q = (-b - sqrt(disc)) / a;
-    if (q < 0.0) q = 0.0;
-    if (q > 1.0) q = 1.0;
-    return q;
-}
-
-// Interpolated bounce-back, Sec. 2.3 Eqs. (9)-(10), with the linear and
-// halfway fallbacks when stencil nodes are not fluid.  Works on stored
-// values of any mode: the coefficients sum to one and f_i, f_ibar share the
-// same rest weight.  wall = 2 w_i rho0 (e_ibar . u_w)/cs^2.
-__device__ __forceinline__ double bouzidi(double q, double fi, double fi1, double fi2, double fib,
-                                          double fib1, bool have1, bool have2, double wall) {
-    if (q <= 0.5) {
-        if (have1 && have2)
-            return q * (2.0 * q + 1.0) * fi + (1.0 - 4.0 * q * q) * fi1 - q * (1.0 - 2.0 * q) * fi2 + wall;
-        if (have1) return 2.0 * q * fi + (1.0 - 2.0 * q) * fi1 + wall;
-        return fi + wall;
+// Run CALL with the storage mode as the compile-time constant M.
+#define PTLBM_DISPATCH(mode, CALL)                                                          \
+    switch (mode) {                                                                         \
+        case LBM_STORE_F64: { constexpr int M = LBM_STORE_F64; CALL; } break;               \
+        case LBM_STORE_F32: { constexpr int M = LBM_STORE_F32; CALL; } break;               \
+        case LBM_STORE_SHIFT_F32: { constexpr int M = LBM_STORE_SHIFT_F32; CALL; } break;   \
+        case LBM_STORE_SHIFT_F16: { constexpr int M = LBM_STORE_SHIFT_F16; CALL; } break;   \
+        case LBM_STORE_SHIFT_BF16: { constexpr int M = LBM_STORE_SHIFT_BF16; CALL; } break; \
+        default: return hipErrorInvalidValue;                                               \
     }
-    const double a = 1.0 / (q * (2.0 * q + 1.0));
-    if (have1) return a * fi + (2.0 * q - 1.0) / q * fib - (2.0 * q - 1.0) / (2.0 * q + 1.0) * fib1 + a * wall;
-    return 1.0 / (2.0 * q) * fi + (2.0 * q - 1.0) / (2.0 * q) * fib + wall / (2.0 * q);
-}
-
-// Thermal curved wall, Sec. 2.3 Eqs. (11)-(12), on stored values whose rest
-// part is w T_store (T_store = T_sh for shifted storage, 0 for plain):
-// g_ibar = -g_i + c (g_i(x_f - e_i) + g_ibar) + c4 2 w (T_w - T_store),
-// c = (2q-1)/(2q+1), c4 = 2/(2q+1); anti-bounce-back without x_f - e_i.
-__device__ __forceinline__ double thermal_link(double q, double gi, double gi1, double gib, bool have1,
-                                               double w, double Tw_rel) {
-    if (!have1) return -gi + 2.0 * w * Tw_rel;
-    const double c = (2.0 * q - 1.0) / (2.0 * q + 1.0);
-    const double c4 = 2.0 / (2.0 * q + 1.0);
-    return (-gi + c * gi1 + c * gib) + c4 * (2.0 * w * Tw_rel);
-}
 
 }  // namespace ptlbm

@@ -1,0 +1,184 @@
+// lattice.hip -- the gfx950 lattice kernels of the particle-resolved thermal
+// lattice Boltzmann method (Xu & Li, arXiv 2308.16597): the fused
+// pull-stream + D2Q9/D2Q5 MRT collision of every node of one step (Sec. 2.1,
+// Eqs. (5)-(6)), for one run or batched over many, and the initialisation
+// and read-back of macroscopic fields.
+// Built with -ffp-contract=off, like the particle kernels.
+#include <hip/hip_runtime.h>
+
+#include "launch.h"
+
+namespace ptlbm {
+
+// ------------------------------------------------------ lattice kernels ----
+
+// Fused pull-stream + collide of every node of the lattice, one thread per
+// node of the pitched layout (flat 1-D grid, rows padded to the pitch).
+// Every node is written, so each wavefront stores whole cache lines: nodes
+// that are solid at t_n+1 receive values nobody reads (their slots facing the
+// fluid are rewritten by the next link pass), and newborn nodes are
+// overwritten by the refill kernel that runs after this one.  The stores are
+// non-temporal: B is not read again before the next step.  A non-finite
+// macroscopic value is an error at a node fluid at t_n (a node solid at t_n
+// pulls from inside the particle); the owner map is read only for a node
+// whose value is non-finite, so the check costs no traffic while the run is
+// sound.  The kernel reads nothing that the particle kernels of the same
+// step write, so those may run concurrently with it.
+template <int MODE>
+__device__ __forceinline__ void stream_collide_body(const RunStep& rs, unsigned bid) {
+    using S = Store<MODE>;
+    using R = typename S::R;
+    const LP& lp = rs.lp;
+    const Pops<ST<MODE>> A = pops_of<MODE>(rs.A), B = pops_of<MODE>(rs.B);
+    const size_t n0 = (size_t)bid * LAT_BLOCK + threadIdx.x;
+    const int y = (int)(n0 / (unsigned)lp.pitch);
+    const int x = (int)(n0 - (size_t)y * lp.pitch);
+    if (x >= lp.nx || y >= lp.ny) return;
+    const size_t k = (size_t)y * lp.pitch + x;
+    R s[9], t[5];
+    pull_node<S>(A, lp, x, y, s, t);
+    const CC<R> c(lp);
+    R rho, ux, uy, T;
+    collide<R>(c, s, t, rho, ux, uy, T);
+    if (!(isfinite(rho) && isfinite(T) && isfinite(ux) && isfinite(uy)) && gl(rs.Ocur)[k] == -1) {
+        // one report per wavefront, none once the bit is set: a run that
+        // has gone non-finite must not serialise on its status word
+        const unsigned long long m = __ballot(1);
+        if ((threadIdx.x & 63) == (unsigned)(__ffsll((long long)m) - 1) && !(gl(rs.status)[0] & ST_NONFINITE))
+            atomicOr(rs.status, ST_NONFINITE);
+    }
+    store_node<S, true>(B, lp, k, s, t);
+}
+
+// Equilibrium of the given macroscopic fields (host layout j*nx + i; NULL
+// pointers select the uniform rest state), collided once: the
+// post-collision state of t_0.
+template <int MODE, class FT>
+__global__ __launch_bounds__(LAT_BLOCK) void k_init(Pops<ST<MODE>> A, const int32_t* __restrict__ owner,
+                                                    const FT* rho_f, const FT* ux_f, const FT* uy_f,
+                                                    const FT* T_f, double rho_u, double T_u, LP lp) {
+    using S = Store<MODE>;
+    using R = typename S::R;
+    const int x = blockIdx.x * LAT_BLOCK + threadIdx.x;
+    const int y = blockIdx.y;
+    if (x >= lp.nx) return;
+    const size_t k = (size_t)y * lp.pitch + x;
+    const size_t h = (size_t)y * lp.nx + x;
+    R s[9], t[5];
+    if (owner[k] >= 0) {
+        for (int i = 0; i < 9; ++i) s[i] = (R)0;
+        for (int i = 0; i < 5; ++i) t[i] = (R)0;
+    } else {
+        const R rho = rho_f ? (R)rho_f[h] : (R)rho_u;
+        const R ux = ux_f ? (R)ux_f[h] : (R)0;
+        const R uy = uy_f ? (R)uy_f[h] : (R)0;
+        const R T = T_f ? (R)T_f[h] : (R)T_u;
+        feq_dev<R>(rho, (R)lp.rho0, ux, uy, s);
+        geq_dev<R>(T, (R)lp.T_sh, ux, uy, (R)lp.w5_0, (R)lp.w5_k, t);
+        const CC<R> c(lp);
+        R r_, u_, v_, T_;
+        collide<R>(c, s, t, r_, u_, v_, T_);
+    }
+    store_node<S>(A, lp, k, s, t);
+}
+
+// Pre-collision macroscopics from the post-collision state: rho and T are
+// collision invariants and the momentum gained the force, so
+// u = (j+ - F/2)/rho.  NaN inside solids.  Output: 4 planes of nx*ny (OT).
+template <int MODE, class OT>
+__global__ __launch_bounds__(LAT_BLOCK) void k_macros(Pops<ST<MODE>> A, const int32_t* __restrict__ owner,
+                                                      OT* out, LP lp) {
+    using S = Store<MODE>;
+    using R = typename S::R;
+    const int x = blockIdx.x * LAT_BLOCK + threadIdx.x;
+    const int y = blockIdx.y;
+    if (x >= lp.nx) return;
+    const size_t k = (size_t)y * lp.pitch + x;
+    const size_t n = (size_t)lp.nx * lp.ny, h = (size_t)y * lp.nx + x;
+    if (owner[k] >= 0) {
+        const OT nan = (OT)NAN;
+        out[h] = nan;
+        out[n + h] = nan;
+        out[2 * n + h] = nan;
+        out[3 * n + h] = nan;
+        return;
+    }
+    R s[9], t[5];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) s[i] = S::ld(A.f[i] + k) - (S::shifted ? (R)0 : w9<R>(i) * (R)lp.rho0);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) t[i] = S::ld(A.g[i] + k);
+    R drho = (R)0, jx = (R)0, jy = (R)0, dT = (R)0;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        drho += s[i];
+        jx += (R)EXd(i) * s[i];
+        jy += (R)EYd(i) * s[i];
+    }
+#pragma unroll
+    for (int i = 0; i < 5; ++i) dT += t[i];
+    const R rho = (R)lp.rho0 + drho;
+    const R T = (R)lp.T_sh + dT;
+    const R Fx = (R)lp.body_fx;
+    const R Fy = rho * (R)lp.gbeta * (T - (R)lp.T_ref);
+    out[h] = (OT)rho;
+    out[n + h] = (OT)((jx - (R)0.5 * Fx) / rho);
+    out[2 * n + h] = (OT)((jy - (R)0.5 * Fy) / rho);
+    out[3 * n + h] = (OT)T;
+}
+
+// The lattice step kernel for one run (RunStep by value) and batched (block
+// b works on block bmap[b].y of run bmap[b].x, whose RunStep is
+// tab[bmap[b].x]); both run the same body.
+template <int MODE>
+__global__ __launch_bounds__(LAT_BLOCK) void k_stream_collide(RunStep rs) {
+    stream_collide_body<MODE>(rs, blockIdx.x);
+}
+template <int MODE>
+__global__ __launch_bounds__(LAT_BLOCK) void k_stream_collide_b(const RunStep* __restrict__ tab,
+                                                                const uint2* __restrict__ bmap) {
+    const uint2 m = bmap[blockIdx.x];
+    stream_collide_body<MODE>(tab[m.x], m.y);
+}
+
+// -------------------------------------------------------------- launchers ----
+
+static dim3 lattice_grid(const LP& lp) { return dim3((lp.nx + LAT_BLOCK - 1) / LAT_BLOCK, lp.ny); }
+
+hipError_t launch_lattice(const RunStep& R, int mode, unsigned nblocks, hipStream_t st) {
+    PTLBM_DISPATCH(mode, (k_stream_collide<M><<<nblocks, LAT_BLOCK, 0, st>>>(R)));
+    return hipGetLastError();
+}
+
+hipError_t launch_lattice_batch(const RunStep* tab, const uint2* bmap, unsigned nblocks, int mode,
+                                hipStream_t st) {
+    PTLBM_DISPATCH(mode, (k_stream_collide_b<M><<<nblocks, LAT_BLOCK, 0, st>>>(tab, bmap)));
+    return hipGetLastError();
+}
+
+hipError_t launch_init(const DevState& d, int cur, const void* rho, const void* ux, const void* uy,
+                       const void* T, bool f64, double rho_u, double T_u, hipStream_t st) {
+    if (f64) {
+        PTLBM_DISPATCH(d.mode, (k_init<M, double><<<lattice_grid(d.lp), LAT_BLOCK, 0, st>>>(
+                                   pops_of<M>(d.S[cur]), d.O[cur], (const double*)rho, (const double*)ux,
+                                   (const double*)uy, (const double*)T, rho_u, T_u, d.lp)));
+    } else {
+        PTLBM_DISPATCH(d.mode, (k_init<M, float><<<lattice_grid(d.lp), LAT_BLOCK, 0, st>>>(
+                                   pops_of<M>(d.S[cur]), d.O[cur], (const float*)rho, (const float*)ux,
+                                   (const float*)uy, (const float*)T, rho_u, T_u, d.lp)));
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_macros(const DevState& d, int cur, void* out, hipStream_t st) {
+    if (d.mode == LBM_STORE_F64) {
+        k_macros<LBM_STORE_F64, double><<<lattice_grid(d.lp), LAT_BLOCK, 0, st>>>(
+            pops_of<LBM_STORE_F64>(d.S[cur]), d.O[cur], (double*)out, d.lp);
+    } else {
+        PTLBM_DISPATCH(d.mode, (k_macros<M, float><<<lattice_grid(d.lp), LAT_BLOCK, 0, st>>>(
+                                   pops_of<M>(d.S[cur]), d.O[cur], (float*)out, d.lp)));
+    }
+    return hipGetLastError();
+}
+
+}  // namespace ptlbm

@@ -1,4 +1,5 @@
-// launch.h -- host-side launchers of the gfx950 kernels (kernels.hip), used
+// launch.h -- host-side launchers of the gfx950 kernels (lattice.hip,
+// particles.hip) and the structures they take, used
 // by the C ABI implementation (api.cpp).  Every launcher enqueues on the
 // given stream and returns the launch status.
 #pragma once
@@ -6,7 +7,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include "device.h"
+#include "lattice.h"
+#include "particles.h"
 
 namespace ptlbm {
 
@@ -18,9 +20,8 @@ struct DevState {
     PState* P[3];                // particle ring (old, current, next rotate)
     double* Fh;                  // per-particle momentum-exchange force/torque (x, y, z, pad)
     double4* contrib;            // per-link momentum exchange (Fx, Fy, Tz, pad)
-    uint2* links;                // compacted link array
+    uint2* links;                // link array: particle p's links at p (12 nwin - 12)
     int2* seg;                   // per-particle {start, count}
-    unsigned* counter;           // [0] link counter, [1] links of the last step
     unsigned* status;            // device error bits
     unsigned* bins[2];           // cell grid (BINCAP particle slots per cell), two time levels
     unsigned* bcnt[2];           // particles per cell
@@ -45,7 +46,6 @@ struct RunStep {
     double4* contrib;
     uint2* links;
     int2* seg;
-    unsigned* counter;
     unsigned* status;
     const unsigned* bins_cur;
     unsigned* cnt_cur;           // read by k_particles, cleared by k_mask_mark
@@ -81,7 +81,7 @@ struct BatchLaunch {
 enum StatusBits : unsigned {
     ST_NONFINITE = 1u,      // non-finite macroscopic value
     ST_OVERSPEED = 2u,      // particle moved more than 0.5 per step
-    ST_LINK_OVERFLOW = 4u,  // link array too small
+    ST_LINK_OVERFLOW = 4u,  // more links for one particle than its segment holds
     ST_BAD_PARTICLE = 8u,   // particle state unusable (not finite / far outside)
     ST_BIN_OVERFLOW = 16u,  // more than BINCAP particles in one neighbour-search cell
     ST_CAND_OVERFLOW = 32u, // more newborn nodes for one particle than its candidate list holds
@@ -94,6 +94,10 @@ int links_particles_per_block(int nwin);
 size_t links_block_lds(int nwin, int ppb);
 
 hipError_t launch_step(int k, const RunStep& R, int mode, hipStream_t st);
+// The lattice kernel alone (lattice.hip), for one run or batched.
+hipError_t launch_lattice(const RunStep& R, int mode, unsigned nblocks, hipStream_t st);
+hipError_t launch_lattice_batch(const RunStep* tab, const uint2* bmap, unsigned nblocks, int mode,
+                                hipStream_t st);
 hipError_t launch_step_batch(int k, const BatchLaunch& b, hipStream_t st);
 // Owner map of R.Pn into R.Onext with no previous time level (set-up).
 hipError_t launch_mask_setup(const RunStep& R, hipStream_t st);
@@ -102,8 +106,8 @@ hipError_t launch_init(const DevState& d, int cur, const void* rho, const void* 
                        const void* T, bool fields_f64, double rho_u, double T_u, hipStream_t st);
 hipError_t launch_macros(const DevState& d, int cur, void* out, hipStream_t st);
 hipError_t launch_bin_init(const DevState& d, const PState* P, int bin_parity, hipStream_t st);
-hipError_t launch_link_q(const DevState& d, int ring, int nlinks, int32_t* node, int32_t* dir,
-                         int32_t* part, double* q, hipStream_t st);
+hipError_t launch_link_q(const DevState& d, int ring, const uint2* links, int nlinks, int32_t* node,
+                         int32_t* dir, int32_t* part, double* q, hipStream_t st);
 
 // Ring slots: current = ring, next = (ring + 1) % 3, old = (ring + 2) % 3.
 inline int ring_next(int r) { return (r + 1) % 3; }

@@ -1,9 +1,11 @@
-// kernels.hip -- the gfx950 kernels of one step of the particle-resolved
-// thermal lattice Boltzmann method (Xu & Li, arXiv 2308.16597).
+// particles.hip -- the gfx950 particle kernels of one step of the
+// particle-resolved thermal lattice Boltzmann method (Xu & Li, arXiv
+// 2308.16597), and the dispatch of all six step kernels (the lattice kernel
+// itself is in lattice.hip).
 //
 // One step n -> n+1 (cur = time level n, ring = particle slot of t_n); the
 // links of t_n were collected at the end of the step before:
-//   k_link_pass     one thread per link of the compacted array: q, wall
+//   k_link_pass     one thread per link slot of the particles' segments: q, wall
 //                   velocity, Bouzidi bounce-back (Eqs. (9)-(10)) and the
 //                   thermal wall (Eqs. (11)-(12)) written into the solid
 //                   slots of the post-collision state; the link's momentum
@@ -22,8 +24,8 @@
 //   k_links         one wavefront per particle: the links of t_n+1 from its
 //                   owner map, collected into LDS in the fixed slot order of
 //                   Sec. 3 (one slot per lattice line and direction), wave
-//                   ballot + prefix count, one global atomic per block to
-//                   reserve contiguous segments.
+//                   ballot + prefix count, compacted to the front of the
+//                   particle's own segment of 12 N - 12 entries.
 // k_particles, k_mask_mark and k_links touch nothing k_stream_collide reads
 // or writes, so a single run launches them on a second stream, concurrent
 // with the lattice kernel.
@@ -35,135 +37,8 @@
 
 namespace ptlbm {
 
-constexpr int LAT_BLOCK = 256;
 constexpr double kPi = 3.14159265358979323846;
 constexpr int OUTSIDE = -2;
-
-template <int MODE> using ST = typename Store<MODE>::T;
-
-template <int MODE> __host__ __device__ Pops<ST<MODE>> pops_of(void* const (&a)[14]) {
-    Pops<ST<MODE>> p;
-    for (int i = 0; i < 9; ++i) p.f[i] = (PT_GLOBAL ST<MODE>*)a[i];
-    for (int i = 0; i < 5; ++i) p.g[i] = (PT_GLOBAL ST<MODE>*)a[9 + i];
-    return p;
-}
-
-// ------------------------------------------------------ lattice kernels ----
-
-// Fused pull-stream + collide of every node of the lattice, one thread per
-// node of the pitched layout (flat 1-D grid, rows padded to the pitch).
-// Every node is written, so each wavefront stores whole cache lines: nodes
-// that are solid at t_n+1 receive values nobody reads (their slots facing the
-// fluid are rewritten by the next link pass), and newborn nodes are
-// overwritten by the refill kernel that runs after this one.  The stores are
-// non-temporal: B is not read again before the next step.  A non-finite
-// macroscopic value is an error at a node fluid at t_n (a node solid at t_n
-// pulls from inside the particle); the owner map is read only for a node
-// whose value is non-finite, so the check costs no traffic while the run is
-// sound.  The kernel reads nothing that the particle kernels of the same
-// step write, so those may run concurrently with it.
-template <int MODE>
-__device__ __forceinline__ void stream_collide_body(const RunStep& rs, unsigned bid) {
-    using S = Store<MODE>;
-    using R = typename S::R;
-    const LP& lp = rs.lp;
-    const Pops<ST<MODE>> A = pops_of<MODE>(rs.A), B = pops_of<MODE>(rs.B);
-    const size_t n0 = (size_t)bid * LAT_BLOCK + threadIdx.x;
-    const int y = (int)(n0 / (unsigned)lp.pitch);
-    const int x = (int)(n0 - (size_t)y * lp.pitch);
-    if (x >= lp.nx || y >= lp.ny) return;
-    const size_t k = (size_t)y * lp.pitch + x;
-    R s[9], t[5];
-    pull_node<S>(A, lp, x, y, s, t);
-    const CC<R> c(lp);
-    R rho, ux, uy, T;
-    collide<R>(c, s, t, rho, ux, uy, T);
-    if (!(isfinite(rho) && isfinite(T) && isfinite(ux) && isfinite(uy)) && gl(rs.Ocur)[k] == -1) {
-        // one report per wavefront, none once the bit is set: a run that
-        // has gone non-finite must not serialise on its status word
-        const unsigned long long m = __ballot(1);
-        if ((threadIdx.x & 63) == (unsigned)(__ffsll((long long)m) - 1) && !(gl(rs.status)[0] & ST_NONFINITE))
-            atomicOr(rs.status, ST_NONFINITE);
-    }
-    store_node<S, true>(B, lp, k, s, t);
-}
-
-// Equilibrium of the given macroscopic fields (host layout j*nx + i; NULL
-// pointers select the uniform rest state), collided once: the
-// post-collision state of t_0.
-template <int MODE, class FT>
-__global__ __launch_bounds__(LAT_BLOCK) void k_init(Pops<ST<MODE>> A, const int32_t* __restrict__ owner,
-                                                    const FT* rho_f, const FT* ux_f, const FT* uy_f,
-                                                    const FT* T_f, double rho_u, double T_u, LP lp) {
-    using S = Store<MODE>;
-    using R = typename S::R;
-    const int x = blockIdx.x * LAT_BLOCK + threadIdx.x;
-    const int y = blockIdx.y;
-    if (x >= lp.nx) return;
-    const size_t k = (size_t)y * lp.pitch + x;
-    const size_t h = (size_t)y * lp.nx + x;
-    R s[9], t[5];
-    if (owner[k] >= 0) {
-        for (int i = 0; i < 9; ++i) s[i] = (R)0;
-        for (int i = 0; i < 5; ++i) t[i] = (R)0;
-    } else {
-        const R rho = rho_f ? (R)rho_f[h] : (R)rho_u;
-        const R ux = ux_f ? (R)ux_f[h] : (R)0;
-        const R uy = uy_f ? (R)uy_f[h] : (R)0;
-        const R T = T_f ? (R)T_f[h] : (R)T_u;
-        feq_dev<R>(rho, (R)lp.rho0, ux, uy, s);
-        geq_dev<R>(T, (R)lp.T_sh, ux, uy, (R)lp.w5_0, (R)lp.w5_k, t);
-        const CC<R> c(lp);
-        R r_, u_, v_, T_;
-        collide<R>(c, s, t, r_, u_, v_, T_);
-    }
-    store_node<S>(A, lp, k, s, t);
-}
-
-// Pre-collision macroscopics from the post-collision state: rho and T are
-// collision invariants and the momentum gained the force, so
-// u = (j+ - F/2)/rho.  NaN inside solids.  Output: 4 planes of nx*ny (OT).
-template <int MODE, class OT>
-__global__ __launch_bounds__(LAT_BLOCK) void k_macros(Pops<ST<MODE>> A, const int32_t* __restrict__ owner,
-                                                      OT* out, LP lp) {
-    using S = Store<MODE>;
-    using R = typename S::R;
-    const int x = blockIdx.x * LAT_BLOCK + threadIdx.x;
-    const int y = blockIdx.y;
-    if (x >= lp.nx) return;
-    const size_t k = (size_t)y * lp.pitch + x;
-    const size_t n = (size_t)lp.nx * lp.ny, h = (size_t)y * lp.nx + x;
-    if (owner[k] >= 0) {
-        const OT nan = (OT)NAN;
-        out[h] = nan;
-        out[n + h] = nan;
-        out[2 * n + h] = nan;
-        out[3 * n + h] = nan;
-        return;
-    }
-    R s[9], t[5];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) s[i] = S::ld(A.f[i] + k) - (S::shifted ? (R)0 : w9<R>(i) * (R)lp.rho0);
-#pragma unroll
-    for (int i = 0; i < 5; ++i) t[i] = S::ld(A.g[i] + k);
-    R drho = (R)0, jx = (R)0, jy = (R)0, dT = (R)0;
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        drho += s[i];
-        jx += (R)EXd(i) * s[i];
-        jy += (R)EYd(i) * s[i];
-    }
-#pragma unroll
-    for (int i = 0; i < 5; ++i) dT += t[i];
-    const R rho = (R)lp.rho0 + drho;
-    const R T = (R)lp.T_sh + dT;
-    const R Fx = (R)lp.body_fx;
-    const R Fy = rho * (R)lp.gbeta * (T - (R)lp.T_ref);
-    out[h] = (OT)rho;
-    out[n + h] = (OT)((jx - (R)0.5 * Fx) / rho);
-    out[2 * n + h] = (OT)((jy - (R)0.5 * Fy) / rho);
-    out[3 * n + h] = (OT)T;
-}
 
 // ----------------------------------------------------- particle kernels ----
 // The per-particle kernels run one wavefront per particle (PPB particles per
@@ -210,7 +85,8 @@ __device__ __forceinline__ int slot_direction(int s, int nxw, int nyw) {
 }
 
 // LDS of one wavefront of k_links: the owner map over the window, the slot
-// array, then the compacted link list.
+// array, then the compacted link list.  links_slots is also the length of
+// each particle's segment of the link array.
 __host__ __device__ inline size_t links_win_ints(int nwin) { return (size_t)nwin * nwin; }
 __host__ __device__ inline size_t links_slots(int nwin) { return (size_t)(12 * nwin - 12); }
 __host__ __device__ inline size_t links_list_offset(int nwin) {
@@ -227,18 +103,15 @@ __host__ __device__ inline size_t links_wave_lds(int nwin) {
 //      neighbour owned by this particle is a link, written into its fixed
 //      slot; the slots are then compacted in slot order (ballot + prefix
 //      count within the wavefront);
-//  (c) one global atomic per block reserves the block's contiguous range of
-//      the link array; each particle's segment is contiguous, in slot order.
+//  (c) the list goes to the particle's fixed segment of the link array,
+//      12 N - 12 entries from p (12 N - 12): no atomics between particles.
 __device__ __forceinline__ void links_body(const RunStep& rs, unsigned bid, int ppb) {
     extern __shared__ uint2 smem[];
-    __shared__ unsigned wave_tot[4];
-    __shared__ unsigned block_base;
     const LP& lp = rs.lp;
     const PT_GLOBAL int32_t* __restrict__ Ocur = gl(rs.Ocur);
     const PState* __restrict__ Pc = rs.Pc;
     uint2* links = rs.links;
     int2* seg = rs.seg;
-    unsigned* counter = rs.counter;
     unsigned* status = rs.status;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int p = (int)bid * ppb + w;
@@ -305,31 +178,14 @@ __device__ __forceinline__ void links_body(const RunStep& rs, unsigned bid, int 
         }
         wave_lds_sync();
     }
-    if (lane == 0) wave_tot[w] = count;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned tot = 0;
-        for (int i = 0; i < ppb; ++i) tot += wave_tot[i];
-        unsigned base = tot ? atomicAdd(counter, tot) : 0u;
-        if ((unsigned long long)base + tot > (unsigned long long)lp.link_cap) {
-            atomicOr(status, ST_LINK_OVERFLOW);
-            base = 0xffffffffu;
-        }
-        block_base = base;
-    }
-    __syncthreads();
     if (!have_p) return;
-    unsigned start = block_base;
-    if (start == 0xffffffffu) {
-        count = 0;
-        start = 0;
-    }
-    for (int i = 0; i < w; ++i) start += wave_tot[i];
+    const size_t start = (size_t)p * links_slots(lp.nwin);
     for (unsigned i = lane; i < count; i += 64) st_u2(links + start + i, lk[i]);
     if (lane == 0) st_i2(seg + p, make_int2((int)start, (int)count));
 }
 
-// The link pass, one thread per link of the compacted array (Sec. 2.3-2.4):
+// The link pass, one thread per entry of the particles' link segments
+// (threads past a particle's link count return) (Sec. 2.3-2.4):
 // q from the circle, wall point x_w = x_f + q e_i and its rigid-body velocity
 // u_w, Bouzidi bounce-back f_ibar (Eqs. (9)-(10), with the linear and halfway
 // fallbacks) and, for axis links, the thermal wall g_ibar (Eqs. (11)-(12)),
@@ -342,7 +198,9 @@ __device__ __forceinline__ void link_pass_body(const RunStep& rs, unsigned bid) 
     using S = Store<MODE>;
     const LP& lp = rs.lp;
     const unsigned l = bid * 256u + threadIdx.x;
-    if (l >= gl(rs.counter)[0]) return;
+    const unsigned per = (unsigned)links_slots(lp.nwin);
+    const unsigned pp = l / per;
+    if (pp >= (unsigned)lp.np || l - pp * per >= (unsigned)ld_i2(rs.seg + pp).y) return;
     // population arrays picked straight from the run's pointer table (a
     // local copy indexed by the link direction would live in scratch)
     auto F = [&](int a) { return (const PT_GLOBAL ST<MODE>*)rs.A[a]; };
@@ -541,10 +399,6 @@ __device__ __forceinline__ void particles_body(const RunStep& rs, unsigned bid) 
         Ry += wy;
     }
     if (lane != 0) return;
-    if (p == 0) {
-        rs.counter[1] = rs.counter[0];
-        rs.counter[0] = 0u;
-    }
     PT_GLOBAL double* Fh = gl(rs.Fh);
     Fh[4 * p + 0] = hx;
     Fh[4 * p + 1] = hy;
@@ -753,17 +607,6 @@ __device__ __forceinline__ void refill_body(const RunStep& rs, unsigned bid) {
 // tab[bmap[b].x]).  Both call the same body, so a run computes the same bits
 // alone and in a batch.
 
-template <int MODE>
-__global__ __launch_bounds__(LAT_BLOCK) void k_stream_collide(RunStep rs) {
-    stream_collide_body<MODE>(rs, blockIdx.x);
-}
-template <int MODE>
-__global__ __launch_bounds__(LAT_BLOCK) void k_stream_collide_b(const RunStep* __restrict__ tab,
-                                                                const uint2* __restrict__ bmap) {
-    const uint2 m = bmap[blockIdx.x];
-    stream_collide_body<MODE>(tab[m.x], m.y);
-}
-
 __global__ __launch_bounds__(256) void k_links(RunStep rs, int ppb) { links_body(rs, blockIdx.x, ppb); }
 __global__ __launch_bounds__(256) void k_links_b(const RunStep* __restrict__ tab, const uint2* __restrict__ bmap,
                                                  int ppb) {
@@ -819,43 +662,6 @@ __global__ void k_link_q(const PState* __restrict__ Pc, const uint2* __restrict_
 
 // -------------------------------------------------------------- launchers ----
 
-static dim3 lattice_grid(const LP& lp) { return dim3((lp.nx + LAT_BLOCK - 1) / LAT_BLOCK, lp.ny); }
-
-#define PTLBM_DISPATCH(mode, CALL)                                      \
-    switch (mode) {                                                     \
-        case LBM_STORE_F64: { constexpr int M = LBM_STORE_F64; CALL; } break;             \
-        case LBM_STORE_F32: { constexpr int M = LBM_STORE_F32; CALL; } break;             \
-        case LBM_STORE_SHIFT_F32: { constexpr int M = LBM_STORE_SHIFT_F32; CALL; } break; \
-        case LBM_STORE_SHIFT_F16: { constexpr int M = LBM_STORE_SHIFT_F16; CALL; } break; \
-        case LBM_STORE_SHIFT_BF16: { constexpr int M = LBM_STORE_SHIFT_BF16; CALL; } break; \
-        default: return hipErrorInvalidValue;                           \
-    }
-
-hipError_t launch_init(const DevState& d, int cur, const void* rho, const void* ux, const void* uy,
-                       const void* T, bool f64, double rho_u, double T_u, hipStream_t st) {
-    if (f64) {
-        PTLBM_DISPATCH(d.mode, (k_init<M, double><<<lattice_grid(d.lp), LAT_BLOCK, 0, st>>>(
-                                   pops_of<M>(d.S[cur]), d.O[cur], (const double*)rho, (const double*)ux,
-                                   (const double*)uy, (const double*)T, rho_u, T_u, d.lp)));
-    } else {
-        PTLBM_DISPATCH(d.mode, (k_init<M, float><<<lattice_grid(d.lp), LAT_BLOCK, 0, st>>>(
-                                   pops_of<M>(d.S[cur]), d.O[cur], (const float*)rho, (const float*)ux,
-                                   (const float*)uy, (const float*)T, rho_u, T_u, d.lp)));
-    }
-    return hipGetLastError();
-}
-
-hipError_t launch_macros(const DevState& d, int cur, void* out, hipStream_t st) {
-    if (d.mode == LBM_STORE_F64) {
-        k_macros<LBM_STORE_F64, double><<<lattice_grid(d.lp), LAT_BLOCK, 0, st>>>(
-            pops_of<LBM_STORE_F64>(d.S[cur]), d.O[cur], (double*)out, d.lp);
-    } else {
-        PTLBM_DISPATCH(d.mode, (k_macros<M, float><<<lattice_grid(d.lp), LAT_BLOCK, 0, st>>>(
-                                   pops_of<M>(d.S[cur]), d.O[cur], (float*)out, d.lp)));
-    }
-    return hipGetLastError();
-}
-
 int links_particles_per_block(int nwin) {
     const size_t per = links_wave_lds(nwin);
     int ppb = (int)(65536 / per);
@@ -885,7 +691,7 @@ hipError_t launch_step(int k, const RunStep& R, int mode, hipStream_t st) {
         case SK_PASS: PTLBM_DISPATCH(mode, (k_link_pass<M><<<nb, 256, 0, st>>>(R))); break;
         case SK_PARTICLES: k_particles<<<nb, 256, 0, st>>>(R); break;
         case SK_MASK: k_mask_mark<<<nb, 256, 0, st>>>(R); break;
-        case SK_LATTICE: PTLBM_DISPATCH(mode, (k_stream_collide<M><<<nb, LAT_BLOCK, 0, st>>>(R))); break;
+        case SK_LATTICE: return launch_lattice(R, mode, nb, st);
         case SK_REFILL: PTLBM_DISPATCH(mode, (k_refill<M><<<nb, 256, 0, st>>>(R))); break;
         default: return hipErrorInvalidValue;
     }
@@ -902,9 +708,7 @@ hipError_t launch_step_batch(int k, const BatchLaunch& b, hipStream_t st) {
         case SK_PASS: PTLBM_DISPATCH(b.mode, (k_link_pass_b<M><<<nb, 256, 0, st>>>(b.tab, bm))); break;
         case SK_PARTICLES: k_particles_b<<<nb, 256, 0, st>>>(b.tab, bm); break;
         case SK_MASK: k_mask_mark_b<<<nb, 256, 0, st>>>(b.tab, bm); break;
-        case SK_LATTICE:
-            PTLBM_DISPATCH(b.mode, (k_stream_collide_b<M><<<nb, LAT_BLOCK, 0, st>>>(b.tab, bm)));
-            break;
+        case SK_LATTICE: return launch_lattice_batch(b.tab, bm, nb, b.mode, st);
         case SK_REFILL: PTLBM_DISPATCH(b.mode, (k_refill_b<M><<<nb, 256, 0, st>>>(b.tab, bm))); break;
         default: return hipErrorInvalidValue;
     }
@@ -928,10 +732,10 @@ hipError_t launch_bin_init(const DevState& d, const PState* P, int bin_parity, h
     return hipGetLastError();
 }
 
-hipError_t launch_link_q(const DevState& d, int ring, int nlinks, int32_t* node, int32_t* dir, int32_t* part,
-                         double* q, hipStream_t st) {
+hipError_t launch_link_q(const DevState& d, int ring, const uint2* links, int nlinks, int32_t* node,
+                         int32_t* dir, int32_t* part, double* q, hipStream_t st) {
     if (nlinks <= 0) return hipSuccess;
-    k_link_q<<<(nlinks + 255) / 256, 256, 0, st>>>(d.P[ring], d.links, nlinks, node, dir, part, q, d.lp);
+    k_link_q<<<(nlinks + 255) / 256, 256, 0, st>>>(d.P[ring], links, nlinks, node, dir, part, q, d.lp);
     return hipGetLastError();
 }
 

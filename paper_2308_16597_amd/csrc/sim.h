@@ -43,6 +43,9 @@ struct lbm_sim {
     int np = 0;
     int64_t steps = 0;
     uint64_t generation = 0;  // bumped whenever the particle count changes
+    hipGraphExec_t cycle_graph = nullptr;  // six overlapped steps from cycle_state
+    int cycle_state = -1;
+    uint64_t cycle_generation = 0;
     std::string err;
 };
 

@@ -184,3 +184,23 @@ def test_paper_scale_parity_full_lattice():
     ep = compare_particles(sim.particles(), orc.particles(), u_floor=U_FF)
     _say("paper scale after 2 steps", ef, ep)
     compare_links(sim.links(), orc.links(), q_abs=1e-12)
+
+
+def test_dense_workload_parity_full_lattice():
+    """The dense workload (4096^2, 64000 particles of diameter 10, 30 % solid,
+    Ra 1e8, gaps >= 3) in the launch configuration the benchmark times, FP64
+    storage: link set at t_0 bit-exact (about 6.2 M links), then every field
+    and particle after one step within 1e-12 of the oracle."""
+    kw = P.workload_params("dense")
+    w = P.WORKLOADS["dense"]
+    rows = lbm_inputs.rsa_particles(w["nx"], w["ny"], w["n"], w["d"], w["gap"], w["seed"])
+    sim, orc = make_pair(**kw)
+    sim.set_particles(rows)
+    orc.set_particles(rows)
+    n, dq = compare_links(sim.links(), orc.links())
+    _say("dense links", n, "max dq", dq)
+    sim.step(1)
+    orc.step(1)
+    ef = compare_fields(sim.fields(), orc.fields(), u_floor=U_FF)
+    ep = compare_particles(sim.particles(), orc.particles(), u_floor=U_FF)
+    _say("dense after 1 step", ef, ep)
