@@ -151,8 +151,8 @@ def main():
     ap.add_argument("--serve-chunk", type=int, default=120)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the lattice would shard as y-slabs; see the design notes)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
+              "(the lattice would shard as y-slabs with a three-row halo)", file=sys.stderr)
         sys.exit(2)
 
     import torch

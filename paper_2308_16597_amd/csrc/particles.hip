@@ -5,16 +5,16 @@
 //
 // One step n -> n+1 (cur = time level n, ring = particle slot of t_n); the
 // links of t_n were collected at the end of the step before:
-//   k_link_pass     one thread per link slot of the particles' segments: q, wall
+//   k_link_pass     one block per particle, a thread per link: q, wall
 //                   velocity, Bouzidi bounce-back (Eqs. (9)-(10)) and the
 //                   thermal wall (Eqs. (11)-(12)) written into the solid
-//                   slots of the post-collision state; the link's momentum
-//                   exchange (Eqs. (13)-(14)) in FP64.
+//                   slots of the post-collision state; the momentum exchange
+//                   (Eqs. (13)-(14)) summed over the particle in FP64 in a
+//                   fixed order.
 //   k_particles     one wavefront per particle: clear its t_n-1 marks in the
-//                   owner-map buffer of t_n+1; FP64 sum of its links'
-//                   momentum exchange in a fixed order, repulsion (Eq. (15))
-//                   summed in ascending partner order over a cell grid, net
-//                   weight, Newton-Euler update.
+//                   owner-map buffer of t_n+1; repulsion (Eq. (15)) summed
+//                   in ascending partner order over a cell grid, net weight,
+//                   Newton-Euler update.
 //   k_mask_mark     one wavefront per particle: owner map of t_n+1 by atomic
 //                   min; newborn-node candidates.
 //   k_stream_collide  one thread per node: fused pull-stream + D2Q9/D2Q5 MRT
@@ -184,23 +184,24 @@ __device__ __forceinline__ void links_body(const RunStep& rs, unsigned bid, int 
     if (lane == 0) st_i2(seg + p, make_int2((int)start, (int)count));
 }
 
-// The link pass, one thread per entry of the particles' link segments
-// (threads past a particle's link count return) (Sec. 2.3-2.4):
-// q from the circle, wall point x_w = x_f + q e_i and its rigid-body velocity
-// u_w, Bouzidi bounce-back f_ibar (Eqs. (9)-(10), with the linear and halfway
-// fallbacks) and, for axis links, the thermal wall g_ibar (Eqs. (11)-(12)),
-// both written into the solid slots x_f + e_i of the post-collision state A
-// that the pull of x_f reads; the link's momentum exchange
-// f_i^+ (e_i - u_w) - f_ibar (e_ibar - u_w) and its torque about X_c go to
-// contrib[l] in FP64.  All gathers are issued before any arithmetic.
+// The link pass, one block of PASS_BLOCK threads per particle, a thread per
+// link of its segment (Sec. 2.3-2.4): q from the circle, wall point
+// x_w = x_f + q e_i and its rigid-body velocity u_w, Bouzidi bounce-back
+// f_ibar (Eqs. (9)-(10), with the linear and halfway fallbacks) and, for
+// axis links, the thermal wall g_ibar (Eqs. (11)-(12)), both written into
+// the solid slots x_f + e_i of the post-collision state A that the pull of
+// x_f reads; the link's momentum exchange f_i^+ (e_i - u_w) -
+// f_ibar (e_ibar - u_w) and its torque about X_c, summed in FP64 over the
+// particle in a fixed order (each thread over its links, a butterfly in each
+// wavefront, the wavefronts in order) into Fh[p].  All gathers of a link are
+// issued before any arithmetic.
+constexpr int PASS_BLOCK = 256;
+
 template <int MODE>
-__device__ __forceinline__ void link_pass_body(const RunStep& rs, unsigned bid) {
+__device__ __forceinline__ void link_pass_link(const RunStep& rs, const PState& P, unsigned l, double& hx,
+                                               double& hy, double& hz) {
     using S = Store<MODE>;
     const LP& lp = rs.lp;
-    const unsigned l = bid * 256u + threadIdx.x;
-    const unsigned per = (unsigned)links_slots(lp.nwin);
-    const unsigned pp = l / per;
-    if (pp >= (unsigned)lp.np || l - pp * per >= (unsigned)ld_i2(rs.seg + pp).y) return;
     // population arrays picked straight from the run's pointer table (a
     // local copy indexed by the link direction would live in scratch)
     auto F = [&](int a) { return (const PT_GLOBAL ST<MODE>*)rs.A[a]; };
@@ -208,7 +209,7 @@ __device__ __forceinline__ void link_pass_body(const RunStep& rs, unsigned bid) 
     const PT_GLOBAL int32_t* __restrict__ Ocur = gl(rs.Ocur);
     const int nx = lp.nx, pitch = lp.pitch;
     const uint2 L = ld_u2(rs.links + l);
-    const int x = (int)(L.x & 0xffffu), y = (int)(L.x >> 16), i = (int)(L.y & 15u), p = (int)(L.y >> 4);
+    const int x = (int)(L.x & 0xffffu), y = (int)(L.x >> 16), i = (int)(L.y & 15u);
     const int ib = OPPd(i), ex = EXd(i), ey = EYd(i);
     const int x1 = wrap_x(x - ex, nx), y1 = y - ey;
     const int x2 = wrap_x(x - 2 * ex, nx), y2 = y - 2 * ey;
@@ -216,7 +217,6 @@ __device__ __forceinline__ void link_pass_body(const RunStep& rs, unsigned bid) 
     const size_t k = (size_t)y * pitch + x;
     const size_t k1 = in1 ? (size_t)y1 * pitch + x1 : k;
     const size_t k2 = in2 ? (size_t)y2 * pitch + x2 : k;
-    const PState P = ld_state(rs.Pc + p);
     const int32_t o1 = Ocur[k1], o2 = Ocur[k2];
     const double fi = (double)S::ld(F(i) + k), fib = (double)S::ld(F(ib) + k);
     const double fi1 = (double)S::ld(F(i) + k1), fib1 = (double)S::ld(F(ib) + k1);
@@ -248,7 +248,45 @@ __device__ __forceinline__ void link_pass_body(const RunStep& rs, unsigned bid) 
     const double Fi = fi + w9i * shf, Fb = (double)(typename S::R)fnew + w9i * shf;
     const double dFx = Fi * (ex - uwx) - Fb * (-ex - uwx);
     const double dFy = Fi * (ey - uwy) - Fb * (-ey - uwy);
-    st_d4(rs.contrib + l, make_double4(dFx, dFy, rx * dFy - ry * dFx, 0.0));   // Eq. (14), z component
+    hx += dFx;
+    hy += dFy;
+    hz += rx * dFy - ry * dFx;   // Eq. (14), z component
+}
+
+template <int MODE>
+__device__ __forceinline__ void link_pass_body(const RunStep& rs, unsigned bid) {
+    __shared__ double part[PASS_BLOCK / 64][3];
+    const int p = (int)bid;
+    if (p >= rs.lp.np) return;   // the whole block
+    const int2 sg = ld_i2(rs.seg + p);
+    const PState P = ld_state(rs.Pc + p);
+    double hx = 0.0, hy = 0.0, hz = 0.0;
+    for (int t = (int)threadIdx.x; t < sg.y; t += PASS_BLOCK)
+        link_pass_link<MODE>(rs, P, (unsigned)(sg.x + t), hx, hy, hz);
+    for (int off = 32; off > 0; off >>= 1) {
+        hx += __shfl_xor(hx, off);
+        hy += __shfl_xor(hy, off);
+        hz += __shfl_xor(hz, off);
+    }
+    const int w = (int)threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        part[w][0] = hx;
+        part[w][1] = hy;
+        part[w][2] = hz;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double sx = 0.0, sy = 0.0, sz = 0.0;
+        for (int j = 0; j < PASS_BLOCK / 64; ++j) {
+            sx += part[j][0];
+            sy += part[j][1];
+            sz += part[j][2];
+        }
+        PT_GLOBAL double* Fh = gl(rs.Fh);
+        Fh[4 * p + 0] = sx;
+        Fh[4 * p + 1] = sy;
+        Fh[4 * p + 2] = sz;
+    }
 }
 
 // Spring repulsion of Eq. (15) on particle (xp, yp, rp) from (xq, yq, rq):
@@ -292,8 +330,7 @@ __global__ __launch_bounds__(256) void k_bin_init(const PState* __restrict__ P, 
 }
 
 // Particle update, one wavefront per particle (Sec. 2.2, 2.4):
-//  - the momentum exchange of the particle's links, summed in FP64 over its
-//    segment in a fixed order (lane-strided, then a butterfly), into Fh[p];
+//  - the momentum-exchange force and torque of the link pass, Fh[p];
 //  - repulsion: partners from the cell grid of t_n (lane = one slot of the
 //    3 x 3 cells around the particle), summed in ascending partner index (the
 //    order of a plain loop over all partners); walls; net weight;
@@ -320,19 +357,8 @@ __device__ __forceinline__ void particles_body(const RunStep& rs, unsigned bid) 
             }
     }
     const PState P = ld_state(Pc + p);
-    const int2 sg = ld_i2(rs.seg + p);
-    double hx = 0.0, hy = 0.0, hz = 0.0;
-    for (int l = lane; l < sg.y; l += 64) {
-        const double4 c = ld_d4(rs.contrib + sg.x + l);
-        hx += c.x;
-        hy += c.y;
-        hz += c.z;
-    }
-    for (int off = 32; off > 0; off >>= 1) {
-        hx += __shfl_xor(hx, off);
-        hy += __shfl_xor(hy, off);
-        hz += __shfl_xor(hz, off);
-    }
+    const PT_GLOBAL double* Fh = gl(rs.Fh);
+    const double hx = Fh[4 * p + 0], hy = Fh[4 * p + 1], hz = Fh[4 * p + 2];   // from the link pass
     double Rx = 0.0, Ry = 0.0;
     if (lp.repulsion && particle_ok(P, lp)) {
         const int c0 = cell_of(P, lp);
@@ -399,10 +425,6 @@ __device__ __forceinline__ void particles_body(const RunStep& rs, unsigned bid) 
         Ry += wy;
     }
     if (lane != 0) return;
-    PT_GLOBAL double* Fh = gl(rs.Fh);
-    Fh[4 * p + 0] = hx;
-    Fh[4 * p + 1] = hy;
-    Fh[4 * p + 2] = hz;
     const double Fg = -(lp.rho_ratio - 1.0) * lp.rho0 * kPi * P.r * P.r * lp.gravity;
     const double Fx = hx + Rx;
     const double Fy = (hy + Ry) + Fg;
@@ -615,9 +637,9 @@ __global__ __launch_bounds__(256) void k_links_b(const RunStep* __restrict__ tab
 }
 
 template <int MODE>
-__global__ __launch_bounds__(256) void k_link_pass(RunStep rs) { link_pass_body<MODE>(rs, blockIdx.x); }
+__global__ __launch_bounds__(PASS_BLOCK) void k_link_pass(RunStep rs) { link_pass_body<MODE>(rs, blockIdx.x); }
 template <int MODE>
-__global__ __launch_bounds__(256) void k_link_pass_b(const RunStep* __restrict__ tab,
+__global__ __launch_bounds__(PASS_BLOCK) void k_link_pass_b(const RunStep* __restrict__ tab,
                                                      const uint2* __restrict__ bmap) {
     const uint2 m = bmap[blockIdx.x];
     link_pass_body<MODE>(tab[m.x], m.y);
@@ -673,8 +695,7 @@ size_t links_block_lds(int nwin, int ppb) { return (size_t)ppb * links_wave_lds(
 unsigned run_blocks(int c, const LP& lp, int ppb) {
     switch (c) {
         case GC_LINKS: return lp.np > 0 ? (unsigned)((lp.np + ppb - 1) / ppb) : 0u;
-        case GC_PASS:   // a particle has at most 12 nwin - 12 links
-            return lp.np > 0 ? (unsigned)(((size_t)lp.np * (12 * lp.nwin - 12) + 255) / 256) : 0u;
+        case GC_PASS: return (unsigned)lp.np;   // a block per particle
         case GC_WAVE: return (unsigned)((lp.np + 3) / 4);
         default: return (unsigned)(((size_t)lp.pitch * lp.ny + LAT_BLOCK - 1) / LAT_BLOCK);
     }
@@ -688,7 +709,7 @@ hipError_t launch_step(int k, const RunStep& R, int mode, hipStream_t st) {
         case SK_COLLECT:   // R: the RunStep of the step whose links are collected
             k_links<<<nb, 64 * ppb, links_block_lds(R.lp.nwin, ppb), st>>>(R, ppb);
             break;
-        case SK_PASS: PTLBM_DISPATCH(mode, (k_link_pass<M><<<nb, 256, 0, st>>>(R))); break;
+        case SK_PASS: PTLBM_DISPATCH(mode, (k_link_pass<M><<<nb, PASS_BLOCK, 0, st>>>(R))); break;
         case SK_PARTICLES: k_particles<<<nb, 256, 0, st>>>(R); break;
         case SK_MASK: k_mask_mark<<<nb, 256, 0, st>>>(R); break;
         case SK_LATTICE: return launch_lattice(R, mode, nb, st);
@@ -705,7 +726,7 @@ hipError_t launch_step_batch(int k, const BatchLaunch& b, hipStream_t st) {
     const uint2* bm = b.bmap[c];
     switch (k) {
         case SK_COLLECT: k_links_b<<<nb, 64 * b.ppb, b.lds, st>>>(b.tab_next, bm, b.ppb); break;
-        case SK_PASS: PTLBM_DISPATCH(b.mode, (k_link_pass_b<M><<<nb, 256, 0, st>>>(b.tab, bm))); break;
+        case SK_PASS: PTLBM_DISPATCH(b.mode, (k_link_pass_b<M><<<nb, PASS_BLOCK, 0, st>>>(b.tab, bm))); break;
         case SK_PARTICLES: k_particles_b<<<nb, 256, 0, st>>>(b.tab, bm); break;
         case SK_MASK: k_mask_mark_b<<<nb, 256, 0, st>>>(b.tab, bm); break;
         case SK_LATTICE: return launch_lattice_batch(b.tab, bm, nb, b.mode, st);
