@@ -144,6 +144,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--addressing", default="indirect", choices=["indirect", "direct"],
+                    help="link pass by indirect (default) or direct addressing (the ablation)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run plain copies of this many bytes (counter calibration)")
     ap.add_argument("--serve-requests", type=int, default=256)
@@ -167,6 +169,8 @@ def main():
     log(f"[bench] {args.workload} {nx}x{ny} n={w['n']} d={w['d']} storage={args.storage}")
     sim = lbm.Sim(p)
     sim.seed_particles(w["n"], w["d"], w["gap"], w["seed"])
+    if args.addressing != "indirect":
+        sim.set_addressing(args.addressing)
     sim.step(args.warmup)
     sim.sync()
     log(f"[bench] warmup {args.warmup} steps done")
@@ -207,7 +211,8 @@ def main():
         "config": {
             "workload": f"{args.workload}: {nx}x{ny} periodic-x channel, {w['n']} hot particles "
                         f"d={w['d']:g}, rho_p/rho_f={w['rho_ratio']}, Pr={w['Pr']}, Ra={w['Ra']:g}, "
-                        f"{args.storage} storage, links rebuilt every step",
+                        f"{args.storage} storage, links rebuilt every step"
+                        + ("" if args.addressing == "indirect" else ", direct link addressing"),
             "nx": nx, "ny": ny, "particles": w["n"], "diameter": w["d"], "storage": args.storage,
             "parallelism": "single GPU",
         },

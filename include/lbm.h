@@ -180,6 +180,17 @@ int lbm_set_particles(lbm_handle h, int32_t n, const double* rows7);
 int lbm_set_equilibrium(lbm_handle h, const double* rho, const double* ux, const double* uy,
                         const double* T);
 
+/* Link addressing of the link pass (Sec. 3 compares the two).
+ * LBM_LINKS_INDIRECT (default): the links are collected into each
+ * particle's segment of the index array and the pass runs over them.
+ * LBM_LINKS_DIRECT: no collection; the pass runs one thread per lattice
+ * node, each fluid node looking for particle neighbours, with FP64 atomic
+ * force sums (their order, and so the last bits, vary between runs).  Kept
+ * as the ablation; lbm_step_many rejects runs in this mode.  Waits; returns
+ * LBM_EINVAL for an unknown mode. */
+enum { LBM_LINKS_INDIRECT = 0, LBM_LINKS_DIRECT = 1 };
+int lbm_set_addressing(lbm_handle h, int32_t mode);
+
 /* Enqueue nsteps steps on the handle's stream and return.  Within a step,
  * the particle update, the owner map of t_n+1 and the link collection of
  * t_n+1 run on a second stream of the library's, concurrently with the

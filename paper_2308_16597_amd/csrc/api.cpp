@@ -60,6 +60,7 @@ Layout make_layout(const lbm_params& p) {
     L.link_cap = cap * (size_t)(12 * L.nwin - 12);
     L.off_P = off; off = round_up(off + 3 * cap * sizeof(PState), kAlign);
     L.off_Fh = off; off = round_up(off + cap * 4 * sizeof(double), kAlign);
+    L.off_Fa = off; off = round_up(off + cap * 4 * sizeof(double), kAlign);
     L.off_seg = off; off = round_up(off + cap * sizeof(int2), kAlign);
     L.off_links = off; off = round_up(off + L.link_cap * sizeof(uint2), kAlign);
     // read_links: the gathered list, then node, direction, particle, q
@@ -181,6 +182,7 @@ void fill_lp(lbm_sim* h) {
     lp.np = 0;
     lp.nwin = h->L.nwin;
     lp.link_cap = (int)h->L.link_cap;
+    lp.direct = 0;
     lp.ncx = h->L.ncx;
     lp.ncy = h->L.ncy;
     lp.ncells = p.max_particles > 0 ? h->L.ncx * h->L.ncy : 0;
@@ -239,6 +241,7 @@ int create_common(const lbm_params* p, void* dev_ptr, size_t bytes, void* stream
     const size_t cap = (size_t)(p->max_particles > 0 ? p->max_particles : 0);
     for (int r = 0; r < 3; ++r) d.P[r] = (PState*)(h->base + L.off_P) + r * cap;
     d.Fh = (double*)(h->base + L.off_Fh);
+    d.Fa = (double*)(h->base + L.off_Fa);
     d.seg = (int2*)(h->base + L.off_seg);
     d.links = (uint2*)(h->base + L.off_links);
     d.status = (unsigned*)(h->base + L.off_status);
@@ -292,6 +295,7 @@ RunStep make_runstep(const lbm_sim* h, int c, int r, int bp) {
     R.Pc = d.P[r];
     R.Pn = d.P[ring_next(r)];
     R.Fh = d.Fh;
+    R.Fa = d.Fa;
     R.links = d.links;
     R.seg = d.seg;
     R.status = d.status;
@@ -569,6 +573,7 @@ int lbm_set_particles(lbm_handle h, int32_t n, const double* rows7) {
         for (int r = 0; r < 3; ++r)
             HIPCHK(h, hipMemcpyAsync(d.P[r], P.data(), sizeof(PState) * n, hipMemcpyHostToDevice, st));
         HIPCHK(h, hipMemsetAsync(d.Fh, 0, sizeof(double) * 4 * n, st));
+        HIPCHK(h, hipMemsetAsync(d.Fa, 0, sizeof(double) * 4 * n, st));
         HIPCHK(h, hipMemsetAsync(d.seg, 0, sizeof(int2) * n, st));
         for (int b = 0; b < 2; ++b)
             HIPCHK(h, hipMemsetAsync(d.bcnt[b], 0, sizeof(unsigned) * (size_t)d.lp.ncells, st));
@@ -581,6 +586,25 @@ int lbm_set_particles(lbm_handle h, int32_t n, const double* rows7) {
     HIPCHK(h, launch_init(d, 0, nullptr, nullptr, nullptr, nullptr, true, h->p.rho0, h->p.T_fluid0, st));
     HIPCHK(h, hipStreamSynchronize(st));
     h->steps = 0;
+    return LBM_OK;
+}
+
+int lbm_set_addressing(lbm_handle h, int32_t mode) {
+    if (!h) return LBM_EINVAL;
+    if (mode != LBM_LINKS_INDIRECT && mode != LBM_LINKS_DIRECT)
+        return fail(h, LBM_EINVAL, "unknown link addressing %d", mode);
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    forget_batches(h);
+    h->generation += 1;   // captured graphs hold the old constants
+    DevState& d = h->d;
+    d.lp.direct = mode == LBM_LINKS_DIRECT ? 1 : 0;
+    if (h->np > 0) {
+        // a direct pass adds into zeroed sums; an indirect step needs the
+        // links of the current state
+        HIPCHK(h, hipMemsetAsync(d.Fa, 0, sizeof(double) * 4 * h->np, h->stream));
+        if (!d.lp.direct) HIPCHK(h, launch_step(SK_COLLECT, current_runstep(h), d.mode, h->stream));
+    }
+    HIPCHK(h, hipStreamSynchronize(h->stream));
     return LBM_OK;
 }
 
@@ -704,6 +728,11 @@ int lbm_read_links(lbm_handle h, int32_t* node, int32_t* dir, int32_t* particle,
     if (n_out) *n_out = 0;
     if (h->np == 0) return LBM_OK;
     DevState& d = h->d;
+    if (d.lp.direct) {   // direct addressing collects nothing: collect now
+        RunStep R = current_runstep(h);
+        R.lp.direct = 0;
+        HIPCHK(h, launch_step(SK_COLLECT, R, d.mode, h->stream));
+    }
     // the links of the current state were collected at the end of the last
     // step (or by lbm_set_particles), each particle's at the front of its
     // own segment; gather them into one list on the host

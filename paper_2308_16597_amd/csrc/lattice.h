@@ -87,6 +87,7 @@ struct LP {
     double particle_T, rho_ratio, gravity, rep_eps, rep_range;
     int repulsion, np, nwin;           // particles, window edge capacity
     int link_cap;
+    int direct;                        // link pass by direct addressing (ablation)
     int ncx, ncy, ncells;              // neighbour-search cell grid
 };
 

@@ -19,6 +19,7 @@ struct DevState {
     int32_t* O[2];               // owner maps
     PState* P[3];                // particle ring (old, current, next rotate)
     double* Fh;                  // per-particle momentum-exchange force/torque (x, y, z, pad)
+    double* Fa;                  // the link pass's sums (x, y, z, pad), read by k_particles
     uint2* links;                // link array: particle p's links at p (12 nwin - 12)
     int2* seg;                   // per-particle {start, count}
     unsigned* status;            // device error bits
@@ -42,6 +43,7 @@ struct RunStep {
     const PState* Pc;            // particles at t_n
     PState* Pn;                  // particles at t_n+1
     double* Fh;
+    double* Fa;
     uint2* links;
     int2* seg;
     unsigned* status;

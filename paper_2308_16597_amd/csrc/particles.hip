@@ -197,9 +197,10 @@ __device__ __forceinline__ void links_body(const RunStep& rs, unsigned bid, int 
 // issued before any arithmetic.
 constexpr int PASS_BLOCK = 256;
 
+// One link: fluid node (x, y), direction i towards particle P.
 template <int MODE>
-__device__ __forceinline__ void link_pass_link(const RunStep& rs, const PState& P, unsigned l, double& hx,
-                                               double& hy, double& hz) {
+__device__ __forceinline__ void link_pass_link(const RunStep& rs, const PState& P, int x, int y, int i,
+                                               double& hx, double& hy, double& hz) {
     using S = Store<MODE>;
     const LP& lp = rs.lp;
     // population arrays picked straight from the run's pointer table (a
@@ -208,8 +209,6 @@ __device__ __forceinline__ void link_pass_link(const RunStep& rs, const PState& 
     auto Fw = [&](int a) { return (PT_GLOBAL ST<MODE>*)rs.A[a]; };
     const PT_GLOBAL int32_t* __restrict__ Ocur = gl(rs.Ocur);
     const int nx = lp.nx, pitch = lp.pitch;
-    const uint2 L = ld_u2(rs.links + l);
-    const int x = (int)(L.x & 0xffffu), y = (int)(L.x >> 16), i = (int)(L.y & 15u);
     const int ib = OPPd(i), ex = EXd(i), ey = EYd(i);
     const int x1 = wrap_x(x - ex, nx), y1 = y - ey;
     const int x2 = wrap_x(x - 2 * ex, nx), y2 = y - 2 * ey;
@@ -261,8 +260,10 @@ __device__ __forceinline__ void link_pass_body(const RunStep& rs, unsigned bid) 
     const int2 sg = ld_i2(rs.seg + p);
     const PState P = ld_state(rs.Pc + p);
     double hx = 0.0, hy = 0.0, hz = 0.0;
-    for (int t = (int)threadIdx.x; t < sg.y; t += PASS_BLOCK)
-        link_pass_link<MODE>(rs, P, (unsigned)(sg.x + t), hx, hy, hz);
+    for (int t = (int)threadIdx.x; t < sg.y; t += PASS_BLOCK) {
+        const uint2 L = ld_u2(rs.links + sg.x + t);
+        link_pass_link<MODE>(rs, P, (int)(L.x & 0xffffu), (int)(L.x >> 16), (int)(L.y & 15u), hx, hy, hz);
+    }
     for (int off = 32; off > 0; off >>= 1) {
         hx += __shfl_xor(hx, off);
         hy += __shfl_xor(hy, off);
@@ -282,10 +283,44 @@ __device__ __forceinline__ void link_pass_body(const RunStep& rs, unsigned bid) 
             sy += part[j][1];
             sz += part[j][2];
         }
-        PT_GLOBAL double* Fh = gl(rs.Fh);
-        Fh[4 * p + 0] = sx;
-        Fh[4 * p + 1] = sy;
-        Fh[4 * p + 2] = sz;
+        PT_GLOBAL double* Fa = gl(rs.Fa);
+        Fa[4 * p + 0] = sx;
+        Fa[4 * p + 1] = sy;
+        Fa[4 * p + 2] = sz;
+    }
+}
+
+// The direct-addressing link pass, kept as the ablation of Sec. 3's
+// comparison: one thread per lattice node, no link collection; a fluid node
+// tests its 8 neighbours in the owner map and handles each link it finds as
+// above, adding the link's force and torque to the particle's sums with
+// FP64 atomics (so their summation order, and the last bits, vary from run
+// to run).  Most threads find no link: the load imbalance the indirect
+// scheme removes.
+template <int MODE>
+__device__ __forceinline__ void link_pass_direct_body(const RunStep& rs, unsigned bid) {
+    const LP& lp = rs.lp;
+    const size_t n0 = (size_t)bid * LAT_BLOCK + threadIdx.x;
+    const int y = (int)(n0 / (unsigned)lp.pitch);
+    const int x = (int)(n0 - (size_t)y * lp.pitch);
+    if (x >= lp.nx || y >= lp.ny) return;
+    const PT_GLOBAL int32_t* __restrict__ Ocur = gl(rs.Ocur);
+    if (Ocur[(size_t)y * lp.pitch + x] != -1) return;
+    int own[9];
+#pragma unroll
+    for (int d = 1; d < 9; ++d) {
+        const int yy = y + EYd(d);
+        own[d] = in_rows(yy, lp) ? Ocur[(size_t)yy * lp.pitch + wrap_x(x + EXd(d), lp.nx)] : -1;
+    }
+    for (int d = 1; d < 9; ++d) {
+        if (own[d] < 0) continue;
+        const PState P = ld_state(rs.Pc + own[d]);
+        double hx = 0.0, hy = 0.0, hz = 0.0;
+        link_pass_link<MODE>(rs, P, x, y, d, hx, hy, hz);
+        double* Fa = rs.Fa + 4 * (size_t)own[d];
+        atomicAdd(Fa + 0, hx);
+        atomicAdd(Fa + 1, hy);
+        atomicAdd(Fa + 2, hz);
     }
 }
 
@@ -357,8 +392,8 @@ __device__ __forceinline__ void particles_body(const RunStep& rs, unsigned bid) 
             }
     }
     const PState P = ld_state(Pc + p);
-    const PT_GLOBAL double* Fh = gl(rs.Fh);
-    const double hx = Fh[4 * p + 0], hy = Fh[4 * p + 1], hz = Fh[4 * p + 2];   // from the link pass
+    PT_GLOBAL double* Fa = gl(rs.Fa);
+    const double hx = Fa[4 * p + 0], hy = Fa[4 * p + 1], hz = Fa[4 * p + 2];   // from the link pass
     double Rx = 0.0, Ry = 0.0;
     if (lp.repulsion && particle_ok(P, lp)) {
         const int c0 = cell_of(P, lp);
@@ -421,10 +456,18 @@ __device__ __forceinline__ void particles_body(const RunStep& rs, unsigned bid) 
                 wy -= C / lp.rep_eps * (t * t);
             }
         }
-        Rx += 0.0;
         Ry += wy;
     }
     if (lane != 0) return;
+    PT_GLOBAL double* Fh = gl(rs.Fh);
+    Fh[4 * p + 0] = hx;
+    Fh[4 * p + 1] = hy;
+    Fh[4 * p + 2] = hz;
+    if (lp.direct) {   // the direct pass adds into Fa: start the next step at zero
+        Fa[4 * p + 0] = 0.0;
+        Fa[4 * p + 1] = 0.0;
+        Fa[4 * p + 2] = 0.0;
+    }
     const double Fg = -(lp.rho_ratio - 1.0) * lp.rho0 * kPi * P.r * P.r * lp.gravity;
     const double Fx = hx + Rx;
     const double Fy = (hy + Ry) + Fg;
@@ -639,6 +682,10 @@ __global__ __launch_bounds__(256) void k_links_b(const RunStep* __restrict__ tab
 template <int MODE>
 __global__ __launch_bounds__(PASS_BLOCK) void k_link_pass(RunStep rs) { link_pass_body<MODE>(rs, blockIdx.x); }
 template <int MODE>
+__global__ __launch_bounds__(LAT_BLOCK) void k_link_pass_direct(RunStep rs) {
+    link_pass_direct_body<MODE>(rs, blockIdx.x);
+}
+template <int MODE>
 __global__ __launch_bounds__(PASS_BLOCK) void k_link_pass_b(const RunStep* __restrict__ tab,
                                                      const uint2* __restrict__ bmap) {
     const uint2 m = bmap[blockIdx.x];
@@ -702,6 +749,13 @@ unsigned run_blocks(int c, const LP& lp, int ppb) {
 }
 
 hipError_t launch_step(int k, const RunStep& R, int mode, hipStream_t st) {
+    if (R.lp.direct && R.lp.np > 0) {   // direct addressing: no collection, a thread per node
+        if (k == SK_COLLECT) return hipSuccess;
+        if (k == SK_PASS) {
+            PTLBM_DISPATCH(mode, (k_link_pass_direct<M><<<run_blocks(GC_LAT, R.lp, 1), LAT_BLOCK, 0, st>>>(R)));
+            return hipGetLastError();
+        }
+    }
     const int ppb = links_particles_per_block(R.lp.nwin);
     const unsigned nb = run_blocks(grid_class(k), R.lp, ppb);
     if (nb == 0) return hipSuccess;

@@ -257,6 +257,8 @@ extern "C" int lbm_step_many(lbm_handle* hs, int32_t count, const int32_t* nstep
         if (nsteps[i] < 0) return fail(h0, LBM_EINVAL, "lbm_step_many: negative step count at %d", i);
         if (hs[i]->d.mode != h0->d.mode)
             return fail(h0, LBM_EINVAL, "lbm_step_many: runs of one call must share the storage mode");
+        if (hs[i]->d.lp.direct)
+            return fail(h0, LBM_EINVAL, "lbm_step_many: direct link addressing is for single runs only");
     }
     hipStream_t S = hip_stream ? (hipStream_t)hip_stream : h0->stream;
     std::lock_guard<std::mutex> lock(g_mu);

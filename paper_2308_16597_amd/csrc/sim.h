@@ -17,7 +17,7 @@ namespace ptlbm {
 struct Layout {
     int pitch = 0;
     size_t npitched = 0, array_stride = 0, state_bytes = 0;
-    size_t off_S[2] = {0, 0}, off_O[2] = {0, 0}, off_P = 0, off_Fh = 0, off_seg = 0,
+    size_t off_S[2] = {0, 0}, off_O[2] = {0, 0}, off_P = 0, off_Fh = 0, off_Fa = 0, off_seg = 0,
            off_links = 0, off_lscratch = 0, off_counter = 0, off_status = 0, off_bins[2] = {0, 0},
            off_bcnt[2] = {0, 0}, off_cand = 0, off_ncand = 0, total = 0;
     int nwin = 0;

@@ -27,6 +27,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "lbm.h")
 
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_ESEED, LBM_EUNSTABLE, LBM_ESTATE = 0, -1, -2, -3, -4, -5, -6
 STORE = {"f64": 0, "f32": 1, "shift_f32": 2, "shift_f16": 3, "shift_bf16": 4}
+LBM_LINKS_INDIRECT, LBM_LINKS_DIRECT = 0, 1
 PHASES = ("links", "particles", "mask", "lattice", "refill", "collect")
 
 _d, _i = ctypes.c_double, ctypes.c_int32
@@ -71,6 +72,7 @@ def _load():
     L.lbm_set_particles.argtypes = [vp, _i, vp]
     L.lbm_set_equilibrium.argtypes = [vp, vp, vp, vp, vp]
     L.lbm_step.argtypes = [vp, _i]
+    L.lbm_set_addressing.argtypes = [vp, _i]
     L.lbm_step_many.argtypes = [vp, _i, vp, vp]
     L.lbm_sync.argtypes = [vp]
     L.lbm_read_fields.argtypes = [vp, vp, vp, vp, vp, vp]
@@ -165,6 +167,13 @@ def lbm_set_particles(h, rows7):
 def lbm_set_equilibrium(h, rho, ux, uy, T):
     arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (rho, ux, uy, T)]
     _check(_lib.lbm_set_equilibrium(h, *[_ptr(a) for a in arrs]), h)
+
+
+def lbm_set_addressing(h, mode):
+    """mode: LBM_LINKS_INDIRECT or LBM_LINKS_DIRECT (or "indirect"/"direct")."""
+    if isinstance(mode, str):
+        mode = {"indirect": LBM_LINKS_INDIRECT, "direct": LBM_LINKS_DIRECT}[mode]
+    _check(_lib.lbm_set_addressing(h, int(mode)), h)
 
 
 def lbm_step(h, n):
@@ -291,6 +300,9 @@ class Sim:
 
     def step(self, n=1):
         lbm_step(self._h, n)
+
+    def set_addressing(self, mode):
+        lbm_set_addressing(self._h, mode)
 
     @property
     def handle(self):

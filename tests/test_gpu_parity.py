@@ -204,3 +204,62 @@ def test_dense_workload_parity_full_lattice():
     ef = compare_fields(sim.fields(), orc.fields(), u_floor=U_FF)
     ep = compare_particles(sim.particles(), orc.particles(), u_floor=U_FF)
     _say("dense after 1 step", ef, ep)
+
+
+def test_graph_replays_equal_eager_steps():
+    """lbm_step replays a captured graph of six overlapped steps for whole
+    cycles; stepping one step per call never does.  Three calls of 36 steps
+    (the graph is captured by the first and replayed six times per call),
+    with field reads between them, must give the bits of 108 single steps."""
+    from paper_2308_16597_amd import lbm
+    rows = np.array([[40.3, 30.2, 6.0, 0.05, -0.02, 0.0, 0.004],
+                     [100.6, 50.5, 7.0, -0.06, 0.03, 0.0, -0.005],
+                     [70.0, 70.5, 4.5, 0.0, -0.03, 0.0, 0.006]])
+    kw = dict(nx=128, ny=96, nu=0.05, alpha=0.04, gravity=1e-4, beta=0.5, particle_T=1.0,
+              rho_ratio=2.0, max_particles=3, max_diameter=14.0)
+    eager = lbm.Sim(lbm.lbm_params_default(**kw))
+    graph = lbm.Sim(lbm.lbm_params_default(**kw))
+    eager.set_particles(rows)
+    graph.set_particles(rows)
+    for call in range(3):
+        for _ in range(36):
+            eager.step(1)
+        graph.step(36)
+        fe, fg = eager.fields(), graph.fields()
+        for k in ("rho", "ux", "uy", "T", "owner"):
+            np.testing.assert_array_equal(fg[k], fe[k], err_msg=f"call {call}: {k}")
+        np.testing.assert_array_equal(graph.particles(), eager.particles())
+        _say("graph replay call", call, "bitwise equal to single steps")
+    eager.close()
+    graph.close()
+
+
+def test_direct_addressing_parity_and_switching():
+    """The direct-addressing link pass (a thread per node, no collection,
+    FP64 atomic force sums) on the small workload: 60 steps direct, 60
+    indirect, 60 direct again, then every field and particle within 1e-12 of
+    the oracle (forces within 1e-9: their summation order differs)."""
+    from paper_2308_16597_amd import lbm
+    rows = lbm_inputs.rsa_particles(256, 256, 20, 12.0, 1.0, 1)
+    sim, orc = make_pair(**C1)
+    sim.set_particles(rows)
+    orc.set_particles(rows)
+    with pytest.raises(lbm.LbmError) as e:
+        sim.set_addressing(7)
+    assert e.value.rc == lbm.LBM_EINVAL
+    for mode in ("direct", "indirect", "direct"):
+        sim.set_addressing(mode)
+        sim.step(60)
+        orc.step(60)
+        ef = compare_fields(sim.fields(), orc.fields(), u_floor=U_FF)
+        ep = compare_particles(sim.particles(), orc.particles(), u_floor=U_FF)
+        _say("addressing", mode, "at step", orc.steps_done, ef, ep)
+    n, dq = compare_links(sim.links(), orc.links(), q_abs=1e-12)   # collected on demand
+    assert n > 0
+    other = lbm.Sim(lbm.lbm_params_default(**C1))
+    other.set_particles(rows)
+    other.set_addressing("direct")
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.step_many([sim, other], [1, 1])
+    assert e.value.rc == lbm.LBM_EINVAL
+    other.close()
