@@ -229,6 +229,10 @@ def main():
             "launch_ms_alone": round(phases["lattice"], 5),
         },
         "phases_ms": {k: round(v, 5) for k, v in phases.items()},
+        # context only: the paper's single-GPU figure, other hardware and workload
+        "paper_context": {"mlups": 1750, "hardware": "NVIDIA A100 40 GB (named for the paper's cluster)",
+                          "precision": "not stated",
+                          "workload": "closed cavity 4000^2, 4800 particles d=40, 6000 steps"},
         "links_per_step": stats["links"],
         "fluid_nodes": n_fluid,
     }

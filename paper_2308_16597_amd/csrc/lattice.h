@@ -42,30 +42,35 @@ template <int MODE> struct Store;
 template <> struct Store<LBM_STORE_F64> {
     using T = double; using R = double; static constexpr bool shifted = false;
     __device__ static R ld(const PT_GLOBAL T* p) { return *p; }
+    __device__ static R ld_nt(const PT_GLOBAL T* p) { return __builtin_nontemporal_load(p); }
     __device__ static void st(PT_GLOBAL T* p, R v) { *p = v; }
     __device__ static void st_nt(PT_GLOBAL T* p, R v) { __builtin_nontemporal_store(v, p); }
 };
 template <> struct Store<LBM_STORE_F32> {
     using T = float; using R = float; static constexpr bool shifted = false;
     __device__ static R ld(const PT_GLOBAL T* p) { return *p; }
+    __device__ static R ld_nt(const PT_GLOBAL T* p) { return __builtin_nontemporal_load(p); }
     __device__ static void st(PT_GLOBAL T* p, R v) { *p = v; }
     __device__ static void st_nt(PT_GLOBAL T* p, R v) { __builtin_nontemporal_store(v, p); }
 };
 template <> struct Store<LBM_STORE_SHIFT_F32> {
     using T = float; using R = float; static constexpr bool shifted = true;
     __device__ static R ld(const PT_GLOBAL T* p) { return *p; }
+    __device__ static R ld_nt(const PT_GLOBAL T* p) { return __builtin_nontemporal_load(p); }
     __device__ static void st(PT_GLOBAL T* p, R v) { *p = v; }
     __device__ static void st_nt(PT_GLOBAL T* p, R v) { __builtin_nontemporal_store(v, p); }
 };
 template <> struct Store<LBM_STORE_SHIFT_F16> {
     using T = _Float16; using R = float; static constexpr bool shifted = true;
     __device__ static R ld(const PT_GLOBAL T* p) { return (float)*p; }
+    __device__ static R ld_nt(const PT_GLOBAL T* p) { return (float)__builtin_nontemporal_load(p); }
     __device__ static void st(PT_GLOBAL T* p, R v) { *p = (_Float16)v; }
     __device__ static void st_nt(PT_GLOBAL T* p, R v) { __builtin_nontemporal_store((_Float16)v, p); }
 };
 template <> struct Store<LBM_STORE_SHIFT_BF16> {
     using T = uint16_t; using R = float; static constexpr bool shifted = true;
     __device__ static R ld(const PT_GLOBAL T* p) { return bf16_to_f32(*p); }
+    __device__ static R ld_nt(const PT_GLOBAL T* p) { return bf16_to_f32(__builtin_nontemporal_load(p)); }
     __device__ static void st(PT_GLOBAL T* p, R v) { *p = f32_to_bf16_rne(v); }
     __device__ static void st_nt(PT_GLOBAL T* p, R v) { __builtin_nontemporal_store(f32_to_bf16_rne(v), p); }
 };
@@ -217,10 +222,12 @@ __device__ __forceinline__ void geq_dev(R T, R Tsh, R ux, R uy, R w0, R wk, R (&
 // bounce-back values written by the link pass.  Plain modes store f (the
 // rest part w_i rho0 is removed here) and g with T_sh = 0; shifted modes
 // store the deviations.
-template <class S>
+template <class S, bool NTL = false>
 __device__ __forceinline__ void pull_node(const Pops<typename S::T>& A, const LP& lp, int x, int y,
                                           typename S::R (&s)[9], typename S::R (&t)[5]) {
     using R = typename S::R;
+    // NTL: non-temporal loads (the lattice kernel reads each value once)
+    auto ld = [](const PT_GLOBAL typename S::T* q) { return NTL ? S::ld_nt(q) : S::ld(q); };
     const int nx = lp.nx, ny = lp.ny, pitch = lp.pitch;
     const int xm = x == 0 ? nx - 1 : x - 1;
     const int xp = x == nx - 1 ? 0 : x + 1;
@@ -233,36 +240,36 @@ __device__ __forceinline__ void pull_node(const Pops<typename S::T>& A, const LP
     R fs[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) fs[i] = S::shifted ? (R)0 : w9<R>(i) * (R)lp.rho0;
-    s[0] = S::ld(A.f[0] + k) - fs[0];
-    s[1] = S::ld(A.f[1] + r0 + xm) - fs[1];
-    s[3] = S::ld(A.f[3] + r0 + xp) - fs[3];
-    t[0] = S::ld(A.g[0] + k);
-    t[1] = S::ld(A.g[1] + r0 + xm);
-    t[3] = S::ld(A.g[3] + r0 + xp);
+    s[0] = ld(A.f[0] + k) - fs[0];
+    s[1] = ld(A.f[1] + r0 + xm) - fs[1];
+    s[3] = ld(A.f[3] + r0 + xp) - fs[3];
+    t[0] = ld(A.g[0] + k);
+    t[1] = ld(A.g[1] + r0 + xm);
+    t[3] = ld(A.g[3] + r0 + xp);
     const R w5k = (R)lp.w5_k;
     if (bot) {
         const R u = (R)lp.wall_ux[0] * (R)lp.rho0 * (R)(1.0 / 6.0);
-        s[2] = S::ld(A.f[4] + k) - fs[4];
-        s[5] = (S::ld(A.f[7] + k) - fs[7]) + u;
-        s[6] = (S::ld(A.f[8] + k) - fs[8]) - u;
-        t[2] = -S::ld(A.g[4] + k) + (R)2 * w5k * ((R)lp.wall_T[0] - (R)lp.T_sh);
+        s[2] = ld(A.f[4] + k) - fs[4];
+        s[5] = (ld(A.f[7] + k) - fs[7]) + u;
+        s[6] = (ld(A.f[8] + k) - fs[8]) - u;
+        t[2] = -ld(A.g[4] + k) + (R)2 * w5k * ((R)lp.wall_T[0] - (R)lp.T_sh);
     } else {
-        s[2] = S::ld(A.f[2] + rm + x) - fs[2];
-        s[5] = S::ld(A.f[5] + rm + xm) - fs[5];
-        s[6] = S::ld(A.f[6] + rm + xp) - fs[6];
-        t[2] = S::ld(A.g[2] + rm + x);
+        s[2] = ld(A.f[2] + rm + x) - fs[2];
+        s[5] = ld(A.f[5] + rm + xm) - fs[5];
+        s[6] = ld(A.f[6] + rm + xp) - fs[6];
+        t[2] = ld(A.g[2] + rm + x);
     }
     if (top) {
         const R u = (R)lp.wall_ux[1] * (R)lp.rho0 * (R)(1.0 / 6.0);
-        s[4] = S::ld(A.f[2] + k) - fs[2];
-        s[7] = (S::ld(A.f[5] + k) - fs[5]) - u;
-        s[8] = (S::ld(A.f[6] + k) - fs[6]) + u;
-        t[4] = -S::ld(A.g[2] + k) + (R)2 * w5k * ((R)lp.wall_T[1] - (R)lp.T_sh);
+        s[4] = ld(A.f[2] + k) - fs[2];
+        s[7] = (ld(A.f[5] + k) - fs[5]) - u;
+        s[8] = (ld(A.f[6] + k) - fs[6]) + u;
+        t[4] = -ld(A.g[2] + k) + (R)2 * w5k * ((R)lp.wall_T[1] - (R)lp.T_sh);
     } else {
-        s[4] = S::ld(A.f[4] + rp + x) - fs[4];
-        s[7] = S::ld(A.f[7] + rp + xp) - fs[7];
-        s[8] = S::ld(A.f[8] + rp + xm) - fs[8];
-        t[4] = S::ld(A.g[4] + rp + x);
+        s[4] = ld(A.f[4] + rp + x) - fs[4];
+        s[7] = ld(A.f[7] + rp + xp) - fs[7];
+        s[8] = ld(A.f[8] + rp + xm) - fs[8];
+        t[4] = ld(A.g[4] + rp + x);
     }
 }
 

@@ -36,7 +36,7 @@ __device__ __forceinline__ void stream_collide_body(const RunStep& rs, unsigned 
     if (x >= lp.nx || y >= lp.ny) return;
     const size_t k = (size_t)y * lp.pitch + x;
     R s[9], t[5];
-    pull_node<S>(A, lp, x, y, s, t);
+    pull_node<S, true>(A, lp, x, y, s, t);
     const CC<R> c(lp);
     R rho, ux, uy, T;
     collide<R>(c, s, t, rho, ux, uy, T);
