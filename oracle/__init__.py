@@ -27,6 +27,7 @@ class OrcParams(ctypes.Structure):
         ("wall_T", _c_d * 2), ("wall_ux", _c_d * 2),
         ("T_fluid0", _c_d), ("particle_T", _c_d), ("rho_ratio", _c_d),
         ("repulsion", _c_i), ("rep_eps", _c_d), ("rep_range", _c_d),
+        ("side_T", _c_d * 2),
     ]
 
 
@@ -34,7 +35,7 @@ DEFAULTS = dict(nx=32, ny=32, periodic_x=1, periodic_y=0, rho0=1.0, nu=0.1, alph
                 gravity=0.0, beta=0.0, T_ref=0.0, body_fx=0.0, s_e=0.0, s_eps=0.0,
                 s_q=0.0, a_T=-2.0, sT_e=0.0, sT_p=0.0, wall_T=(0.0, 0.0),
                 wall_ux=(0.0, 0.0), T_fluid0=0.0, particle_T=1.0, rho_ratio=1.5,
-                repulsion=1, rep_eps=1e-3, rep_range=3.0)
+                repulsion=1, rep_eps=1e-3, rep_range=3.0, side_T=(0.0, 0.0))
 
 
 def make_params(**kw):
@@ -45,7 +46,7 @@ def make_params(**kw):
     d.update(kw)
     p = OrcParams()
     for k, v in d.items():
-        if k in ("wall_T", "wall_ux"):
+        if k in ("wall_T", "wall_ux", "side_T"):
             getattr(p, k)[0], getattr(p, k)[1] = float(v[0]), float(v[1])
         else:
             setattr(p, k, v)
@@ -88,7 +89,7 @@ def lib():
         L.orc_thermal_link.restype = _c_d
         L.orc_repulsion_pair.argtypes = [ctypes.POINTER(OrcParams), _c_d, _c_d, _c_d,
                                          _c_d, _c_d, _c_d, vp]
-        L.orc_repulsion_walls.argtypes = [ctypes.POINTER(OrcParams), _c_d, _c_d, vp]
+        L.orc_repulsion_walls.argtypes = [ctypes.POINTER(OrcParams), _c_d, _c_d, _c_d, vp]
         L.orc_newton_euler.argtypes = [ctypes.POINTER(OrcParams), vp, _c_d, _c_d, _c_d, vp]
         L.orc_refill_node.argtypes = [vp, _c_i, vp, vp, vp, _c_d, _c_d, vp, vp]
         L.orc_rates.argtypes = [vp, vp, vp, vp]
@@ -227,9 +228,9 @@ def repulsion_pair(params, xp, yp, rp, xq, yq, rq):
     return out
 
 
-def repulsion_walls(params, yp, rp):
+def repulsion_walls(params, xp, yp, rp):
     out = np.empty(2)
-    lib().orc_repulsion_walls(ctypes.byref(params), yp, rp, _ptr(out))
+    lib().orc_repulsion_walls(ctypes.byref(params), xp, yp, rp, _ptr(out))
     return out
 
 

@@ -269,7 +269,9 @@ static void compute_owner(const orc_sim* s, int32_t* owner) {
             if (s->p.periodic_y) j = wrapi(jj, s->ny);
             else if (jj < 0 || jj >= s->ny) continue;
             for (int ii = i0; ii <= i1; ++ii) {
-                int i = wrapi(ii, s->nx);
+                int i = ii;
+                if (s->p.periodic_x) i = wrapi(ii, s->nx);
+                else if (ii < 0 || ii >= s->nx) continue;
                 long k = (long)j * s->nx + i;
                 if (owner[k] >= 0) continue;
                 if (inside(s, i, j, P)) owner[k] = q;
@@ -363,13 +365,26 @@ void orc_repulsion_pair(const orc_params* p, double xp, double yp, double rp,
     out[1] = mag * (dy / dist);
 }
 
-/* Repulsion from the flat walls: |x_s| is the distance from the wall plane
- * to the particle surface, the force points away from the wall. */
-void orc_repulsion_walls(const orc_params* p, double yp, double rp, double out[2]) {
+/* Repulsion from the flat walls (the y walls, and the side walls of a
+ * closed cavity): |x_s| is the distance from the wall plane to the particle
+ * surface, the force points away from the wall. */
+void orc_repulsion_walls(const orc_params* p, double xp, double yp, double rp, double out[2]) {
     out[0] = 0.0;
     out[1] = 0.0;
-    if (p->periodic_y) return;
     double C = ORC_PI * (rp * rp) * (p->rho_ratio - 1.0) * p->rho0 * p->gravity;
+    if (!p->periodic_x) {
+        double gap_l = (xp + 0.5) - rp;
+        if (gap_l <= p->rep_range) {
+            double t = (gap_l - p->rep_range) / p->rep_range;
+            out[0] += C / p->rep_eps * (t * t);
+        }
+        double gap_r = ((p->nx - 0.5) - xp) - rp;
+        if (gap_r <= p->rep_range) {
+            double t = (gap_r - p->rep_range) / p->rep_range;
+            out[0] -= C / p->rep_eps * (t * t);
+        }
+    }
+    if (p->periodic_y) return;
     double gap_b = (yp + 0.5) - rp;
     if (gap_b <= p->rep_range) {
         double t = (gap_b - p->rep_range) / p->rep_range;
@@ -453,7 +468,7 @@ void orc_refill_node(const orc_sim* s, int32_t K, const double* f1, const double
 
 static int validate(const orc_params* p, char* err, size_t n) {
     if (p->nx < 8 || p->ny < 8) return snprintf(err, n, "nx and ny must be >= 8"), 0;
-    if (!p->periodic_x) return snprintf(err, n, "periodic_x must be 1"), 0;
+    if (p->periodic_x != 0 && p->periodic_x != 1) return snprintf(err, n, "periodic_x must be 0 or 1"), 0;
     if (!(p->nu > 0) || !(p->alpha > 0)) return snprintf(err, n, "nu and alpha must be > 0"), 0;
     if (!(p->rho0 > 0)) return snprintf(err, n, "rho0 must be > 0"), 0;
     if (!(p->a_T > -4.0 && p->a_T <= 1.0)) return snprintf(err, n, "a_T out of (-4, 1]"), 0;
@@ -532,8 +547,13 @@ int orc_set_particles(orc_sim* s, int32_t n, const double* rows7) {
         if (!(in[2] > 1.0) || !isfinite(in[0]) || !isfinite(in[1]))
             return set_err(s, "particle radius must be > 1 and centre finite"), ORC_EINVAL;
         if (2.0 * in[2] + 4.0 > s->nx) return set_err(s, "particle wider than the lattice"), ORC_EINVAL;
-        double x = fmod(in[0], (double)s->nx);
-        if (x < 0) x += s->nx;
+        double x = in[0];
+        if (s->p.periodic_x) {
+            x = fmod(in[0], (double)s->nx);
+            if (x < 0) x += s->nx;
+        } else if (x < -0.5 || x > s->nx - 0.5) {
+            return set_err(s, "particle centre outside the cavity"), ORC_EINVAL;
+        }
         P[0] = x;
         for (int c = 1; c < 7; ++c) P[c] = in[c];
     }
@@ -570,6 +590,7 @@ typedef struct {
  * flat wall are not nodes). */
 static int fluid_at(const orc_sim* s, const int32_t* owner, int i, int j) {
     if (!s->p.periodic_y && (j < 0 || j >= s->ny)) return 0;
+    if (!s->p.periodic_x && (i < 0 || i >= s->nx)) return 0;
     i = wrapi(i, s->nx);
     j = wrapi(j, s->ny);
     return owner[(long)j * s->nx + i] < 0;
@@ -587,8 +608,9 @@ static long collect_links(const orc_sim* s, link_t* out) {
         if (s->owner[k] >= 0) continue;
         int i = (int)(k % s->nx), j = (int)(k / s->nx);
         for (int d = 1; d < 9; ++d) {
-            int tj = j + EY[d];
+            int tj = j + EY[d], ti = i + EX[d];
             if (!s->p.periodic_y && (tj < 0 || tj >= s->ny)) continue;
+            if (!s->p.periodic_x && (ti < 0 || ti >= s->nx)) continue;
             int32_t o = s->owner[node_of(s, i + EX[d], tj)];
             if (o >= 0) {
                 if (out) {
@@ -639,21 +661,27 @@ static int step_once(orc_sim* s) {
 
     /* 5. streaming into s->f / s->g (reused as the t_n+1 arrays): pull from
      * the upstream node; flat walls use halfway bounce-back for f (with the
-     * wall's tangential velocity) and anti-bounce-back for g (Dirichlet
-     * T_wall).  Populations coming from a particle are set in step 6. */
+     * y wall's tangential velocity; side walls are at rest) and
+     * anti-bounce-back for g (Dirichlet T_wall).  A diagonal population whose
+     * upstream node lies beyond both a y wall and a side wall (a cavity
+     * corner) is bounced back with the y wall's velocity and, being a
+     * diagonal, has no g.  Populations coming from a particle are set in
+     * step 6. */
     for (long k = 0; k < N; ++k) {
         for (int i = 0; i < 9; ++i) s->f[i * N + k] = NAN;
         for (int i = 0; i < 5; ++i) s->g[i * N + k] = NAN;
         if (s->owner[k] >= 0) continue;
         int x = (int)(k % nx), y = (int)(k / nx);
         for (int i = 0; i < 9; ++i) {
-            int sy = y - EY[i];
-            if (!p->periodic_y && (sy < 0 || sy >= ny)) {
-                int w = sy < 0 ? 0 : 1;
+            int sy = y - EY[i], sx = x - EX[i];
+            int outy = !p->periodic_y && (sy < 0 || sy >= ny);
+            int outx = !p->periodic_x && (sx < 0 || sx >= nx);
+            if (outy || outx) {
                 int ib = OPP[i];
-                s->f[i * N + k] =
-                    s->fp[ib * N + k] - 2.0 * W9[ib] * p->rho0 * (EX[ib] * p->wall_ux[w]) / CS2;
-                if (i < 5) s->g[i * N + k] = -s->gp[ib * N + k] + 2.0 * s->w5[i] * p->wall_T[w];
+                double uw = outy ? p->wall_ux[sy < 0 ? 0 : 1] : 0.0;
+                double Tw = outy ? p->wall_T[sy < 0 ? 0 : 1] : p->side_T[sx < 0 ? 0 : 1];
+                s->f[i * N + k] = s->fp[ib * N + k] - 2.0 * W9[ib] * p->rho0 * (EX[ib] * uw) / CS2;
+                if (i < 5) s->g[i * N + k] = -s->gp[ib * N + k] + 2.0 * s->w5[i] * Tw;
                 continue;
             }
             long src = node_of(s, x - EX[i], sy);
@@ -738,7 +766,7 @@ static int step_once(orc_sim* s) {
                 Ry += fr[1];
             }
             double fw[2];
-            orc_repulsion_walls(p, P[1], P[2], fw);
+            orc_repulsion_walls(p, P[0], P[1], P[2], fw);
             Rx += fw[0];
             Ry += fw[1];
         }
@@ -748,7 +776,7 @@ static int step_once(orc_sim* s) {
         double st[7], out[7];
         for (int c = 0; c < 7; ++c) st[c] = P[c];
         orc_newton_euler(p, st, Fx, Fy, Fsum[3 * a + 2], out);
-        double ddx = min_image(out[0] - P[0], nx, 1), ddy = out[1] - P[1];
+        double ddx = min_image(out[0] - P[0], nx, p->periodic_x), ddy = out[1] - P[1];
         if (!(ddx * ddx + ddy * ddy <= 0.25)) unstable = 1;
         double* O = Pn + 10 * a;
         for (int c = 0; c < 7; ++c) O[c] = out[c];

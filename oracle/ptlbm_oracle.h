@@ -33,7 +33,8 @@ enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_ENOMEM = -2, ORC_EUNSTABLE = -5 };
 
 typedef struct {
     int32_t nx, ny;
-    int32_t periodic_x;   /* must be 1 */
+    int32_t periodic_x;   /* 1: periodic; 0: side walls at x = -1/2 and nx - 1/2 (static,
+                             no-slip, Dirichlet side_T) -- the closed cavity */
     int32_t periodic_y;   /* 0: flat walls at y (required with particles); 1: periodic */
     double rho0;          /* reference density */
     double nu;            /* kinematic viscosity (lattice units) */
@@ -53,6 +54,7 @@ typedef struct {
     int32_t repulsion;    /* 1: spring repulsion on (Sec. 2.4, Eq. (15)) */
     double rep_eps;       /* stiffness epsilon_w */
     double rep_range;     /* threshold distance s */
+    double side_T[2];     /* Dirichlet temperature of the [left, right] side wall */
 } orc_params;
 
 typedef struct orc_sim orc_sim;
@@ -97,7 +99,7 @@ double orc_thermal_link(double q, int32_t i, double gi_xf, double gi_xf1, double
                         int32_t have1, double w5_i, double Tw);
 void orc_repulsion_pair(const orc_params* p, double xp, double yp, double rp,
                         double xq, double yq, double rq, double out[2]);
-void orc_repulsion_walls(const orc_params* p, double yp, double rp, double out[2]);
+void orc_repulsion_walls(const orc_params* p, double xp, double yp, double rp, double out[2]);
 void orc_newton_euler(const orc_params* p, const double state7[7], double Fx, double Fy,
                       double Tz, double out7[7]);
 void orc_refill_node(const orc_sim* s, int32_t K, const double* f1, const double* f2,

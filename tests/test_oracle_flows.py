@@ -142,3 +142,51 @@ def test_mass_conserved_with_moving_wall():
     o.step(500)
     f1, _ = o.populations()
     assert abs(f1.sum() - f0.sum()) / f0.sum() < 1e-13
+
+
+# ----------------------------------------------------------- closed cavity
+# Side walls at x = -1/2 and nx - 1/2 (periodic_x = 0): the same halfway
+# bounce-back and anti-bounce-back as the flat y walls, pinned the same way.
+
+@pytest.mark.parametrize("rates", [(0.0, 0.0), (1.3, 0.7), (0.4, 1.9)])
+def test_side_wall_conduction_exact(rates):
+    """Hot left wall T=1, cold right wall T=0, periodic y:
+    T(x) = 1 - (x+1/2)/W for any rates."""
+    nx = 16
+    o = Oracle(nx=nx, ny=8, periodic_x=0, periodic_y=1, nu=0.1, alpha=0.15, side_T=(1.0, 0.0),
+               sT_e=rates[0], sT_p=rates[1])
+    o.step(6000)
+    f = o.fields()
+    x = np.arange(nx)
+    assert np.abs(f["T"] - (1 - (x + 0.5) / nx)[None, :]).max() < 1e-12
+
+
+@pytest.mark.parametrize("nu", [0.02, 1 / 6])
+def test_side_wall_poiseuille_exact(nu):
+    """Uniform buoyancy force F = rho g beta (T - T_ref) along +y between the
+    side walls (T = 1 everywhere, walls included, periodic y):
+    u_y(x) = F (x+1/2)(W-1/2-x) / (2 rho0 nu), u_x = 0."""
+    nx, G = 12, 1e-5
+    o = Oracle(nx=nx, ny=8, periodic_x=0, periodic_y=1, nu=nu, alpha=0.1, gravity=1.0, beta=G,
+               T_ref=0.0, T_fluid0=1.0, side_T=(1.0, 1.0))
+    o.set_equilibrium(np.ones((8, nx)), np.zeros((8, nx)), np.zeros((8, nx)), np.ones((8, nx)))
+    o.step(int(40 * nx * nx / nu / 9.87))
+    f = o.fields()
+    x = np.arange(nx)
+    exact = G * (x + 0.5) * (nx - 0.5 - x) / (2 * nu)
+    err = np.abs(f["uy"] - exact[None, :]).max() / exact.max()
+    assert err < 1e-11, err
+    assert np.abs(f["ux"]).max() < 1e-15
+
+
+def test_closed_cavity_conserves_mass():
+    """Four walls (moving lid and bottom, resting sides, corners included):
+    sum f is invariant."""
+    rho, ux, uy, T = lbm_inputs.smooth_fields(20, 16, seed=13)
+    o = Oracle(nx=20, ny=16, periodic_x=0, nu=0.05, alpha=0.03, wall_ux=(0.02, -0.01),
+               wall_T=(0.3, 0.0), side_T=(0.7, 0.1), gravity=1e-3, beta=0.1)
+    o.set_equilibrium(rho, ux, uy, T)
+    f0, _ = o.populations()
+    o.step(500)
+    f1, _ = o.populations()
+    assert abs(f1.sum() - f0.sum()) / f0.sum() < 1e-13

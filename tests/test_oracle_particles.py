@@ -110,10 +110,21 @@ def test_repulsion_hand_values():
     # across the periodic seam: centres 1 and 89 are 12 apart
     s = oracle.repulsion_pair(p, 1.0, 50.0, 5.0, 89.0, 50.0, 5.0)
     assert abs(s[0] - C / 1e-3 / 9) < 1e-15
-    w = oracle.repulsion_walls(p, 5.5, 5.0)  # gap to the bottom wall plane y=-1/2 is 1
-    assert abs(w[1] - C / 1e-3 * (2 / 3) ** 2) < 1e-15 and w[0] == 0.0
-    w = oracle.repulsion_walls(p, 99.5 - 5.0 - 2.0, 5.0)  # gap 2 to the top wall plane y=99.5
+    w = oracle.repulsion_walls(p, 1.0, 5.5, 5.0)  # gap to the bottom wall plane y=-1/2 is 1
+    assert abs(w[1] - C / 1e-3 * (2 / 3) ** 2) < 1e-15 and w[0] == 0.0   # periodic x: no side walls
+    w = oracle.repulsion_walls(p, 1.0, 99.5 - 5.0 - 2.0, 5.0)  # gap 2 to the top wall plane y=99.5
     assert abs(w[1] + C / 1e-3 / 9) < 1e-15
+    # a closed cavity also pushes off its side walls at x = -1/2 and nx - 1/2
+    pc = oracle.make_params(nx=90, ny=100, periodic_x=0, gravity=2e-4, rho_ratio=1.5, rep_eps=1e-3,
+                            rep_range=3.0)
+    w = oracle.repulsion_walls(pc, 5.5, 50.0, 5.0)   # gap 1 to the left wall
+    assert abs(w[0] - C / 1e-3 * (2 / 3) ** 2) < 1e-15 and w[1] == 0.0
+    w = oracle.repulsion_walls(pc, 89.5 - 5.0 - 2.0, 50.0, 5.0)   # gap 2 to the right wall
+    assert abs(w[0] + C / 1e-3 / 9) < 1e-15
+    c = oracle.repulsion_walls(pc, 5.5, 5.5, 5.0)   # a corner: both walls at gap 1
+    assert abs(c[0] - C / 1e-3 * (2 / 3) ** 2) < 1e-15 and abs(c[1] - C / 1e-3 * (2 / 3) ** 2) < 1e-15
+    # and no minimum image across a side wall: centres 1 and 89 are 88 apart
+    assert (oracle.repulsion_pair(pc, 1.0, 50.0, 5.0, 89.0, 50.0, 5.0) == 0).all()
 
 
 def test_newton_euler_constant_force_is_exact_quadratic():
@@ -234,7 +245,36 @@ def test_invalid_parameters_are_rejected():
     with pytest.raises(OracleError):
         Oracle(nx=4, ny=32)
     with pytest.raises(OracleError):
-        Oracle(nx=32, ny=32, periodic_x=0)
+        Oracle(nx=32, ny=32, periodic_x=2)
+    cav = Oracle(nx=32, ny=32, periodic_x=0)
+    with pytest.raises(OracleError):   # no wrapping into a closed cavity
+        cav.set_particles([_row(33.0, 10, 3)])
     o = Oracle(nx=32, ny=32, periodic_y=1)
     with pytest.raises(OracleError):
         o.set_particles([_row(10, 10, 3)])
+
+
+@pytest.mark.parametrize("cx,cy", [(2.3, 20.0), (29.6, 2.4), (1.9, 37.2)])
+def test_links_next_to_cavity_walls_brute_force(cx, cy):
+    """In a closed cavity nothing wraps: the link set of a disk touching a
+    side wall (and, in the corners, a y wall) is the brute-force set over the
+    nodes of the lattice alone, and the disk owns no node beyond the walls."""
+    nx, ny, r = 32, 40, 4.7
+    o = Oracle(nx=nx, ny=ny, periodic_x=0, **QUIET)
+    o.set_particles([_row(cx, cy, r)])
+    links, _ = _links_set(o)
+
+    def solid(i, j):
+        return 0 <= i < nx and 0 <= j < ny and (i - cx) ** 2 + (j - cy) ** 2 <= r * r
+
+    expect = set()
+    for j in range(ny):
+        for i in range(nx):
+            if solid(i, j):
+                continue
+            for d in range(1, 9):
+                if solid(i + EX[d], j + EY[d]):
+                    expect.add((j * nx + i, d, 0))
+    assert links == expect and len(links) > 0
+    owner = o.fields()["owner"]
+    assert (owner == 0).sum() == sum(solid(i, j) for j in range(ny) for i in range(nx))
