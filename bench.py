@@ -18,6 +18,11 @@ Prints one JSON line.  Besides the throughput it carries:
                against 8 TB/s.
   cpu_baseline the CPU oracle (single thread, FP64) on a bounded sample of
                the same workload, timed on this host.
+  paper_workload  the paper's own benchmark case (Sec. 2.6.3: closed 4000^2
+               cavity, 60 x 80 hot particles of diameter 40, Pr 5, Gr_p 60,
+               rho_p/rho_f = 1.1), a short timed run beside the paper's
+               single-GPU figure for it (other hardware: context).  With
+               --workload e4_cavity that case is the headline itself.
   serving      256 seeded requests (lattices 128..1024 on a side, aspect 1
                or 2, 5..400 particles of diameter 8..24, Ra 1e5..1e8, 500..5000
                steps, BF16 storage) served from a 2 GiB device budget: first
@@ -81,7 +86,7 @@ def cpu_baseline(workload, steps):
     kw = params.workload_params(workload)
     w = params.WORKLOADS[workload]
     okw = {k: v for k, v in kw.items() if k not in ("storage", "max_particles", "max_diameter")}
-    rows = lbm_inputs.rsa_particles(w["nx"], w["ny"], w["n"], w["d"], w["gap"], w["seed"])
+    rows = lbm_inputs.workload_particles(w)
     orc = Oracle(**okw)
     orc.set_particles(rows)
     orc.step(1)  # first touch of the oracle's arrays, not timed
@@ -93,6 +98,51 @@ def cpu_baseline(workload, steps):
                 kind="oracle",
                 sample=f"steps 2..{steps + 1} of the {w['nx']}x{w['ny']} workload with {w['n']} "
                        f"particles (FP64, one thread): {dt:.1f} s")
+
+
+def describe(name, storage):
+    """One-line description of a named workload."""
+    from paper_2308_16597_amd import params
+    w = params.WORKLOADS[name]
+    geom = "closed cavity" if w.get("closed") else "periodic-x channel"
+    if "lattice" in w:
+        lat = w["lattice"]
+        phys = (f"nu={lat['nu']:g}, alpha={lat['alpha']:g}, g={lat['gravity']:g}, "
+                f"beta={lat['beta']:g} (Pr={lat['nu'] / lat['alpha']:g})")
+    else:
+        phys = f"Pr={w['Pr']}, Ra={w['Ra']:g}"
+    place = (f"{w['rows']}x{w['cols']} grid" if w.get("layout") == "grid" else "random")
+    return (f"{name}: {w['nx']}x{w['ny']} {geom}, {w['n']} hot particles d={w['d']:g} ({place}), "
+            f"rho_p/rho_f={w['rho_ratio']}, {phys}, {storage} storage, links rebuilt every step")
+
+
+def paper_workload(steps, warmup, storage):
+    """The paper's own benchmark case (closed 4000^2 cavity, 60 x 80
+    particles of diameter 40, 6000 steps there), timed over `steps` steps
+    after `warmup`, beside the paper's figure for it."""
+    import torch
+    import lbm_inputs
+    from paper_2308_16597_amd import lbm, params
+    name = "e4_cavity"
+    w = params.WORKLOADS[name]
+    sim = lbm.Sim(lbm.lbm_params_default(**params.workload_params(name, lbm.STORE[storage])))
+    sim.set_particles(lbm_inputs.workload_particles(w))
+    sim.step(warmup)
+    sim.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    sim.sync()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    links = sim.stats()["links"]
+    sim.close()
+    v = params.mlups(w["nx"] * w["ny"], steps, dt)
+    log(f"[bench] {name}: {steps} steps in {dt:.3f} s: {v:.1f} MLUPS")
+    return dict(workload=describe(name, storage), steps=steps, warmup=warmup, mlups=round(v, 2),
+                ms_per_step=round(dt / steps * 1e3, 5), links_per_step=links,
+                paper_mlups=1750, ratio_to_paper=round(v / 1750.0, 3),
+                paper_hardware="NVIDIA A100 40 GB (named for the paper's cluster), precision not stated")
 
 
 def serving(n_req, budget_gib, chunk):
@@ -144,6 +194,9 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-paper-workload", action="store_true",
+                    help="skip the short timed run of the paper's closed-cavity case")
+    ap.add_argument("--paper-steps", type=int, default=600)
     ap.add_argument("--addressing", default="indirect", choices=["indirect", "direct"],
                     help="link pass by indirect (default) or direct addressing (the ablation)")
     ap.add_argument("--copy-probe", type=int, default=0,
@@ -167,8 +220,9 @@ def main():
     nx, ny = w["nx"], w["ny"]
     p = lbm.lbm_params_default(**params.workload_params(args.workload, lbm.STORE[args.storage]))
     log(f"[bench] {args.workload} {nx}x{ny} n={w['n']} d={w['d']} storage={args.storage}")
+    import lbm_inputs
     sim = lbm.Sim(p)
-    sim.seed_particles(w["n"], w["d"], w["gap"], w["seed"])
+    sim.set_particles(lbm_inputs.workload_particles(w))
     if args.addressing != "indirect":
         sim.set_addressing(args.addressing)
     sim.step(args.warmup)
@@ -205,13 +259,11 @@ def main():
         "ms_per_step": round(dt / args.steps * 1e3, 5),
         "higher_is_better": True,
         "scaling": "weak",
-        "vs_baseline": None,
+        "vs_baseline": round(mlups / 1750.0, 4) if args.workload == "e4_cavity" else None,
         "dtype": STORE_DTYPE[args.storage],
         "data": "synthetic",
         "config": {
-            "workload": f"{args.workload}: {nx}x{ny} periodic-x channel, {w['n']} hot particles "
-                        f"d={w['d']:g}, rho_p/rho_f={w['rho_ratio']}, Pr={w['Pr']}, Ra={w['Ra']:g}, "
-                        f"{args.storage} storage, links rebuilt every step"
+            "workload": describe(args.workload, args.storage)
                         + ("" if args.addressing == "indirect" else ", direct link addressing"),
             "nx": nx, "ny": ny, "particles": w["n"], "diameter": w["d"], "storage": args.storage,
             "parallelism": "single GPU",
@@ -238,6 +290,8 @@ def main():
     }
     sim.close()
     del sim
+    if args.workload != "e4_cavity" and not args.no_paper_workload:
+        out["paper_workload"] = paper_workload(args.paper_steps, 20, args.storage)
     if not args.no_serve:
         out["serving"] = serving(args.serve_requests, args.serve_budget_gib, args.serve_chunk)
     if not args.no_cpu_baseline:

@@ -21,8 +21,9 @@
  *      Eqs. (16)-(17)).
  *
  * Geometry: node (i, j) is at (x, y) = (i, j), 0 <= i < nx, 0 <= j < ny; x is
- * periodic; the flat walls are halfway between nodes, at y = -1/2 and
- * y = ny - 1/2.  Gravity points along -y.  D2Q9 velocities e0..e8 are
+ * periodic, or (periodic_x = 0, the closed cavity) bounded by static side
+ * walls at x = -1/2 and x = nx - 1/2; the flat walls are halfway between
+ * nodes, at y = -1/2 and y = ny - 1/2.  Gravity points along -y.  D2Q9 velocities e0..e8 are
  * (0,0) (1,0) (0,1) (-1,0) (0,-1) (1,1) (-1,1) (-1,-1) (1,-1); D2Q5 uses the
  * first five.
  *
@@ -54,7 +55,7 @@
 extern "C" {
 #endif
 
-#define LBM_ABI_VERSION 1
+#define LBM_ABI_VERSION 2
 
 typedef struct lbm_sim* lbm_handle;
 
@@ -86,7 +87,7 @@ enum {
 typedef struct {
     int32_t abi_version;   /* must be LBM_ABI_VERSION */
     int32_t nx, ny;        /* 8 <= nx, ny <= 65535 */
-    int32_t periodic_x;    /* must be 1 */
+    int32_t periodic_x;    /* 1: periodic; 0: static side walls (no-slip, Dirichlet side_T) */
     int32_t periodic_y;    /* 0: flat walls at y (required with particles); 1: periodic */
     int32_t storage;       /* LBM_STORE_* */
     double rho0;           /* reference density (> 0) */
@@ -109,6 +110,7 @@ typedef struct {
     double T_shift;        /* SHIFT_ storage: g is stored as g_k - w_k T_shift */
     int32_t max_particles; /* capacity for particles (>= 0) */
     double max_diameter;   /* largest particle diameter the buffers are sized for */
+    double side_T[2];      /* periodic_x = 0: Dirichlet temperature of the [left, right] wall */
 } lbm_params;
 
 /* Phases reported by lbm_time_phases, in the order of a sequential step.
@@ -165,13 +167,16 @@ const char* lbm_last_error(lbm_handle h);
 int lbm_rsa_seed(int32_t nx, int32_t ny, int32_t n, double diameter, double min_gap,
                  uint64_t seed, double* rows7);
 
-/* lbm_rsa_seed with the handle's lattice, then lbm_set_particles. */
+/* lbm_rsa_seed with the handle's lattice, then lbm_set_particles.  Periodic
+ * channels only (LBM_EINVAL for the closed cavity, whose particles are
+ * placed with lbm_set_particles). */
 int lbm_seed_particles(lbm_handle h, int32_t n, double diameter, double min_gap, uint64_t seed);
 
 /* Replace the particles (n rows of x, y, r, ux, uy, theta, omega; host
  * memory) and re-initialise the run: fluid at rest at rho0 and T_fluid0,
  * step counter 0.  Requires n <= max_particles, 1 < r <= max_diameter/2,
- * finite values and walls in y. */
+ * finite values, walls in y, -1/2 <= y <= ny - 1/2 and, in the closed
+ * cavity, -1/2 <= x <= nx - 1/2 (a periodic x is wrapped into [0, nx)). */
 int lbm_set_particles(lbm_handle h, int32_t n, const double* rows7);
 
 /* Re-initialise fluid nodes to the equilibria f^eq(rho, u) and g^eq(T, u)

@@ -106,6 +106,35 @@ def rsa_particles(nx, ny, n, diameter, min_gap=1.0, seed=1):
     return out
 
 
+def grid_particles(nx, ny, rows, cols, diameter, spacing):
+    """Particles at rest on a regular grid hanging from the top of a closed
+    cavity (walls at x = -1/2, nx - 1/2 and y = -1/2, ny - 1/2): `cols` per
+    line centred across the width at `spacing` apart, `rows` lines from the
+    top down, the top line one half spacing below the top wall.  Row-major
+    from the top left."""
+    width = cols * spacing
+    if width > nx or rows * spacing > ny or diameter > spacing:
+        raise ValueError("grid does not fit the cavity")
+    x0 = -0.5 + 0.5 * (nx - width) + 0.5 * spacing
+    y0 = (ny - 0.5) - 0.5 * spacing
+    out = np.zeros((rows * cols, 7))
+    for j in range(rows):
+        for i in range(cols):
+            out[j * cols + i, 0] = x0 + i * spacing
+            out[j * cols + i, 1] = y0 - j * spacing
+    out[:, 2] = 0.5 * diameter
+    return out
+
+
+def workload_particles(w):
+    """Initial particle rows of a workload description: `layout` "grid"
+    (rows x cols at `spacing`) or, by default, random sequential addition
+    with its gap and seed."""
+    if w.get("layout") == "grid":
+        return grid_particles(w["nx"], w["ny"], w["rows"], w["cols"], w["d"], w["spacing"])
+    return rsa_particles(w["nx"], w["ny"], w["n"], w["d"], w["gap"], w["seed"])
+
+
 def smooth_fields(nx, ny, seed, amp_u=0.02, amp_T=0.5, modes=3, rho0=1.0):
     """Smooth random macroscopic fields (rho, ux, uy, T), each (ny, nx).
 

@@ -115,7 +115,7 @@ bool validate(const lbm_params* p, std::string& why) {
         return false;
     }
     if (p->nx < 8 || p->ny < 8 || p->nx > 65535 || p->ny > 65535) return bad("nx and ny must lie in [8, 65535]");
-    if (p->periodic_x != 1) return bad("periodic_x must be 1");
+    if (p->periodic_x != 0 && p->periodic_x != 1) return bad("periodic_x must be 0 or 1");
     if (p->periodic_y != 0 && p->periodic_y != 1) return bad("periodic_y must be 0 or 1");
     if (elem_size(p->storage) == 0) return bad("unknown storage mode");
     if (!(p->rho0 > 0) || !(p->nu > 0) || !(p->alpha > 0)) return bad("rho0, nu and alpha must be > 0");
@@ -134,8 +134,9 @@ bool validate(const lbm_params* p, std::string& why) {
         if (!(p->rep_eps > 0) || !(p->rep_range > 0)) return bad("rep_eps and rep_range must be > 0");
         if (!(p->rho_ratio > 0)) return bad("rho_ratio must be > 0");
     }
-    const double vals[] = {p->gravity, p->beta, p->T_ref, p->body_fx, p->wall_T[0], p->wall_T[1],
-                           p->wall_ux[0], p->wall_ux[1], p->T_fluid0, p->particle_T, p->T_shift};
+    const double vals[] = {p->gravity,  p->beta,       p->T_ref,      p->body_fx,    p->wall_T[0],
+                           p->wall_T[1], p->wall_ux[0], p->wall_ux[1], p->T_fluid0,   p->particle_T,
+                           p->T_shift,  p->side_T[0],  p->side_T[1]};
     for (double v : vals)
         if (!std::isfinite(v)) return bad("parameters must be finite");
     return true;
@@ -147,6 +148,7 @@ void fill_lp(lbm_sim* h) {
     lp.nx = p.nx;
     lp.ny = p.ny;
     lp.pitch = h->L.pitch;
+    lp.periodic_x = p.periodic_x;
     lp.periodic_y = p.periodic_y;
     lp.rho0 = p.rho0;
     lp.gbeta = p.gravity * p.beta;
@@ -170,6 +172,7 @@ void fill_lp(lbm_sim* h) {
     for (int w = 0; w < 2; ++w) {
         lp.wall_T[w] = p.wall_T[w];
         lp.wall_ux[w] = p.wall_ux[w];
+        lp.side_T[w] = p.periodic_x ? 0.0 : p.side_T[w];
     }
     const bool shifted = p.storage >= LBM_STORE_SHIFT_F32;
     lp.T_sh = shifted ? p.T_shift : 0.0;
@@ -533,6 +536,7 @@ int lbm_rsa_seed(int32_t nx, int32_t ny, int32_t n, double diameter, double min_
 int lbm_seed_particles(lbm_handle h, int32_t n, double diameter, double min_gap, uint64_t seed) {
     if (!h) return LBM_EINVAL;
     if (n < 0) return fail(h, LBM_EINVAL, "negative particle count");
+    if (!h->p.periodic_x) return fail(h, LBM_EINVAL, "seeding is for periodic channels; place cavity particles with lbm_set_particles");
     std::vector<double> rows((size_t)n * 7 + 1);
     int rc = lbm_rsa_seed(h->p.nx, h->p.ny, n, diameter, min_gap, seed, rows.data());
     if (rc != LBM_OK) return fail(h, rc, "%s", g_create_error.c_str());
@@ -551,8 +555,13 @@ int lbm_set_particles(lbm_handle h, int32_t n, const double* rows7) {
             if (!std::isfinite(in[c])) return fail(h, LBM_EINVAL, "particle %d: non-finite value", i);
         if (!(in[2] > 1.0) || in[2] > rmax) return fail(h, LBM_EINVAL, "particle %d: radius %g outside (1, %g]", i, in[2], rmax);
         if (in[1] < -0.5 || in[1] > h->p.ny - 0.5) return fail(h, LBM_EINVAL, "particle %d: centre outside the channel", i);
-        double x = std::fmod(in[0], (double)h->p.nx);
-        if (x < 0) x += h->p.nx;
+        double x = in[0];
+        if (h->p.periodic_x) {
+            x = std::fmod(in[0], (double)h->p.nx);
+            if (x < 0) x += h->p.nx;
+        } else if (x < -0.5 || x > h->p.nx - 0.5) {
+            return fail(h, LBM_EINVAL, "particle %d: centre outside the cavity", i);
+        }
         P[i] = PState{x, in[1], in[2], in[3], in[4], in[5], in[6], 0.0};
     }
     DevState& d = h->d;

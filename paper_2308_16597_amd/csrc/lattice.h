@@ -82,12 +82,13 @@ template <class T> struct Pops {
 
 // Lattice constants handed to every kernel (host-filled, FP64).
 struct LP {
-    int nx, ny, pitch, periodic_y;
+    int nx, ny, pitch, periodic_x, periodic_y;   // periodic_x = 0: closed cavity
     double rho0, gbeta, T_ref, body_fx;
     double s_e, s_eps, s_q, s_nu;      // D2Q9 rates (the j rates are immaterial)
     double s_a, s_Te, s_Tp, a_T;       // D2Q5 rates and equilibrium constant
     double w5_0, w5_k;                 // D2Q5 weights
     double wall_T[2], wall_ux[2];      // [bottom, top]
+    double side_T[2];                  // [left, right] side walls of the cavity
     double T_sh;                       // storage shift of g (0 for plain modes)
     double particle_T, rho_ratio, gravity, rep_eps, rep_range;
     int repulsion, np, nwin;           // particles, window edge capacity
@@ -218,7 +219,10 @@ __device__ __forceinline__ void geq_dev(R T, R Tsh, R ux, R uy, R w0, R wk, R (&
 // Pull of the 9 + 5 populations arriving at node (x, y) from the
 // post-collision state A, as deviations: flat walls in y by halfway
 // bounce-back (moving tangentially at wall_ux) for f and anti-bounce-back
-// (Dirichlet wall_T) for g; x periodic.  Solid upstream nodes hold the
+// (Dirichlet wall_T) for g; x periodic, or bounded by the static side walls
+// of the closed cavity (the same two rules at rest, Dirichlet side_T).  A
+// diagonal population whose upstream node is beyond a y wall and a side
+// wall at once takes the y wall's rule.  Solid upstream nodes hold the
 // bounce-back values written by the link pass.  Plain modes store f (the
 // rest part w_i rho0 is removed here) and g with T_sh = 0; shifted modes
 // store the deviations.
@@ -233,6 +237,8 @@ __device__ __forceinline__ void pull_node(const Pops<typename S::T>& A, const LP
     const int xp = x == nx - 1 ? 0 : x + 1;
     const bool bot = !lp.periodic_y && y == 0;
     const bool top = !lp.periodic_y && y == ny - 1;
+    const bool lft = !lp.periodic_x && x == 0;
+    const bool rgt = !lp.periodic_x && x == nx - 1;
     const int ym = y == 0 ? ny - 1 : y - 1;
     const int yp = y == ny - 1 ? 0 : y + 1;
     const size_t r0 = (size_t)y * pitch, rm = (size_t)ym * pitch, rp = (size_t)yp * pitch;
@@ -240,13 +246,17 @@ __device__ __forceinline__ void pull_node(const Pops<typename S::T>& A, const LP
     R fs[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) fs[i] = S::shifted ? (R)0 : w9<R>(i) * (R)lp.rho0;
-    s[0] = ld(A.f[0] + k) - fs[0];
-    s[1] = ld(A.f[1] + r0 + xm) - fs[1];
-    s[3] = ld(A.f[3] + r0 + xp) - fs[3];
-    t[0] = ld(A.g[0] + k);
-    t[1] = ld(A.g[1] + r0 + xm);
-    t[3] = ld(A.g[3] + r0 + xp);
+    // at a side wall the address moves to the node's own opposite population
+    // (the pairs share their rest weight, so fs stays the same)
     const R w5k = (R)lp.w5_k;
+    s[0] = ld(A.f[0] + k) - fs[0];
+    s[1] = ld(lft ? A.f[3] + k : A.f[1] + r0 + xm) - fs[1];
+    s[3] = ld(rgt ? A.f[1] + k : A.f[3] + r0 + xp) - fs[3];
+    t[0] = ld(A.g[0] + k);
+    const R g1 = ld(lft ? A.g[3] + k : A.g[1] + r0 + xm);
+    const R g3 = ld(rgt ? A.g[1] + k : A.g[3] + r0 + xp);
+    t[1] = lft ? (R)2 * w5k * ((R)lp.side_T[0] - (R)lp.T_sh) - g1 : g1;
+    t[3] = rgt ? (R)2 * w5k * ((R)lp.side_T[1] - (R)lp.T_sh) - g3 : g3;
     if (bot) {
         const R u = (R)lp.wall_ux[0] * (R)lp.rho0 * (R)(1.0 / 6.0);
         s[2] = ld(A.f[4] + k) - fs[4];
@@ -255,8 +265,8 @@ __device__ __forceinline__ void pull_node(const Pops<typename S::T>& A, const LP
         t[2] = -ld(A.g[4] + k) + (R)2 * w5k * ((R)lp.wall_T[0] - (R)lp.T_sh);
     } else {
         s[2] = ld(A.f[2] + rm + x) - fs[2];
-        s[5] = ld(A.f[5] + rm + xm) - fs[5];
-        s[6] = ld(A.f[6] + rm + xp) - fs[6];
+        s[5] = ld(lft ? A.f[7] + k : A.f[5] + rm + xm) - fs[5];
+        s[6] = ld(rgt ? A.f[8] + k : A.f[6] + rm + xp) - fs[6];
         t[2] = ld(A.g[2] + rm + x);
     }
     if (top) {
@@ -267,8 +277,8 @@ __device__ __forceinline__ void pull_node(const Pops<typename S::T>& A, const LP
         t[4] = -ld(A.g[2] + k) + (R)2 * w5k * ((R)lp.wall_T[1] - (R)lp.T_sh);
     } else {
         s[4] = ld(A.f[4] + rp + x) - fs[4];
-        s[7] = ld(A.f[7] + rp + xp) - fs[7];
-        s[8] = ld(A.f[8] + rp + xm) - fs[8];
+        s[7] = ld(rgt ? A.f[5] + k : A.f[7] + rp + xp) - fs[7];
+        s[8] = ld(lft ? A.f[6] + k : A.f[8] + rp + xm) - fs[8];
         t[4] = ld(A.g[4] + rp + x);
     }
 }

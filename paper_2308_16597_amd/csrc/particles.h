@@ -15,13 +15,15 @@ constexpr int BINCAP = 7;
 
 // ------------------------------------------------------------- geometry ----
 // The exact solid test shared by every kernel that builds or reads the
-// solid map: dx = (i - X) with the minimum image along the periodic x axis,
-// dy = j - Y, inside when dx*dx + dy*dy <= r*r (no fused multiply-add: the
-// translation unit is compiled with -ffp-contract=off).
-__device__ __forceinline__ double min_image_x(double d, int nx) {
-    const double h = 0.5 * nx;
-    if (d > h) return d - nx;
-    if (d < -h) return d + nx;
+// solid map: dx = (i - X) with the minimum image along a periodic x axis
+// (the plain difference in the closed cavity), dy = j - Y, inside when
+// dx*dx + dy*dy <= r*r (no fused multiply-add: the translation unit is
+// compiled with -ffp-contract=off).
+__device__ __forceinline__ double min_image_x(double d, const LP& lp) {
+    if (!lp.periodic_x) return d;
+    const double h = 0.5 * lp.nx;
+    if (d > h) return d - lp.nx;
+    if (d < -h) return d + lp.nx;
     return d;
 }
 
@@ -96,6 +98,12 @@ __device__ __forceinline__ bool particle_ok(const PState& P, const LP& lp) {
 __device__ __forceinline__ int wrap_x(int x, int nx) {
     x %= nx;
     return x < 0 ? x + nx : x;
+}
+// Column of lattice coordinate x: wrapped on a periodic axis; -1 beyond the
+// side walls of the closed cavity (not a node).
+__device__ __forceinline__ int col_of(int x, const LP& lp) {
+    if (lp.periodic_x) return wrap_x(x, lp.nx);
+    return (x >= 0 && x < lp.nx) ? x : -1;
 }
 
 // Link fraction q of Sec. 2.3 for the circle: the nearer root of

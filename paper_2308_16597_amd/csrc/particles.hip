@@ -116,7 +116,7 @@ __device__ __forceinline__ void links_body(const RunStep& rs, unsigned bid, int 
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int p = (int)bid * ppb + w;
     const bool have_p = w < ppb && p < lp.np;
-    const int nx = lp.nx, pitch = lp.pitch;
+    const int pitch = lp.pitch;
 
     const size_t wl = links_wave_lds(lp.nwin) / sizeof(uint2);
     int* win = (int*)(smem + (size_t)w * wl);
@@ -141,9 +141,8 @@ __device__ __forceinline__ void links_body(const RunStep& rs, unsigned bid, int 
             for (int u = 0; u < 8; ++u) {
                 const int idx = base + u * 64 + lane;
                 const int b = idx / wn.nxw, a = idx - b * wn.nxw;
-                const int yy = wn.y0 + b;
-                v[u] = (idx < nw && in_rows(yy, lp)) ? Ocur[(size_t)yy * pitch + wrap_x(wn.x0 + a, nx)]
-                                                      : OUTSIDE;
+                const int yy = wn.y0 + b, xx = col_of(wn.x0 + a, lp);
+                v[u] = (idx < nw && in_rows(yy, lp) && xx >= 0) ? Ocur[(size_t)yy * pitch + xx] : OUTSIDE;
             }
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
@@ -156,7 +155,7 @@ __device__ __forceinline__ void links_body(const RunStep& rs, unsigned bid, int 
         for (int idx = lane; idx < nw; idx += 64) {
             const int b = idx / wn.nxw, a = idx - b * wn.nxw;
             if (win[idx] != -1) continue;
-            const unsigned code = (unsigned)wrap_x(wn.x0 + a, nx) | ((unsigned)(wn.y0 + b) << 16);
+            const unsigned code = (unsigned)col_of(wn.x0 + a, lp) | ((unsigned)(wn.y0 + b) << 16);
 #pragma unroll
             for (int d = 1; d < 9; ++d) {
                 const int ta = a + EXd(d), tb = b + EYd(d);
@@ -208,11 +207,11 @@ __device__ __forceinline__ void link_pass_link(const RunStep& rs, const PState& 
     auto F = [&](int a) { return (const PT_GLOBAL ST<MODE>*)rs.A[a]; };
     auto Fw = [&](int a) { return (PT_GLOBAL ST<MODE>*)rs.A[a]; };
     const PT_GLOBAL int32_t* __restrict__ Ocur = gl(rs.Ocur);
-    const int nx = lp.nx, pitch = lp.pitch;
+    const int pitch = lp.pitch;
     const int ib = OPPd(i), ex = EXd(i), ey = EYd(i);
-    const int x1 = wrap_x(x - ex, nx), y1 = y - ey;
-    const int x2 = wrap_x(x - 2 * ex, nx), y2 = y - 2 * ey;
-    const bool in1 = in_rows(y1, lp), in2 = in_rows(y2, lp);
+    const int x1 = col_of(x - ex, lp), y1 = y - ey;
+    const int x2 = col_of(x - 2 * ex, lp), y2 = y - 2 * ey;
+    const bool in1 = in_rows(y1, lp) && x1 >= 0, in2 = in_rows(y2, lp) && x2 >= 0;
     const size_t k = (size_t)y * pitch + x;
     const size_t k1 = in1 ? (size_t)y1 * pitch + x1 : k;
     const size_t k2 = in2 ? (size_t)y2 * pitch + x2 : k;
@@ -228,7 +227,7 @@ __device__ __forceinline__ void link_pass_link(const RunStep& rs, const PState& 
     }
     const bool have1 = in1 && o1 == -1;
     const bool have2 = have1 && in2 && o2 == -1;
-    const double dx = min_image_x((double)x - P.x, nx);
+    const double dx = min_image_x((double)x - P.x, lp);
     const double dy = (double)y - P.y;
     const double q = link_q(dx, dy, P.r, i);
     const double rx = dx + q * ex, ry = dy + q * ey;   // x_w - X_c
@@ -236,7 +235,7 @@ __device__ __forceinline__ void link_pass_link(const RunStep& rs, const PState& 
     const double w9i = i <= 4 ? 1.0 / 9.0 : 1.0 / 36.0;
     const double wall = 6.0 * w9i * lp.rho0 * (-(ex * uwx) - ey * uwy);
     const double fnew = bouzidi(q, fi, fi1, fi2, fib, fib1, have1, have2, wall);
-    const size_t kb = (size_t)(y + ey) * pitch + wrap_x(x + ex, nx);
+    const size_t kb = (size_t)(y + ey) * pitch + col_of(x + ex, lp);   // a node of P
     S::st(Fw(ib) + kb, (typename S::R)fnew);
     if (i <= 4) {
         const double gnew = thermal_link(q, gi, gi1, gib, have1, lp.w5_k, lp.particle_T - lp.T_sh);
@@ -309,8 +308,8 @@ __device__ __forceinline__ void link_pass_direct_body(const RunStep& rs, unsigne
     int own[9];
 #pragma unroll
     for (int d = 1; d < 9; ++d) {
-        const int yy = y + EYd(d);
-        own[d] = in_rows(yy, lp) ? Ocur[(size_t)yy * lp.pitch + wrap_x(x + EXd(d), lp.nx)] : -1;
+        const int yy = y + EYd(d), xx = col_of(x + EXd(d), lp);
+        own[d] = in_rows(yy, lp) && xx >= 0 ? Ocur[(size_t)yy * lp.pitch + xx] : -1;
     }
     for (int d = 1; d < 9; ++d) {
         if (own[d] < 0) continue;
@@ -328,7 +327,7 @@ __device__ __forceinline__ void link_pass_direct_body(const RunStep& rs, unsigne
 // surface gap along the centre line, force scale pi rp rq (rho_p - rho_f) g.
 __device__ __forceinline__ void repulsion_pair(const LP& lp, double xp, double yp, double rp, double xq,
                                                double yq, double rq, double& fx, double& fy) {
-    const double dx = min_image_x(xp - xq, lp.nx);
+    const double dx = min_image_x(xp - xq, lp);
     const double dy = yp - yq;
     const double dist = sqrt(dx * dx + dy * dy);
     const double gap = dist - rp - rq;
@@ -387,8 +386,8 @@ __device__ __forceinline__ void particles_body(const RunStep& rs, unsigned bid) 
         if (particle_ok(po, lp) && wo.nxw <= lp.nwin && wo.nyw <= lp.nwin)
             for (int idx = lane; idx < wo.nxw * wo.nyw; idx += 64) {
                 const int b = idx / wo.nxw, a = idx - b * wo.nxw;
-                const int yy = wo.y0 + b;
-                if (in_rows(yy, lp)) Onext[(size_t)yy * lp.pitch + wrap_x(wo.x0 + a, lp.nx)] = -1;
+                const int yy = wo.y0 + b, xx = col_of(wo.x0 + a, lp);
+                if (in_rows(yy, lp) && xx >= 0) Onext[(size_t)yy * lp.pitch + xx] = -1;
             }
     }
     const PState P = ld_state(Pc + p);
@@ -405,18 +404,22 @@ __device__ __forceinline__ void particles_body(const RunStep& rs, unsigned bid) 
             const int j = lane / BINCAP, sl = lane - j * BINCAP;
             const int dcx = j % 3 - 1, dcy = j / 3 - 1;
             const int yy = cy + dcy;
+            int xx = cx + dcx;
             bool cell_ok = yy >= 0 && yy < lp.ncy;
-            if (lp.ncx == 1 && dcx != 0) cell_ok = false;   // the 3 x-neighbours coincide
-            if (lp.ncx == 2 && dcx == 1) cell_ok = false;
-            if (cell_ok) {
-                int xx = cx + dcx;
+            if (!lp.periodic_x) {
+                if (xx < 0 || xx >= lp.ncx) cell_ok = false;   // beyond a side wall
+            } else {
+                if (lp.ncx == 1 && dcx != 0) cell_ok = false;   // the 3 x-neighbours coincide
+                if (lp.ncx == 2 && dcx == 1) cell_ok = false;
                 xx = xx < 0 ? xx + lp.ncx : (xx >= lp.ncx ? xx - lp.ncx : xx);
+            }
+            if (cell_ok) {
                 const int c = yy * lp.ncx + xx;
                 if ((unsigned)sl < min(cnt_cur[c], (unsigned)BINCAP)) {
                     const int qq = (int)bins_cur[(size_t)c * BINCAP + sl];
                     if (qq != p) {
                         const PState Q = ld_state(Pc + qq);
-                        const double dx = min_image_x(P.x - Q.x, lp.nx);
+                        const double dx = min_image_x(P.x - Q.x, lp);
                         const double dy = P.y - Q.y;
                         if (sqrt(dx * dx + dy * dy) - P.r - Q.r <= lp.rep_range) {
                             near = true;
@@ -441,10 +444,22 @@ __device__ __forceinline__ void particles_body(const RunStep& rs, unsigned bid) 
             Ry += __shfl(fy, b);
         }
     }
-    if (lp.repulsion) {
-        double wy = 0.0;
+    if (lp.repulsion) {   // the flat walls: Eq. (15) with the wall plane as the partner surface
+        const double C = kPi * (P.r * P.r) * (lp.rho_ratio - 1.0) * lp.rho0 * lp.gravity;
+        double wx = 0.0, wy = 0.0;
+        if (!lp.periodic_x) {
+            const double gap_l = (P.x + 0.5) - P.r;
+            if (gap_l <= lp.rep_range) {
+                const double t = (gap_l - lp.rep_range) / lp.rep_range;
+                wx += C / lp.rep_eps * (t * t);
+            }
+            const double gap_r = ((lp.nx - 0.5) - P.x) - P.r;
+            if (gap_r <= lp.rep_range) {
+                const double t = (gap_r - lp.rep_range) / lp.rep_range;
+                wx -= C / lp.rep_eps * (t * t);
+            }
+        }
         if (!lp.periodic_y) {
-            const double C = kPi * (P.r * P.r) * (lp.rho_ratio - 1.0) * lp.rho0 * lp.gravity;
             const double gb = (P.y + 0.5) - P.r;
             if (gb <= lp.rep_range) {
                 const double t = (gb - lp.rep_range) / lp.rep_range;
@@ -456,6 +471,7 @@ __device__ __forceinline__ void particles_body(const RunStep& rs, unsigned bid) 
                 wy -= C / lp.rep_eps * (t * t);
             }
         }
+        Rx += wx;
         Ry += wy;
     }
     if (lane != 0) return;
@@ -482,9 +498,11 @@ __device__ __forceinline__ void particles_body(const RunStep& rs, unsigned bid) 
     N.x = P.x + 0.5 * (P.ux + N.ux);
     N.y = P.y + 0.5 * (P.uy + N.uy);
     N.th = P.th + 0.5 * (P.om + N.om);
-    if (N.x < 0.0) N.x += lp.nx;
-    else if (N.x >= lp.nx) N.x -= lp.nx;
-    const double ddx = min_image_x(N.x - P.x, lp.nx), ddy = N.y - P.y;
+    if (lp.periodic_x) {
+        if (N.x < 0.0) N.x += lp.nx;
+        else if (N.x >= lp.nx) N.x -= lp.nx;
+    }
+    const double ddx = min_image_x(N.x - P.x, lp), ddy = N.y - P.y;
     if (!(ddx * ddx + ddy * ddy <= 0.25)) atomicOr(status, ST_OVERSPEED);
     st_state(rs.Pn + p, N);
     bin_insert(N, p, rs.bins_next, rs.cnt_next, status, lp);
@@ -522,8 +540,10 @@ __device__ __forceinline__ void mask_body(const RunStep& rs, unsigned bid) {
     if (with_prev) {
         Q = ld_state(Pprev + p);
         Win v = window_of(Q);
-        if (v.x0 - w.x0 > lp.nx / 2) v.x0 -= lp.nx;
-        else if (w.x0 - v.x0 > lp.nx / 2) v.x0 += lp.nx;
+        if (lp.periodic_x) {   // the two windows on the same side of the seam
+            if (v.x0 - w.x0 > lp.nx / 2) v.x0 -= lp.nx;
+            else if (w.x0 - v.x0 > lp.nx / 2) v.x0 += lp.nx;
+        }
         xa = min(xa, v.x0);
         xb = max(xb, v.x0 + v.nxw);
         ya = min(ya, v.y0);
@@ -541,15 +561,15 @@ __device__ __forceinline__ void mask_body(const RunStep& rs, unsigned bid) {
         if (idx < bw * bh) {
             const int b = idx / bw, a = idx - b * bw;
             const int yy = ya + b;
-            if (in_rows(yy, lp)) {
-                const int xx = wrap_x(xa + a, lp.nx);
-                const double dx = min_image_x((double)xx - P.x, lp.nx);
+            const int xx = col_of(xa + a, lp);
+            if (in_rows(yy, lp) && xx >= 0) {
+                const double dx = min_image_x((double)xx - P.x, lp);
                 const double dy = (double)yy - P.y;
                 const size_t k = (size_t)yy * lp.pitch + xx;
                 if (dx * dx + dy * dy <= r2) {
                     atomicMin((unsigned*)&O[k], (unsigned)p);
                 } else if (with_prev) {
-                    const double qx = min_image_x((double)xx - Q.x, lp.nx);
+                    const double qx = min_image_x((double)xx - Q.x, lp);
                     const double qy = (double)yy - Q.y;
                     nb = qx * qx + qy * qy <= q2;
                     code = (unsigned)xx | ((unsigned)yy << 16);
@@ -586,7 +606,7 @@ __device__ void refill_node(const Pops<ST<MODE>>& A, const Pops<ST<MODE>>& B, co
     using S = Store<MODE>;
     using R = typename S::R;
     const size_t k0 = (size_t)y * lp.pitch + x;
-    const double dx = min_image_x((double)x - P.x, lp.nx);
+    const double dx = min_image_x((double)x - P.x, lp);
     const double dy = (double)y - P.y;
     int c = 1;
     double best = dx * EXd(1) + dy * EYd(1);
@@ -605,9 +625,9 @@ __device__ void refill_node(const Pops<ST<MODE>>& A, const Pops<ST<MODE>>& B, co
     const bool mine = Ocur[k0] == p && Onext[k0] == -1;
     for (int m = 0; m < 3; ++m) {
         ys[m] = y + (m + 1) * EYd(c);
-        xs[m] = wrap_x(x + (m + 1) * EXd(c), lp.nx);
+        xs[m] = col_of(x + (m + 1) * EXd(c), lp);
         fl[m] = false;
-        if (in_rows(ys[m], lp)) {
+        if (in_rows(ys[m], lp) && xs[m] >= 0) {
             const size_t km = (size_t)ys[m] * lp.pitch + xs[m];
             fl[m] = Ocur[km] == -1 && Onext[km] == -1;
             R tt[5];
@@ -721,7 +741,7 @@ __global__ void k_link_q(const PState* __restrict__ Pc, const uint2* __restrict_
     const uint2 L = links[l];
     const int x = (int)(L.x & 0xffffu), y = (int)(L.x >> 16), i = (int)(L.y & 15u), p = (int)(L.y >> 4);
     const PState P = Pc[p];
-    const double dx = min_image_x((double)x - P.x, lp.nx);
+    const double dx = min_image_x((double)x - P.x, lp);
     const double dy = (double)y - P.y;
     node[l] = y * lp.nx + x;
     dir[l] = i;

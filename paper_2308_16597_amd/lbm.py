@@ -41,6 +41,7 @@ class LbmParams(ctypes.Structure):
         ("sT_e", _d), ("sT_p", _d), ("wall_T", _d * 2), ("wall_ux", _d * 2), ("T_fluid0", _d),
         ("particle_T", _d), ("rho_ratio", _d), ("repulsion", _i), ("rep_eps", _d),
         ("rep_range", _d), ("T_shift", _d), ("max_particles", _i), ("max_diameter", _d),
+        ("side_T", _d * 2),
     ]
 
 
@@ -113,7 +114,7 @@ def lbm_params_default(**overrides):
     p = LbmParams()
     _lib.lbm_params_default(ctypes.byref(p))
     for k, v in overrides.items():
-        if k in ("wall_T", "wall_ux"):
+        if k in ("wall_T", "wall_ux", "side_T"):
             getattr(p, k)[0], getattr(p, k)[1] = float(v[0]), float(v[1])
         elif k == "storage" and isinstance(v, str):
             p.storage = STORE[v]

@@ -65,20 +65,34 @@ WORKLOADS = {
     # step within 20 steps)
     "dense": dict(nx=4096, ny=4096, n=64000, d=10.0, seed=5, gap=3.0, Ra=1e8, Pr=0.7,
                   rho_ratio=1.5, steps=1000),
+    # The paper's benchmark case (Sec. 2.6.3, the 4,800-particle sedimentation
+    # and its parameter table): closed 4000^2 cavity with cold walls, 60 lines
+    # of 80 hot particles of diameter 40 at 50 apart in the upper part
+    # (37.7 % solid), rho_p/rho_f = 1.1, Pr 5, Gr_p 60, lattice parameters
+    # as tabulated; 6000 steps in the paper's timing.
+    "e4_cavity": dict(nx=4000, ny=4000, n=4800, d=40.0, layout="grid", rows=60, cols=80,
+                      spacing=50.0, rho_ratio=1.1, closed=True, steps=6000,
+                      lattice=dict(nu=0.01, alpha=0.002, gravity=7.84e-6, beta=1.20e-2)),
 }
 
 
 def workload_params(name, storage=0):
     """Parameter dict (lbm_params field names) of a named workload: hot
-    particles (T = 1) in cold fluid between cold walls (T = 0), gravity -y,
-    repulsion on, periodic x."""
+    particles (T = 1) in cold fluid (T = 0) between cold walls, gravity -y,
+    repulsion on; periodic x, or a closed cavity with cold side walls.  The
+    lattice parameters are the tabulated ones where the workload gives them,
+    else mapped from (Ra, Pr) on the height."""
     w = WORKLOADS[name]
-    phys = from_dimensionless(w["ny"], w["Ra"], w["Pr"], w["d"], w["rho_ratio"])
-    return dict(nx=w["nx"], ny=w["ny"], storage=storage, rho0=1.0, nu=phys["nu"],
-                alpha=phys["alpha"], gravity=phys["gravity"], beta=phys["beta"], T_ref=0.0,
-                wall_T=(0.0, 0.0), wall_ux=(0.0, 0.0), T_fluid0=0.0, particle_T=1.0,
-                rho_ratio=w["rho_ratio"], repulsion=1, rep_eps=1e-3, rep_range=3.0,
-                max_particles=w["n"], max_diameter=w["d"])
+    phys = w.get("lattice") or from_dimensionless(w["ny"], w["Ra"], w["Pr"], w["d"], w["rho_ratio"])
+    closed = bool(w.get("closed"))
+    out = dict(nx=w["nx"], ny=w["ny"], storage=storage, rho0=1.0, nu=phys["nu"],
+               alpha=phys["alpha"], gravity=phys["gravity"], beta=phys["beta"], T_ref=0.0,
+               wall_T=(0.0, 0.0), wall_ux=(0.0, 0.0), T_fluid0=0.0, particle_T=1.0,
+               rho_ratio=w["rho_ratio"], repulsion=1, rep_eps=1e-3, rep_range=3.0,
+               max_particles=w["n"], max_diameter=w["d"], periodic_x=0 if closed else 1)
+    if closed:
+        out["side_T"] = (0.0, 0.0)
+    return out
 
 
 def mlups(mesh_size, steps, seconds):

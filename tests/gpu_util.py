@@ -7,7 +7,7 @@ from oracle import Oracle
 ORACLE_KEYS = {"nx", "ny", "periodic_x", "periodic_y", "rho0", "nu", "alpha", "gravity", "beta",
                "T_ref", "body_fx", "s_e", "s_eps", "s_q", "a_T", "sT_e", "sT_p", "wall_T",
                "wall_ux", "T_fluid0", "particle_T", "rho_ratio", "repulsion", "rep_eps",
-               "rep_range"}
+               "rep_range", "side_T"}
 
 
 def make_pair(torch_memory=True, **kw):

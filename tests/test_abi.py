@@ -19,19 +19,26 @@ def test_every_declared_function_is_exported():
 
 
 def test_abi_version_and_defaults():
-    assert lbm.lbm_abi_version() == 1
+    assert lbm.lbm_abi_version() == 2
     p = lbm.lbm_params_default()
-    assert (p.abi_version, p.nx, p.ny, p.periodic_x, p.periodic_y, p.storage) == (1, 64, 64, 1, 0, 0)
+    assert (p.abi_version, p.nx, p.ny, p.periodic_x, p.periodic_y, p.storage) == (2, 64, 64, 1, 0, 0)
     assert (p.rho0, p.a_T, p.rep_eps, p.rep_range, p.repulsion) == (1.0, -2.0, 1e-3, 3.0, 1)
+    assert tuple(p.side_T) == (0.0, 0.0)
 
 
-@pytest.mark.parametrize("bad", [dict(nx=4), dict(ny=70000), dict(periodic_x=0), dict(storage=9),
+def test_params_struct_matches_the_header_layout():
+    # side_T is the last field: its offset is the size of every field before it
+    assert lbm.LbmParams.side_T.offset == 232 and ctypes.sizeof(lbm.LbmParams) == 248
+
+
+@pytest.mark.parametrize("bad", [dict(nx=4), dict(ny=70000), dict(periodic_x=2), dict(storage=9),
                                  dict(nu=0.0), dict(alpha=-1.0), dict(s_q=2.5), dict(a_T=-5.0),
                                  dict(max_particles=-1),
                                  dict(max_particles=10, max_diameter=2.0),
                                  dict(max_particles=10, max_diameter=12.0, periodic_y=1),
                                  dict(nx=16, max_particles=10, max_diameter=14.0),
-                                 dict(gravity=float("inf")), dict(abi_version=7)])
+                                 dict(gravity=float("inf")), dict(abi_version=7),
+                                 dict(abi_version=1), dict(periodic_x=0, side_T=(float("nan"), 0.0))])
 def test_invalid_parameters_rejected_on_the_host(bad):
     p = lbm.lbm_params_default(**bad)
     assert lbm.lbm_bytes_required(p) == 0
