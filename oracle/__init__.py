@@ -69,6 +69,17 @@ def lib():
         L.orc_last_error.argtypes = [vp]
         L.orc_last_error.restype = ctypes.c_char_p
         L.orc_set_particles.argtypes = [vp, _c_i, vp]
+        L.orc_set_particles_ellipse.argtypes = [vp, _c_i, vp]
+        L.orc_link_q_ellipse.argtypes = [_c_d, _c_d, _c_d, _c_d, _c_d, _c_i]
+        L.orc_link_q_ellipse.restype = _c_d
+        L.orc_inside_shape.argtypes = [_c_d, _c_d, _c_d, _c_d, _c_d]
+        L.orc_inside_shape.restype = _c_i
+        L.orc_refill_direction.argtypes = [_c_d, _c_d, _c_d, _c_d, _c_d]
+        L.orc_refill_direction.restype = _c_i
+        L.orc_repulsion_pair_ellipse.argtypes = [ctypes.POINTER(OrcParams)] + [_c_d] * 10 + [vp]
+        L.orc_repulsion_walls_ellipse.argtypes = [ctypes.POINTER(OrcParams)] + [_c_d] * 5 + [vp]
+        L.orc_newton_euler_ellipse.argtypes = [ctypes.POINTER(OrcParams), vp, _c_d, _c_d, _c_d,
+                                               _c_d, vp]
         L.orc_set_equilibrium.argtypes = [vp, vp, vp, vp, vp]
         L.orc_step.argtypes = [vp, _c_i]
         L.orc_steps_done.argtypes = [vp]
@@ -138,6 +149,10 @@ class Oracle:
     def set_particles(self, rows7):
         rows7 = np.ascontiguousarray(rows7, dtype=np.float64).reshape(-1, 7)
         self._check(lib().orc_set_particles(self._h, rows7.shape[0], _ptr(rows7)))
+
+    def set_particles_ellipse(self, rows8):
+        rows8 = np.ascontiguousarray(rows8, dtype=np.float64).reshape(-1, 8)
+        self._check(lib().orc_set_particles_ellipse(self._h, rows8.shape[0], _ptr(rows8)))
 
     def set_equilibrium(self, rho, ux, uy, T):
         arrs = [np.ascontiguousarray(a, dtype=np.float64).reshape(self.ny, self.nx)
@@ -213,6 +228,18 @@ def link_q(dx, dy, r, i):
     return lib().orc_link_q(float(dx), float(dy), float(r), int(i))
 
 
+def link_q_ellipse(dx, dy, a, b, theta, i):
+    return lib().orc_link_q_ellipse(float(dx), float(dy), float(a), float(b), float(theta), int(i))
+
+
+def inside_shape(dx, dy, a, b, theta):
+    return bool(lib().orc_inside_shape(float(dx), float(dy), float(a), float(b), float(theta)))
+
+
+def refill_direction(dx, dy, a, b, theta):
+    return lib().orc_refill_direction(float(dx), float(dy), float(a), float(b), float(theta))
+
+
 def bouzidi(q, i, fi_xf, fi_xf1, fi_xf2, fib_xf, fib_xf1, have1, have2, rho0, uwx, uwy):
     return lib().orc_bouzidi(q, i, fi_xf, fi_xf1, fi_xf2, fib_xf, fib_xf1, int(have1),
                              int(have2), rho0, uwx, uwy)
@@ -231,6 +258,28 @@ def repulsion_pair(params, xp, yp, rp, xq, yq, rq):
 def repulsion_walls(params, xp, yp, rp):
     out = np.empty(2)
     lib().orc_repulsion_walls(ctypes.byref(params), xp, yp, rp, _ptr(out))
+    return out
+
+
+def repulsion_pair_ellipse(params, p, q):
+    """p, q: (x, y, a, b, theta) of the two particles."""
+    out = np.empty(2)
+    lib().orc_repulsion_pair_ellipse(ctypes.byref(params), *[float(v) for v in p],
+                                     *[float(v) for v in q], _ptr(out))
+    return out
+
+
+def repulsion_walls_ellipse(params, x, y, a, b, theta):
+    out = np.empty(2)
+    lib().orc_repulsion_walls_ellipse(ctypes.byref(params), float(x), float(y), float(a), float(b),
+                                      float(theta), _ptr(out))
+    return out
+
+
+def newton_euler_ellipse(params, state7, b, Fx, Fy, Tz):
+    st = np.ascontiguousarray(state7, dtype=np.float64)
+    out = np.empty(7)
+    lib().orc_newton_euler_ellipse(ctypes.byref(params), _ptr(st), float(b), Fx, Fy, Tz, _ptr(out))
     return out
 
 

@@ -18,13 +18,16 @@
  *             constraint; Eq. (17): equilibrium refilling of g.
  *   Sec. 3    links between fluid nodes and particles, collected anew every
  *             step.
+ *   Sec. 2.6.2 and App. A: particles may be ellipses; the solid test, the link
+ *             fraction, the refill normal, the repulsion gaps, mass and
+ *             inertia then follow the ellipse (readings at the point of use).
  * Where the paper is silent (the MRT matrices, equilibria and forcing moments,
  * fallbacks when an interpolation stencil leaves the fluid, wall handling,
  * the integrator) the reading used is stated at the point of use.
  *
  * There is no blocking, fusion or reordering: each step runs the phases one
  * after the other over whole arrays.  The only shortcut is that the solid
- * test of a particle is evaluated over a bounding box that contains its disk,
+ * test of a particle is evaluated over a bounding box that contains its shape,
  * which cannot change the result.
  */
 #include "ptlbm_oracle.h"
@@ -35,6 +38,7 @@
 #include <string.h>
 
 static const double ORC_PI = 3.14159265358979323846;
+#define PSTRIDE 11
 
 /* ---------------------------------------------------------------- lattice */
 
@@ -83,7 +87,8 @@ struct orc_sim {
     double *fp, *gp;        /* post-collision populations */
     int32_t *owner, *owner_new;
     int np;
-    double *P;              /* particles, np rows of 10 */
+    double *P;              /* particles, np rows of PSTRIDE: x, y, a, u_x, u_y,
+                               theta, Omega, F_x, F_y, T_z, b */
     int64_t steps;
     char err[256];
 };
@@ -249,19 +254,40 @@ static double min_image(double d, int n, int periodic) {
     return d;
 }
 
-/* A node is inside particle p when |x - X_p|^2 <= r_p^2 (a node exactly on
- * the circle counts as solid, so the link fraction q lies in (0, 1]). */
+/* Particle shapes (Sec. 2.6.2 uses ellipses, the other cases circles): a
+ * record holds the semi-axis a along the body axis at angle theta from +x
+ * and the semi-axis b across it; b == a is a circle, evaluated with the
+ * plain circle formulas.  (u, v) are the body-frame coordinates of an offset
+ * (dx, dy): u along the body axis. */
+static void to_body(double dx, double dy, double c, double s, double* u, double* v) {
+    *u = dx * c + dy * s;
+    *v = dy * c - dx * s;
+}
+
+/* Offset (dx, dy) from the centre inside the shape: dx^2 + dy^2 <= r^2 for a
+ * circle; (u/a)^2 + (v/b)^2 <= 1 for an ellipse, evaluated as
+ * b^2 u^2 + a^2 v^2 <= a^2 b^2.  On the boundary counts as inside. */
+int32_t orc_inside_shape(double dx, double dy, double a, double b, double theta) {
+    if (a == b) return dx * dx + dy * dy <= a * a;
+    double u, v;
+    to_body(dx, dy, cos(theta), sin(theta), &u, &v);
+    return (u * u) * (b * b) + (v * v) * (a * a) <= (a * a) * (b * b);
+}
+
+/* A node is inside particle p when its offset from X_p (minimum image on a
+ * periodic axis) is inside the shape (a node exactly on the boundary counts
+ * as solid, so the link fraction q lies in (0, 1]). */
 static int inside(const orc_sim* s, int i, int j, const double* P) {
     double dx = min_image((double)i - P[0], s->nx, s->p.periodic_x);
     double dy = min_image((double)j - P[1], s->ny, s->p.periodic_y);
-    return dx * dx + dy * dy <= P[2] * P[2];
+    return orc_inside_shape(dx, dy, P[2], P[10], P[5]);
 }
 
 /* owner = lowest particle index whose disk holds the node, else -1. */
 static void compute_owner(const orc_sim* s, int32_t* owner) {
     for (long k = 0; k < s->n; ++k) owner[k] = -1;
     for (int q = 0; q < s->np; ++q) {
-        const double* P = s->P + 10 * q;
+        const double* P = s->P + PSTRIDE * q;   /* the box of half-width a holds the shape */
         int i0 = (int)floor(P[0] - P[2]), i1 = (int)floor(P[0] + P[2]) + 1;
         int j0 = (int)floor(P[1] - P[2]), j1 = (int)floor(P[1] + P[2]) + 1;
         for (int jj = j0; jj <= j1; ++jj) {
@@ -291,6 +317,26 @@ double orc_link_q(double dx, double dy, double r, int32_t i) {
     double disc = b * b - a * c;
     if (disc < 0.0) disc = 0.0;
     double q = (-b - sqrt(disc)) / a;
+    if (q < 0.0) q = 0.0;
+    if (q > 1.0) q = 1.0;
+    return q;
+}
+
+/* The same for the ellipse of semi-axes a, b at angle theta (a circle when
+ * b == a): in body coordinates the smaller root of
+ * b^2 (u + t e_u)^2 + a^2 (v + t e_v)^2 = a^2 b^2. */
+double orc_link_q_ellipse(double dx, double dy, double a, double b, double theta, int32_t i) {
+    if (a == b) return orc_link_q(dx, dy, a, i);
+    double c = cos(theta), s = sin(theta), u, v, eu, ev;
+    to_body(dx, dy, c, s, &u, &v);
+    to_body((double)EX[i], (double)EY[i], c, s, &eu, &ev);
+    double a2 = a * a, b2 = b * b;
+    double A = b2 * (eu * eu) + a2 * (ev * ev);
+    double B = b2 * (u * eu) + a2 * (v * ev);
+    double C = (b2 * (u * u) + a2 * (v * v)) - a2 * b2;
+    double disc = B * B - A * C;
+    if (disc < 0.0) disc = 0.0;
+    double q = (-B - sqrt(disc)) / A;
     if (q < 0.0) q = 0.0;
     if (q > 1.0) q = 1.0;
     return q;
@@ -344,69 +390,120 @@ double orc_thermal_link(double q, int32_t i, double gi_xf, double gi_xf1, double
 
 /* ------------------------------------------------------ particle motion */
 
+/* Distance from the centre to the boundary of a shape along the unit
+ * direction (nx_, ny_): r for a circle; for an ellipse
+ * a b / sqrt(b^2 n_u^2 + a^2 n_v^2) with (n_u, n_v) the direction in body
+ * coordinates. */
+static double radial_extent(double a, double b, double theta, double nx_, double ny_) {
+    if (a == b) return a;
+    double nu, nv;
+    to_body(nx_, ny_, cos(theta), sin(theta), &nu, &nv);
+    return (a * b) / sqrt((b * b) * (nu * nu) + (a * a) * (nv * nv));
+}
+
+/* Half-extents of a shape along x and along y (the distance from the centre
+ * to its supporting lines): r for a circle; sqrt(a^2 c^2 + b^2 s^2) along x
+ * and sqrt(a^2 s^2 + b^2 c^2) along y for an ellipse at angle theta. */
+static void half_extents(double a, double b, double theta, double* hx, double* hy) {
+    if (a == b) {
+        *hx = a;
+        *hy = a;
+        return;
+    }
+    double c = cos(theta), s = sin(theta);
+    *hx = sqrt((a * a) * (c * c) + (b * b) * (s * s));
+    *hy = sqrt((a * a) * (s * s) + (b * b) * (c * c));
+}
+
+/* Radius of the disk of equal area: r for a circle, sqrt(a b) for an
+ * ellipse (the force scale C of Eq. (15) is the particle's immersed weight
+ * pi r^2 (rho_p - rho_f) g). */
+static double area_radius(double a, double b) { return a == b ? a : sqrt(a * b); }
+
 /* Spring repulsion, Sec. 2.4 Eq. (15), on particle p from particle q:
- * |x_s| is the surface gap |X_p - X_q| - r_p - r_q, the direction is the
+ * |x_s| is the surface gap along the centre line, |X_p - X_q| minus the two
+ * shapes' extents along it (r_p + r_q for circles), the direction is the
  * centre line from q to p, s = rep_range, eps = rep_eps, and the force scale
- * C = pi r^2 (rho_p - rho_f) g is taken with r^2 = r_p r_q so that the pair
- * forces are equal and opposite. */
-void orc_repulsion_pair(const orc_params* p, double xp, double yp, double rp,
-                        double xq, double yq, double rq, double out[2]) {
+ * C = pi r^2 (rho_p - rho_f) g is taken with r^2 = r_p r_q (equal-area radii)
+ * so that the pair forces are equal and opposite. */
+void orc_repulsion_pair_ellipse(const orc_params* p, double xp, double yp, double ap, double bp,
+                                double thp, double xq, double yq, double aq, double bq,
+                                double thq, double out[2]) {
     out[0] = 0.0;
     out[1] = 0.0;
     double dx = min_image(xp - xq, p->nx, p->periodic_x);
     double dy = yp - yq;
     double dist = sqrt(dx * dx + dy * dy);
-    double gap = dist - rp - rq;
+    double ep = radial_extent(ap, bp, thp, dx / dist, dy / dist);
+    double eq = radial_extent(aq, bq, thq, dx / dist, dy / dist);
+    double gap = dist - ep - eq;
     if (gap > p->rep_range) return;
-    double C = ORC_PI * (rp * rq) * (p->rho_ratio - 1.0) * p->rho0 * p->gravity;
+    double C = ORC_PI * (area_radius(ap, bp) * area_radius(aq, bq)) * (p->rho_ratio - 1.0) * p->rho0 *
+               p->gravity;
     double t = (gap - p->rep_range) / p->rep_range;
     double mag = C / p->rep_eps * (t * t);
     out[0] = mag * (dx / dist);
     out[1] = mag * (dy / dist);
 }
 
+void orc_repulsion_pair(const orc_params* p, double xp, double yp, double rp,
+                        double xq, double yq, double rq, double out[2]) {
+    orc_repulsion_pair_ellipse(p, xp, yp, rp, rp, 0.0, xq, yq, rq, rq, 0.0, out);
+}
+
 /* Repulsion from the flat walls (the y walls, and the side walls of a
  * closed cavity): |x_s| is the distance from the wall plane to the particle
- * surface, the force points away from the wall. */
-void orc_repulsion_walls(const orc_params* p, double xp, double yp, double rp, double out[2]) {
+ * surface (the centre's distance minus the shape's half-extent normal to
+ * the wall), the force points away from the wall; C with the particle's
+ * own equal-area radius. */
+void orc_repulsion_walls_ellipse(const orc_params* p, double xp, double yp, double a, double b,
+                                 double theta, double out[2]) {
     out[0] = 0.0;
     out[1] = 0.0;
-    double C = ORC_PI * (rp * rp) * (p->rho_ratio - 1.0) * p->rho0 * p->gravity;
+    double R = area_radius(a, b);
+    double C = ORC_PI * (R * R) * (p->rho_ratio - 1.0) * p->rho0 * p->gravity;
+    double hx, hy;
+    half_extents(a, b, theta, &hx, &hy);
     if (!p->periodic_x) {
-        double gap_l = (xp + 0.5) - rp;
+        double gap_l = (xp + 0.5) - hx;
         if (gap_l <= p->rep_range) {
             double t = (gap_l - p->rep_range) / p->rep_range;
             out[0] += C / p->rep_eps * (t * t);
         }
-        double gap_r = ((p->nx - 0.5) - xp) - rp;
+        double gap_r = ((p->nx - 0.5) - xp) - hx;
         if (gap_r <= p->rep_range) {
             double t = (gap_r - p->rep_range) / p->rep_range;
             out[0] -= C / p->rep_eps * (t * t);
         }
     }
     if (p->periodic_y) return;
-    double gap_b = (yp + 0.5) - rp;
+    double gap_b = (yp + 0.5) - hy;
     if (gap_b <= p->rep_range) {
         double t = (gap_b - p->rep_range) / p->rep_range;
         out[1] += C / p->rep_eps * (t * t);
     }
-    double gap_t = ((p->ny - 0.5) - yp) - rp;
+    double gap_t = ((p->ny - 0.5) - yp) - hy;
     if (gap_t <= p->rep_range) {
         double t = (gap_t - p->rep_range) / p->rep_range;
         out[1] -= C / p->rep_eps * (t * t);
     }
 }
 
+void orc_repulsion_walls(const orc_params* p, double xp, double yp, double rp, double out[2]) {
+    orc_repulsion_walls_ellipse(p, xp, yp, rp, rp, 0.0, out);
+}
+
 /* Newton-Euler update over one time step (Sec. 2.2 Eqs. (7)-(8); the
  * gyroscopic term vanishes in 2D).  Reading of the integrator: explicit
- * velocity update, trapezoidal position and angle update.  Mass and inertia
- * of a disk: M = rho_p pi r^2 with rho_p = rho_ratio rho0, I = M r^2 / 2.
- * state7 = (x, y, r, ux, uy, theta, omega). */
-void orc_newton_euler(const orc_params* p, const double state7[7], double Fx, double Fy,
-                      double Tz, double out7[7]) {
+ * velocity update, trapezoidal position and angle update.  Mass and inertia:
+ * M = rho_p pi a b with rho_p = rho_ratio rho0; I = M r^2 / 2 for a disk
+ * (b == a = r), I = M (a^2 + b^2) / 4 for an ellipse.
+ * state7 = (x, y, a, ux, uy, theta, omega); b the semi-axis across. */
+void orc_newton_euler_ellipse(const orc_params* p, const double state7[7], double b, double Fx,
+                              double Fy, double Tz, double out7[7]) {
     double r = state7[2];
-    double mass = p->rho_ratio * p->rho0 * ORC_PI * r * r;
-    double inertia = 0.5 * mass * r * r;
+    double mass = p->rho_ratio * p->rho0 * ORC_PI * r * b;
+    double inertia = r == b ? 0.5 * mass * r * r : 0.25 * mass * (r * r + b * b);
     double ux = state7[3] + Fx / mass;
     double uy = state7[4] + Fy / mass;
     double om = state7[6] + Tz / inertia;
@@ -426,7 +523,38 @@ void orc_newton_euler(const orc_params* p, const double state7[7], double Fx, do
     out7[6] = om;
 }
 
+void orc_newton_euler(const orc_params* p, const double state7[7], double Fx, double Fy,
+                      double Tz, double out7[7]) {
+    orc_newton_euler_ellipse(p, state7, state7[2], Fx, Fy, Tz, out7);
+}
+
 /* ------------------------------------------------------------- refilling */
+
+/* Refill direction (Sec. 2.5): e_c maximises n . e_c over the moving
+ * directions, n the outward normal at the newborn node, read as the
+ * gradient of the shape's implicit function there: parallel to (dx, dy) for
+ * a disk, to (b^2 u, a^2 v) in body coordinates for an ellipse.  The
+ * unnormalised vector ranks the same; ties go to the lowest index. */
+int32_t orc_refill_direction(double dx, double dy, double a, double b, double theta) {
+    double gx = dx, gy = dy;
+    if (a != b) {
+        double cth = cos(theta), sth = sin(theta), u, v;
+        to_body(dx, dy, cth, sth, &u, &v);
+        double gu = (b * b) * u, gv = (a * a) * v;
+        gx = gu * cth - gv * sth;
+        gy = gu * sth + gv * cth;
+    }
+    int c = 1;
+    double best = gx * EX[1] + gy * EY[1];
+    for (int d = 2; d < 9; ++d) {
+        double v = gx * EX[d] + gy * EY[d];
+        if (v > best) {
+            best = v;
+            c = d;
+        }
+    }
+    return c;
+}
 
 /* Refilling of one newborn node, Sec. 2.5.  K is the number of usable
  * extrapolation points x_new + k e_c, k = 1..K (the paper uses three; with
@@ -531,21 +659,36 @@ static void init_rest(orc_sim* s) {
     }
 }
 
-int orc_set_particles(orc_sim* s, int32_t n, const double* rows7) {
+/* rows: n rows of `cols` values; cols 7 = (x, y, r, ux, uy, theta, omega)
+ * (circles), cols 8 = (x, y, a, b, ux, uy, theta, omega) (ellipses). */
+static int set_particles_rows(orc_sim* s, int32_t n, const double* rows, int cols) {
     if (n < 0) return set_err(s, "negative particle count"), ORC_EINVAL;
     if (n > 0 && s->p.periodic_y) return set_err(s, "particles need walls in y"), ORC_EINVAL;
     free(s->P);
     s->P = NULL;
     s->np = n;
     if (n > 0) {
-        s->P = (double*)calloc((size_t)n * 10, sizeof(double));
+        s->P = (double*)calloc((size_t)n * PSTRIDE, sizeof(double));
         if (!s->P) return ORC_ENOMEM;
     }
     for (int q = 0; q < n; ++q) {
-        const double* in = rows7 + 7 * q;
-        double* P = s->P + 10 * q;
+        const double* row = rows + (size_t)cols * q;
+        double in[7], b;
+        if (cols == 7) {
+            for (int c = 0; c < 7; ++c) in[c] = row[c];
+            b = row[2];
+        } else {
+            in[0] = row[0];
+            in[1] = row[1];
+            in[2] = row[2];
+            b = row[3];
+            for (int c = 3; c < 7; ++c) in[c] = row[c + 1];
+        }
+        double* P = s->P + PSTRIDE * q;
         if (!(in[2] > 1.0) || !isfinite(in[0]) || !isfinite(in[1]))
             return set_err(s, "particle radius must be > 1 and centre finite"), ORC_EINVAL;
+        if (!(b > 1.0) || b > in[2])
+            return set_err(s, "semi-axis b must lie in (1, a]"), ORC_EINVAL;
         if (2.0 * in[2] + 4.0 > s->nx) return set_err(s, "particle wider than the lattice"), ORC_EINVAL;
         double x = in[0];
         if (s->p.periodic_x) {
@@ -556,11 +699,20 @@ int orc_set_particles(orc_sim* s, int32_t n, const double* rows7) {
         }
         P[0] = x;
         for (int c = 1; c < 7; ++c) P[c] = in[c];
+        P[10] = b;
     }
     compute_owner(s, s->owner);
     init_rest(s);
     s->steps = 0;
     return ORC_OK;
+}
+
+int orc_set_particles(orc_sim* s, int32_t n, const double* rows7) {
+    return set_particles_rows(s, n, rows7, 7);
+}
+
+int orc_set_particles_ellipse(orc_sim* s, int32_t n, const double* rows8) {
+    return set_particles_rows(s, n, rows8, 8);
 }
 
 int orc_set_equilibrium(orc_sim* s, const double* rho, const double* ux, const double* uy,
@@ -626,11 +778,11 @@ static long collect_links(const orc_sim* s, link_t* out) {
 }
 
 static double link_q_of(const orc_sim* s, long k, int d, int part) {
-    const double* P = s->P + 10 * part;
+    const double* P = s->P + PSTRIDE * part;
     int i = (int)(k % s->nx), j = (int)(k / s->nx);
     double dx = min_image((double)i - P[0], s->nx, s->p.periodic_x);
     double dy = min_image((double)j - P[1], s->ny, s->p.periodic_y);
-    return orc_link_q(dx, dy, P[2], d);
+    return orc_link_q_ellipse(dx, dy, P[2], P[10], P[5], d);
 }
 
 static int step_once(orc_sim* s) {
@@ -702,11 +854,11 @@ static int step_once(orc_sim* s) {
     for (long l = 0; l < nl; ++l) {
         long k = links[l].node;
         int i = links[l].dir, ib = OPP[i], part = links[l].part;
-        const double* P = s->P + 10 * part;
+        const double* P = s->P + PSTRIDE * part;
         int x = (int)(k % nx), y = (int)(k / nx);
         double dx = min_image((double)x - P[0], nx, p->periodic_x);
         double dy = min_image((double)y - P[1], ny, p->periodic_y);
-        double q = orc_link_q(dx, dy, P[2], i);
+        double q = orc_link_q_ellipse(dx, dy, P[2], P[10], P[5], i);
         double rx = dx + q * EX[i], ry = dy + q * EY[i]; /* x_w - X_c */
         double uwx = P[3] - P[6] * ry, uwy = P[4] + P[6] * rx;
         int have1 = fluid_at(s, s->owner, x - EX[i], y - EY[i]);
@@ -746,46 +898,49 @@ static int step_once(orc_sim* s) {
     }
 
     /* 8. particle motion: hydrodynamic force, repulsion (evaluated at t_n for
-     * all particles), net weight -(rho_p - rho_f) pi r^2 g y^. */
-    double* Pn = (double*)malloc(sizeof(double) * 10 * (s->np > 0 ? s->np : 1));
+     * all particles), net weight -(rho_p - rho_f) pi a b g y^ (pi r^2 for a
+     * disk). */
+    double* Pn = (double*)malloc(sizeof(double) * PSTRIDE * (s->np > 0 ? s->np : 1));
     if (!Pn) {
         free(Fsum);
         return ORC_ENOMEM;
     }
     int unstable = 0;
     for (int a = 0; a < s->np; ++a) {
-        const double* P = s->P + 10 * a;
+        const double* P = s->P + PSTRIDE * a;
         double Rx = 0.0, Ry = 0.0;
         if (p->repulsion) {
             for (int b = 0; b < s->np; ++b) {
                 if (b == a) continue;
-                const double* Q = s->P + 10 * b;
+                const double* Q = s->P + PSTRIDE * b;
                 double fr[2];
-                orc_repulsion_pair(p, P[0], P[1], P[2], Q[0], Q[1], Q[2], fr);
+                orc_repulsion_pair_ellipse(p, P[0], P[1], P[2], P[10], P[5], Q[0], Q[1], Q[2], Q[10],
+                                           Q[5], fr);
                 Rx += fr[0];
                 Ry += fr[1];
             }
             double fw[2];
-            orc_repulsion_walls(p, P[0], P[1], P[2], fw);
+            orc_repulsion_walls_ellipse(p, P[0], P[1], P[2], P[10], P[5], fw);
             Rx += fw[0];
             Ry += fw[1];
         }
-        double Fg = -(p->rho_ratio - 1.0) * p->rho0 * ORC_PI * P[2] * P[2] * p->gravity;
+        double Fg = -(p->rho_ratio - 1.0) * p->rho0 * ORC_PI * P[2] * P[10] * p->gravity;
         double Fx = Fsum[3 * a + 0] + Rx;
         double Fy = (Fsum[3 * a + 1] + Ry) + Fg;
         double st[7], out[7];
         for (int c = 0; c < 7; ++c) st[c] = P[c];
-        orc_newton_euler(p, st, Fx, Fy, Fsum[3 * a + 2], out);
+        orc_newton_euler_ellipse(p, st, P[10], Fx, Fy, Fsum[3 * a + 2], out);
         double ddx = min_image(out[0] - P[0], nx, p->periodic_x), ddy = out[1] - P[1];
         if (!(ddx * ddx + ddy * ddy <= 0.25)) unstable = 1;
-        double* O = Pn + 10 * a;
+        double* O = Pn + PSTRIDE * a;
         for (int c = 0; c < 7; ++c) O[c] = out[c];
         O[7] = Fsum[3 * a + 0];
         O[8] = Fsum[3 * a + 1];
         O[9] = Fsum[3 * a + 2];
+        O[10] = P[10];
     }
     free(Fsum);
-    if (s->np > 0) memcpy(s->P, Pn, sizeof(double) * 10 * s->np);
+    if (s->np > 0) memcpy(s->P, Pn, sizeof(double) * PSTRIDE * s->np);
     free(Pn);
 
     /* 9. owner at t_n+1; newborn = solid at t_n, fluid at t_n+1. */
@@ -796,22 +951,11 @@ static int step_once(orc_sim* s) {
     for (long k = 0; k < N; ++k) {
         int32_t o = s->owner[k];
         if (o < 0 || s->owner_new[k] >= 0) continue;
-        const double* P = s->P + 10 * o;
+        const double* P = s->P + PSTRIDE * o;
         int x = (int)(k % nx), y = (int)(k / nx);
         double dx = min_image((double)x - P[0], nx, p->periodic_x);
         double dy = min_image((double)y - P[1], ny, p->periodic_y);
-        /* e_c maximises n . e_c over the moving directions; n is parallel to
-         * (dx, dy), so the unnormalised offset ranks the same; ties go to the
-         * lowest direction index. */
-        int c = 1;
-        double best = dx * EX[1] + dy * EY[1];
-        for (int d = 2; d < 9; ++d) {
-            double v = dx * EX[d] + dy * EY[d];
-            if (v > best) {
-                best = v;
-                c = d;
-            }
-        }
+        int c = orc_refill_direction(dx, dy, P[2], P[10], P[5]);
         int K = 0;
         double fs[3][9];
         for (int m = 1; m <= 3; ++m) {
@@ -881,7 +1025,8 @@ int orc_read_populations(const orc_sim* s, double* f, double* g) {
 
 int orc_read_particles(const orc_sim* s, double* rows10, int32_t* n) {
     if (n) *n = s->np;
-    if (rows10 && s->np > 0) memcpy(rows10, s->P, sizeof(double) * 10 * s->np);
+    if (rows10)
+        for (int q = 0; q < s->np; ++q) memcpy(rows10 + 10 * q, s->P + PSTRIDE * q, sizeof(double) * 10);
     return ORC_OK;
 }
 

@@ -66,6 +66,10 @@ const char* orc_last_error(const orc_sim* s);
 /* Replace the particles and re-initialise the run: fluid at rest at rho0 and
  * T_fluid0 (equilibrium), step counter 0.  n may be 0. */
 int  orc_set_particles(orc_sim* s, int32_t n, const double* rows7);
+/* The same for ellipses (Sec. 2.6.2): rows of (x, y, a, b, ux, uy, theta,
+ * omega), a the semi-axis along the body axis at angle theta from +x, b the
+ * semi-axis across it, 1 < b <= a (b == a is a circle). */
+int  orc_set_particles_ellipse(orc_sim* s, int32_t n, const double* rows8);
 /* Re-initialise fluid nodes to f^eq(rho, u), g^eq(T, u) from the given fields
  * (nx*ny each, row-major); particles are kept; step counter 0. */
 int  orc_set_equilibrium(orc_sim* s, const double* rho, const double* ux,
@@ -92,6 +96,9 @@ int  orc_nusselt(const orc_sim* s, double* nu_bottom, double* nu_top);
 void orc_collide_node(const orc_sim* s, const double f[9], const double g[5],
                       double fo[9], double go[5], double macro[4]);
 double orc_link_q(double dx, double dy, double r, int32_t i);
+double orc_link_q_ellipse(double dx, double dy, double a, double b, double theta, int32_t i);
+int32_t orc_inside_shape(double dx, double dy, double a, double b, double theta);
+int32_t orc_refill_direction(double dx, double dy, double a, double b, double theta);
 double orc_bouzidi(double q, int32_t i, double fi_xf, double fi_xf1, double fi_xf2,
                    double fib_xf, double fib_xf1, int32_t have1, int32_t have2,
                    double rho0, double uwx, double uwy);
@@ -100,8 +107,15 @@ double orc_thermal_link(double q, int32_t i, double gi_xf, double gi_xf1, double
 void orc_repulsion_pair(const orc_params* p, double xp, double yp, double rp,
                         double xq, double yq, double rq, double out[2]);
 void orc_repulsion_walls(const orc_params* p, double xp, double yp, double rp, double out[2]);
+void orc_repulsion_pair_ellipse(const orc_params* p, double xp, double yp, double ap, double bp,
+                                double thp, double xq, double yq, double aq, double bq,
+                                double thq, double out[2]);
+void orc_repulsion_walls_ellipse(const orc_params* p, double xp, double yp, double a, double b,
+                                 double theta, double out[2]);
 void orc_newton_euler(const orc_params* p, const double state7[7], double Fx, double Fy,
                       double Tz, double out7[7]);
+void orc_newton_euler_ellipse(const orc_params* p, const double state7[7], double b, double Fx,
+                              double Fy, double Tz, double out7[7]);
 void orc_refill_node(const orc_sim* s, int32_t K, const double* f1, const double* f2,
                      const double* f3, double uwx, double uwy, double fo[9], double go[5]);
 void orc_rates(const orc_sim* s, double s9[9], double s5[5], double w5[5]);
