@@ -78,6 +78,13 @@ def measured_traffic(workload, storage):
     return float(t.group(1))
 
 
+def place(run, rows):
+    """Particles of a workload into a run (library or oracle): rows of 7
+    values are circles, rows of 8 ellipses."""
+    rows = np.asarray(rows)
+    (run.set_particles_ellipse if rows.shape[1] == 8 else run.set_particles)(rows)
+
+
 def cpu_baseline(workload, steps):
     """The CPU oracle on `steps` steps of the same workload (one thread)."""
     import lbm_inputs
@@ -88,7 +95,7 @@ def cpu_baseline(workload, steps):
     okw = {k: v for k, v in kw.items() if k not in ("storage", "max_particles", "max_diameter")}
     rows = lbm_inputs.workload_particles(w)
     orc = Oracle(**okw)
-    orc.set_particles(rows)
+    place(orc, rows)
     orc.step(1)  # first touch of the oracle's arrays, not timed
     t0 = time.perf_counter()
     orc.step(steps)
@@ -111,8 +118,11 @@ def describe(name, storage):
                 f"beta={lat['beta']:g} (Pr={lat['nu'] / lat['alpha']:g})")
     else:
         phys = f"Pr={w['Pr']}, Ra={w['Ra']:g}"
-    place = (f"{w['rows']}x{w['cols']} grid" if w.get("layout") == "grid" else "random")
-    return (f"{name}: {w['nx']}x{w['ny']} {geom}, {w['n']} hot particles d={w['d']:g} ({place}), "
+    layout = w.get("layout")
+    where = (f"{w['rows']}x{w['cols']} grid" if layout == "grid" else
+             "ring cluster" if layout == "rings" else "random")
+    shape = f"ellipses {w['d']:g}x{w['d_minor']:g}" if "d_minor" in w else f"d={w['d']:g}"
+    return (f"{name}: {w['nx']}x{w['ny']} {geom}, {w['n']} hot particles {shape} ({where}), "
             f"rho_p/rho_f={w['rho_ratio']}, {phys}, {storage} storage, links rebuilt every step")
 
 
@@ -126,7 +136,7 @@ def paper_workload(steps, warmup, storage):
     name = "e4_cavity"
     w = params.WORKLOADS[name]
     sim = lbm.Sim(lbm.lbm_params_default(**params.workload_params(name, lbm.STORE[storage])))
-    sim.set_particles(lbm_inputs.workload_particles(w))
+    place(sim, lbm_inputs.workload_particles(w))
     sim.step(warmup)
     sim.sync()
     torch.cuda.synchronize()
@@ -222,7 +232,7 @@ def main():
     log(f"[bench] {args.workload} {nx}x{ny} n={w['n']} d={w['d']} storage={args.storage}")
     import lbm_inputs
     sim = lbm.Sim(p)
-    sim.set_particles(lbm_inputs.workload_particles(w))
+    place(sim, lbm_inputs.workload_particles(w))
     if args.addressing != "indirect":
         sim.set_addressing(args.addressing)
     sim.step(args.warmup)
@@ -290,7 +300,7 @@ def main():
     }
     sim.close()
     del sim
-    if args.workload != "e4_cavity" and not args.no_paper_workload:
+    if args.workload == "paper_scale" and not args.no_paper_workload:
         out["paper_workload"] = paper_workload(args.paper_steps, 20, args.storage)
     if not args.no_serve:
         out["serving"] = serving(args.serve_requests, args.serve_budget_gib, args.serve_chunk)

@@ -179,6 +179,15 @@ int lbm_seed_particles(lbm_handle h, int32_t n, double diameter, double min_gap,
  * cavity, -1/2 <= x <= nx - 1/2 (a periodic x is wrapped into [0, nx)). */
 int lbm_set_particles(lbm_handle h, int32_t n, const double* rows7);
 
+/* The same for elliptical particles (Sec. 2.6.2): n rows of (x, y, a, b,
+ * ux, uy, theta, omega), a the semi-axis along the body axis at angle theta
+ * from +x, b the semi-axis across it, 1 < b <= a <= max_diameter/2 (b == a
+ * is a circle).  The solid test, link fractions, refill normal, repulsion
+ * gaps (along the centre line for pairs, to the supporting line for walls),
+ * mass pi a b rho_p and inertia M (a^2 + b^2)/4 follow the ellipse; theta
+ * evolves with omega.  lbm_read_particles reports a in the r column. */
+int lbm_set_particles_ellipse(lbm_handle h, int32_t n, const double* rows8);
+
 /* Re-initialise fluid nodes to the equilibria f^eq(rho, u) and g^eq(T, u)
  * of the given fields (host arrays of nx*ny); particles are kept; step
  * counter 0. */

@@ -126,12 +126,31 @@ def grid_particles(nx, ny, rows, cols, diameter, spacing):
     return out
 
 
+def ring_cluster_ellipses(centre, counts, ring_spacing, a, b, theta=0.0):
+    """Ellipses at rest in a circular cluster: one at `centre`, then ring k
+    (k = 1, 2, ...) of counts[k - 1] particles at radius k * ring_spacing,
+    evenly spaced in angle starting from +x, all with semi-axes (a, b) and
+    body angle `theta`.  Rows of (x, y, a, b, ux, uy, theta, omega)."""
+    cx, cy = centre
+    rows = [[cx, cy, a, b, 0.0, 0.0, theta, 0.0]]
+    for k, m in enumerate(counts, start=1):
+        R = k * ring_spacing
+        for j in range(m):
+            phi = 2.0 * math.pi * j / m
+            rows.append([cx + R * math.cos(phi), cy + R * math.sin(phi), a, b, 0.0, 0.0, theta, 0.0])
+    return np.array(rows)
+
+
 def workload_particles(w):
     """Initial particle rows of a workload description: `layout` "grid"
-    (rows x cols at `spacing`) or, by default, random sequential addition
-    with its gap and seed."""
+    (rows x cols at `spacing`), "rings" (an elliptical-particle cluster:
+    rows of 8 values) or, by default, random sequential addition with its
+    gap and seed."""
     if w.get("layout") == "grid":
         return grid_particles(w["nx"], w["ny"], w["rows"], w["cols"], w["d"], w["spacing"])
+    if w.get("layout") == "rings":
+        return ring_cluster_ellipses(w["centre"], w["rings"], w["ring_spacing"], 0.5 * w["d"],
+                                     0.5 * w["d_minor"], w.get("theta", 0.0))
     return rsa_particles(w["nx"], w["ny"], w["n"], w["d"], w["gap"], w["seed"])
 
 

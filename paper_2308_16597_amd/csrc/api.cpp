@@ -543,17 +543,33 @@ int lbm_seed_particles(lbm_handle h, int32_t n, double diameter, double min_gap,
     return lbm_set_particles(h, n, rows.data());
 }
 
-int lbm_set_particles(lbm_handle h, int32_t n, const double* rows7) {
+namespace {
+
+// rows of `cols` values: 7 = (x, y, r, ux, uy, theta, omega) for circles,
+// 8 = (x, y, a, b, ux, uy, theta, omega) for ellipses.
+int set_particles_rows(lbm_handle h, int32_t n, const double* rows, int cols) {
     if (!h) return LBM_EINVAL;
     if (n < 0 || n > h->p.max_particles) return fail(h, LBM_EINVAL, "particle count %d outside [0, %d]", n, h->p.max_particles);
-    if (n > 0 && !rows7) return fail(h, LBM_EINVAL, "null particle rows");
+    if (n > 0 && !rows) return fail(h, LBM_EINVAL, "null particle rows");
     std::vector<PState> P((size_t)n);
     const double rmax = 0.5 * h->p.max_diameter;
     for (int i = 0; i < n; ++i) {
-        const double* in = rows7 + 7 * (size_t)i;
-        for (int c = 0; c < 7; ++c)
-            if (!std::isfinite(in[c])) return fail(h, LBM_EINVAL, "particle %d: non-finite value", i);
+        const double* row = rows + (size_t)cols * i;
+        for (int c = 0; c < cols; ++c)
+            if (!std::isfinite(row[c])) return fail(h, LBM_EINVAL, "particle %d: non-finite value", i);
+        double in[7];
+        double b = row[2];
+        if (cols == 7) {
+            for (int c = 0; c < 7; ++c) in[c] = row[c];
+        } else {
+            in[0] = row[0];
+            in[1] = row[1];
+            in[2] = row[2];
+            b = row[3];
+            for (int c = 3; c < 7; ++c) in[c] = row[c + 1];
+        }
         if (!(in[2] > 1.0) || in[2] > rmax) return fail(h, LBM_EINVAL, "particle %d: radius %g outside (1, %g]", i, in[2], rmax);
+        if (!(b > 1.0) || b > in[2]) return fail(h, LBM_EINVAL, "particle %d: semi-axis b = %g outside (1, a]", i, b);
         if (in[1] < -0.5 || in[1] > h->p.ny - 0.5) return fail(h, LBM_EINVAL, "particle %d: centre outside the channel", i);
         double x = in[0];
         if (h->p.periodic_x) {
@@ -562,7 +578,7 @@ int lbm_set_particles(lbm_handle h, int32_t n, const double* rows7) {
         } else if (x < -0.5 || x > h->p.nx - 0.5) {
             return fail(h, LBM_EINVAL, "particle %d: centre outside the cavity", i);
         }
-        P[i] = PState{x, in[1], in[2], in[3], in[4], in[5], in[6], 0.0};
+        P[i] = PState{x, in[1], in[2], in[3], in[4], in[5], in[6], b};
     }
     DevState& d = h->d;
     hipStream_t st = h->stream;
@@ -596,6 +612,14 @@ int lbm_set_particles(lbm_handle h, int32_t n, const double* rows7) {
     HIPCHK(h, hipStreamSynchronize(st));
     h->steps = 0;
     return LBM_OK;
+}
+
+}  // namespace
+
+int lbm_set_particles(lbm_handle h, int32_t n, const double* rows7) { return set_particles_rows(h, n, rows7, 7); }
+
+int lbm_set_particles_ellipse(lbm_handle h, int32_t n, const double* rows8) {
+    return set_particles_rows(h, n, rows8, 8);
 }
 
 int lbm_set_addressing(lbm_handle h, int32_t mode) {

@@ -28,7 +28,7 @@ __device__ __forceinline__ double min_image_x(double d, const LP& lp) {
 }
 
 struct PState {   // one particle, FP64
-    double x, y, r, ux, uy, th, om, pad;
+    double x, y, r, ux, uy, th, om, b;   // r: semi-axis a along the body axis at th; b across it
 };
 
 // Whole-record global-memory accesses of the small structs kept in device
@@ -41,7 +41,7 @@ __device__ __forceinline__ PState ld_state(const PState* p) {
 }
 __device__ __forceinline__ void st_state(PState* p, const PState& v) {
     PT_GLOBAL double* q = (PT_GLOBAL double*)p;
-    q[0] = v.x; q[1] = v.y; q[2] = v.r; q[3] = v.ux; q[4] = v.uy; q[5] = v.th; q[6] = v.om; q[7] = v.pad;
+    q[0] = v.x; q[1] = v.y; q[2] = v.r; q[3] = v.ux; q[4] = v.uy; q[5] = v.th; q[6] = v.om; q[7] = v.b;
 }
 __device__ __forceinline__ uint2 ld_u2(const uint2* p) {
     const PT_GLOBAL unsigned* q = (const PT_GLOBAL unsigned*)p;
@@ -106,6 +106,54 @@ __device__ __forceinline__ int col_of(int x, const LP& lp) {
     return (x >= 0 && x < lp.nx) ? x : -1;
 }
 
+// ---------------------------------------------------------------- shapes ----
+// Particles are circles or ellipses (Sec. 2.6.2): semi-axis a = r along the
+// body axis at angle th from +x, b across it; b == a is a circle and takes
+// the plain circle formulas.  An ellipse is handled in body coordinates
+// (u, v) = (dx c + dy s, dy c - dx s), c = cos th, s = sin th.
+struct Shape {
+    double a, b, c, s;
+    bool circle;
+};
+__device__ __forceinline__ Shape shape_of(const PState& P) {
+    Shape sh;
+    sh.a = P.r;
+    sh.b = P.b;
+    sh.circle = P.b == P.r;
+    sh.c = 1.0;
+    sh.s = 0.0;
+    if (!sh.circle) {
+        sh.c = cos(P.th);
+        sh.s = sin(P.th);
+    }
+    return sh;
+}
+// Solid test: dx^2 + dy^2 <= r^2, or b^2 u^2 + a^2 v^2 <= a^2 b^2.
+__device__ __forceinline__ bool inside_shape(const Shape& sh, double dx, double dy) {
+    if (sh.circle) return dx * dx + dy * dy <= sh.a * sh.a;
+    const double u = dx * sh.c + dy * sh.s, v = dy * sh.c - dx * sh.s;
+    return (u * u) * (sh.b * sh.b) + (v * v) * (sh.a * sh.a) <= (sh.a * sh.a) * (sh.b * sh.b);
+}
+// Distance from the centre to the boundary along the unit direction (nx, ny).
+__device__ __forceinline__ double radial_extent(const Shape& sh, double nx, double ny) {
+    if (sh.circle) return sh.a;
+    const double nu = nx * sh.c + ny * sh.s, nv = ny * sh.c - nx * sh.s;
+    return (sh.a * sh.b) / sqrt((sh.b * sh.b) * (nu * nu) + (sh.a * sh.a) * (nv * nv));
+}
+// Half-extents along x and y (distance from the centre to the supporting
+// lines normal to the axes).
+__device__ __forceinline__ void half_extents(const Shape& sh, double& hx, double& hy) {
+    if (sh.circle) {
+        hx = sh.a;
+        hy = sh.a;
+        return;
+    }
+    hx = sqrt((sh.a * sh.a) * (sh.c * sh.c) + (sh.b * sh.b) * (sh.s * sh.s));
+    hy = sqrt((sh.a * sh.a) * (sh.s * sh.s) + (sh.b * sh.b) * (sh.c * sh.c));
+}
+// Radius of the disk of equal area (the repulsion force scale).
+__device__ __forceinline__ double area_radius(const Shape& sh) { return sh.circle ? sh.a : sqrt(sh.a * sh.b); }
+
 // Link fraction q of Sec. 2.3 for the circle: the nearer root of
 // |d + t e_i|^2 = r^2, clamped to [0, 1].
 __device__ __forceinline__ double link_q(double dx, double dy, double r, int i) {
@@ -116,6 +164,25 @@ __device__ __forceinline__ double link_q(double dx, double dy, double r, int i) 
     double disc = b * b - a * c;
     if (disc < 0.0) disc = 0.0;
     double q = (-b - sqrt(disc)) / a;
+    if (q < 0.0) q = 0.0;
+    if (q > 1.0) q = 1.0;
+    return q;
+}
+
+// The same for either shape: for an ellipse the smaller root of
+// b^2 (u + t e_u)^2 + a^2 (v + t e_v)^2 = a^2 b^2 in body coordinates.
+__device__ __forceinline__ double link_q_shape(const Shape& sh, double dx, double dy, int i) {
+    if (sh.circle) return link_q(dx, dy, sh.a, i);
+    const double ex = EXd(i), ey = EYd(i);
+    const double u = dx * sh.c + dy * sh.s, v = dy * sh.c - dx * sh.s;
+    const double eu = ex * sh.c + ey * sh.s, ev = ey * sh.c - ex * sh.s;
+    const double a2 = sh.a * sh.a, b2 = sh.b * sh.b;
+    const double A = b2 * (eu * eu) + a2 * (ev * ev);
+    const double B = b2 * (u * eu) + a2 * (v * ev);
+    const double C = (b2 * (u * u) + a2 * (v * v)) - a2 * b2;
+    double disc = B * B - A * C;
+    if (disc < 0.0) disc = 0.0;
+    double q = (-B - sqrt(disc)) / A;
     if (q < 0.0) q = 0.0;
     if (q > 1.0) q = 1.0;
     return q;

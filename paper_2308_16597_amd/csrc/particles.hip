@@ -198,8 +198,8 @@ constexpr int PASS_BLOCK = 256;
 
 // One link: fluid node (x, y), direction i towards particle P.
 template <int MODE>
-__device__ __forceinline__ void link_pass_link(const RunStep& rs, const PState& P, int x, int y, int i,
-                                               double& hx, double& hy, double& hz) {
+__device__ __forceinline__ void link_pass_link(const RunStep& rs, const PState& P, const Shape& sh, int x, int y,
+                                               int i, double& hx, double& hy, double& hz) {
     using S = Store<MODE>;
     const LP& lp = rs.lp;
     // population arrays picked straight from the run's pointer table (a
@@ -229,7 +229,7 @@ __device__ __forceinline__ void link_pass_link(const RunStep& rs, const PState& 
     const bool have2 = have1 && in2 && o2 == -1;
     const double dx = min_image_x((double)x - P.x, lp);
     const double dy = (double)y - P.y;
-    const double q = link_q(dx, dy, P.r, i);
+    const double q = link_q_shape(sh, dx, dy, i);
     const double rx = dx + q * ex, ry = dy + q * ey;   // x_w - X_c
     const double uwx = P.ux - P.om * ry, uwy = P.uy + P.om * rx;
     const double w9i = i <= 4 ? 1.0 / 9.0 : 1.0 / 36.0;
@@ -258,10 +258,11 @@ __device__ __forceinline__ void link_pass_body(const RunStep& rs, unsigned bid) 
     if (p >= rs.lp.np) return;   // the whole block
     const int2 sg = ld_i2(rs.seg + p);
     const PState P = ld_state(rs.Pc + p);
+    const Shape sh = shape_of(P);
     double hx = 0.0, hy = 0.0, hz = 0.0;
     for (int t = (int)threadIdx.x; t < sg.y; t += PASS_BLOCK) {
         const uint2 L = ld_u2(rs.links + sg.x + t);
-        link_pass_link<MODE>(rs, P, (int)(L.x & 0xffffu), (int)(L.x >> 16), (int)(L.y & 15u), hx, hy, hz);
+        link_pass_link<MODE>(rs, P, sh, (int)(L.x & 0xffffu), (int)(L.x >> 16), (int)(L.y & 15u), hx, hy, hz);
     }
     for (int off = 32; off > 0; off >>= 1) {
         hx += __shfl_xor(hx, off);
@@ -315,7 +316,7 @@ __device__ __forceinline__ void link_pass_direct_body(const RunStep& rs, unsigne
         if (own[d] < 0) continue;
         const PState P = ld_state(rs.Pc + own[d]);
         double hx = 0.0, hy = 0.0, hz = 0.0;
-        link_pass_link<MODE>(rs, P, x, y, d, hx, hy, hz);
+        link_pass_link<MODE>(rs, P, shape_of(P), x, y, d, hx, hy, hz);
         double* Fa = rs.Fa + 4 * (size_t)own[d];
         atomicAdd(Fa + 0, hx);
         atomicAdd(Fa + 1, hy);
@@ -323,19 +324,26 @@ __device__ __forceinline__ void link_pass_direct_body(const RunStep& rs, unsigne
     }
 }
 
-// Spring repulsion of Eq. (15) on particle (xp, yp, rp) from (xq, yq, rq):
-// surface gap along the centre line, force scale pi rp rq (rho_p - rho_f) g.
-__device__ __forceinline__ void repulsion_pair(const LP& lp, double xp, double yp, double rp, double xq,
-                                               double yq, double rq, double& fx, double& fy) {
-    const double dx = min_image_x(xp - xq, lp);
-    const double dy = yp - yq;
+// Spring repulsion of Eq. (15) on particle P from Q: surface gap along the
+// centre line (the centre distance minus each shape's extent along it),
+// force scale pi r_p r_q (rho_p - rho_f) g with equal-area radii.  Returns
+// whether the gap is within the range s (else no force).
+__device__ __forceinline__ bool repulsion_pair(const LP& lp, const PState& P, const Shape& sp, const PState& Q,
+                                               double& fx, double& fy) {
+    const double dx = min_image_x(P.x - Q.x, lp);
+    const double dy = P.y - Q.y;
     const double dist = sqrt(dx * dx + dy * dy);
-    const double gap = dist - rp - rq;
-    const double C = kPi * (rp * rq) * (lp.rho_ratio - 1.0) * lp.rho0 * lp.gravity;
+    const Shape sq = shape_of(Q);
+    const double ep = radial_extent(sp, dx / dist, dy / dist);
+    const double eq = radial_extent(sq, dx / dist, dy / dist);
+    const double gap = dist - ep - eq;
+    if (gap > lp.rep_range) return false;
+    const double C = kPi * (area_radius(sp) * area_radius(sq)) * (lp.rho_ratio - 1.0) * lp.rho0 * lp.gravity;
     const double t = (gap - lp.rep_range) / lp.rep_range;
     const double mag = C / lp.rep_eps * (t * t);
     fx = mag * (dx / dist);
     fy = mag * (dy / dist);
+    return true;
 }
 
 // Uniform cell grid for the neighbour search: cells at least 2 r_max + s
@@ -391,6 +399,7 @@ __device__ __forceinline__ void particles_body(const RunStep& rs, unsigned bid) 
             }
     }
     const PState P = ld_state(Pc + p);
+    const Shape sh = shape_of(P);
     PT_GLOBAL double* Fa = gl(rs.Fa);
     const double hx = Fa[4 * p + 0], hy = Fa[4 * p + 1], hz = Fa[4 * p + 2];   // from the link pass
     double Rx = 0.0, Ry = 0.0;
@@ -417,15 +426,9 @@ __device__ __forceinline__ void particles_body(const RunStep& rs, unsigned bid) 
                 const int c = yy * lp.ncx + xx;
                 if ((unsigned)sl < min(cnt_cur[c], (unsigned)BINCAP)) {
                     const int qq = (int)bins_cur[(size_t)c * BINCAP + sl];
-                    if (qq != p) {
-                        const PState Q = ld_state(Pc + qq);
-                        const double dx = min_image_x(P.x - Q.x, lp);
-                        const double dy = P.y - Q.y;
-                        if (sqrt(dx * dx + dy * dy) - P.r - Q.r <= lp.rep_range) {
-                            near = true;
-                            q = qq;
-                            repulsion_pair(lp, P.x, P.y, P.r, Q.x, Q.y, Q.r, fx, fy);
-                        }
+                    if (qq != p && repulsion_pair(lp, P, sh, ld_state(Pc + qq), fx, fy)) {
+                        near = true;
+                        q = qq;
                     }
                 }
             }
@@ -445,27 +448,30 @@ __device__ __forceinline__ void particles_body(const RunStep& rs, unsigned bid) 
         }
     }
     if (lp.repulsion) {   // the flat walls: Eq. (15) with the wall plane as the partner surface
-        const double C = kPi * (P.r * P.r) * (lp.rho_ratio - 1.0) * lp.rho0 * lp.gravity;
+        const double R = area_radius(sh);
+        const double C = kPi * (R * R) * (lp.rho_ratio - 1.0) * lp.rho0 * lp.gravity;
+        double ex, ey;   // the shape's half-extents normal to the walls
+        half_extents(sh, ex, ey);
         double wx = 0.0, wy = 0.0;
         if (!lp.periodic_x) {
-            const double gap_l = (P.x + 0.5) - P.r;
+            const double gap_l = (P.x + 0.5) - ex;
             if (gap_l <= lp.rep_range) {
                 const double t = (gap_l - lp.rep_range) / lp.rep_range;
                 wx += C / lp.rep_eps * (t * t);
             }
-            const double gap_r = ((lp.nx - 0.5) - P.x) - P.r;
+            const double gap_r = ((lp.nx - 0.5) - P.x) - ex;
             if (gap_r <= lp.rep_range) {
                 const double t = (gap_r - lp.rep_range) / lp.rep_range;
                 wx -= C / lp.rep_eps * (t * t);
             }
         }
         if (!lp.periodic_y) {
-            const double gb = (P.y + 0.5) - P.r;
+            const double gb = (P.y + 0.5) - ey;
             if (gb <= lp.rep_range) {
                 const double t = (gb - lp.rep_range) / lp.rep_range;
                 wy += C / lp.rep_eps * (t * t);
             }
-            const double gt = ((lp.ny - 0.5) - P.y) - P.r;
+            const double gt = ((lp.ny - 0.5) - P.y) - ey;
             if (gt <= lp.rep_range) {
                 const double t = (gt - lp.rep_range) / lp.rep_range;
                 wy -= C / lp.rep_eps * (t * t);
@@ -484,13 +490,14 @@ __device__ __forceinline__ void particles_body(const RunStep& rs, unsigned bid) 
         Fa[4 * p + 1] = 0.0;
         Fa[4 * p + 2] = 0.0;
     }
-    const double Fg = -(lp.rho_ratio - 1.0) * lp.rho0 * kPi * P.r * P.r * lp.gravity;
+    const double Fg = -(lp.rho_ratio - 1.0) * lp.rho0 * kPi * P.r * P.b * lp.gravity;   // pi a b
     const double Fx = hx + Rx;
     const double Fy = (hy + Ry) + Fg;
     const double Tz = hz;
-    // Newton-Euler (Sec. 2.2): explicit velocities, trapezoidal positions.
-    const double mass = lp.rho_ratio * lp.rho0 * kPi * P.r * P.r;
-    const double inertia = 0.5 * mass * P.r * P.r;
+    // Newton-Euler (Sec. 2.2): explicit velocities, trapezoidal positions;
+    // M = rho_p pi a b, I = M r^2 / 2 (disk) or M (a^2 + b^2) / 4 (ellipse).
+    const double mass = lp.rho_ratio * lp.rho0 * kPi * P.r * P.b;
+    const double inertia = sh.circle ? 0.5 * mass * P.r * P.r : 0.25 * mass * (P.r * P.r + P.b * P.b);
     PState N = P;
     N.ux = P.ux + Fx / mass;
     N.uy = P.uy + Fy / mass;
@@ -551,7 +558,7 @@ __device__ __forceinline__ void mask_body(const RunStep& rs, unsigned bid) {
     }
     const int bw = xb - xa, bh = yb - ya;
     if (bw > lp.nwin + 2 || bh > lp.nwin + 2) return;
-    const double r2 = P.r * P.r, q2 = Q.r * Q.r;
+    const Shape sp = shape_of(P), sq = shape_of(Q);
     unsigned nc = 0;
     const unsigned ccap = (unsigned)(4 * lp.nwin);
     for (int base = 0; base < bw * bh; base += 64) {
@@ -566,12 +573,12 @@ __device__ __forceinline__ void mask_body(const RunStep& rs, unsigned bid) {
                 const double dx = min_image_x((double)xx - P.x, lp);
                 const double dy = (double)yy - P.y;
                 const size_t k = (size_t)yy * lp.pitch + xx;
-                if (dx * dx + dy * dy <= r2) {
+                if (inside_shape(sp, dx, dy)) {
                     atomicMin((unsigned*)&O[k], (unsigned)p);
                 } else if (with_prev) {
                     const double qx = min_image_x((double)xx - Q.x, lp);
                     const double qy = (double)yy - Q.y;
-                    nb = qx * qx + qy * qy <= q2;
+                    nb = inside_shape(sq, qx, qy);
                     code = (unsigned)xx | ((unsigned)yy << 16);
                 }
             }
@@ -601,17 +608,26 @@ __device__ __forceinline__ void mask_body(const RunStep& rs, unsigned bid) {
 // node is skipped unless p owned it at t_n and it is fluid at t_n+1.
 template <int MODE>
 __device__ void refill_node(const Pops<ST<MODE>>& A, const Pops<ST<MODE>>& B, const PT_GLOBAL int32_t* Ocur,
-                            const PT_GLOBAL int32_t* Onext, const PState& P, int p, int x, int y,
-                            const LP& lp) {
+                            const PT_GLOBAL int32_t* Onext, const PState& P, const Shape& sh, int p, int x,
+                            int y, const LP& lp) {
     using S = Store<MODE>;
     using R = typename S::R;
     const size_t k0 = (size_t)y * lp.pitch + x;
     const double dx = min_image_x((double)x - P.x, lp);
     const double dy = (double)y - P.y;
+    // n along the gradient of the shape's implicit function: (dx, dy) for a
+    // disk, (b^2 u, a^2 v) in body coordinates for an ellipse
+    double gx = dx, gy = dy;
+    if (!sh.circle) {
+        const double u = dx * sh.c + dy * sh.s, v = dy * sh.c - dx * sh.s;
+        const double gu = (sh.b * sh.b) * u, gv = (sh.a * sh.a) * v;
+        gx = gu * sh.c - gv * sh.s;
+        gy = gu * sh.s + gv * sh.c;
+    }
     int c = 1;
-    double best = dx * EXd(1) + dy * EYd(1);
+    double best = gx * EXd(1) + gy * EYd(1);
     for (int d = 2; d < 9; ++d) {
-        const double v = dx * EXd(d) + dy * EYd(d);
+        const double v = gx * EXd(d) + gy * EYd(d);
         if (v > best) {
             best = v;
             c = d;
@@ -679,9 +695,11 @@ __device__ __forceinline__ void refill_body(const RunStep& rs, unsigned bid) {
     if (n == 0) return;
     const Pops<ST<MODE>> A = pops_of<MODE>(rs.A), B = pops_of<MODE>(rs.B);
     const PState P1 = ld_state(rs.Pn + p);
+    const Shape sh = shape_of(P1);
     for (unsigned i = lane; i < n; i += 64) {
         const unsigned code = gl(rs.cand)[(size_t)p * ccap + i];
-        refill_node<MODE>(A, B, gl(rs.Ocur), gl(rs.Onext), P1, p, (int)(code & 0xffffu), (int)(code >> 16), lp);
+        refill_node<MODE>(A, B, gl(rs.Ocur), gl(rs.Onext), P1, sh, p, (int)(code & 0xffffu), (int)(code >> 16),
+                          lp);
     }
 }
 
@@ -746,7 +764,7 @@ __global__ void k_link_q(const PState* __restrict__ Pc, const uint2* __restrict_
     node[l] = y * lp.nx + x;
     dir[l] = i;
     part[l] = p;
-    qo[l] = link_q(dx, dy, P.r, i);
+    qo[l] = link_q_shape(shape_of(P), dx, dy, i);
 }
 
 // -------------------------------------------------------------- launchers ----

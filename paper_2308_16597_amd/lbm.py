@@ -71,6 +71,7 @@ def _load():
     L.lbm_rsa_seed.argtypes = [_i, _i, _i, _d, _d, ctypes.c_uint64, vp]
     L.lbm_seed_particles.argtypes = [vp, _i, _d, _d, ctypes.c_uint64]
     L.lbm_set_particles.argtypes = [vp, _i, vp]
+    L.lbm_set_particles_ellipse.argtypes = [vp, _i, vp]
     L.lbm_set_equilibrium.argtypes = [vp, vp, vp, vp, vp]
     L.lbm_step.argtypes = [vp, _i]
     L.lbm_set_addressing.argtypes = [vp, _i]
@@ -163,6 +164,11 @@ def lbm_seed_particles(h, n, diameter, min_gap, seed):
 def lbm_set_particles(h, rows7):
     rows7 = np.ascontiguousarray(rows7, dtype=np.float64).reshape(-1, 7)
     _check(_lib.lbm_set_particles(h, rows7.shape[0], _ptr(rows7)), h)
+
+
+def lbm_set_particles_ellipse(h, rows8):
+    rows8 = np.ascontiguousarray(rows8, dtype=np.float64).reshape(-1, 8)
+    _check(_lib.lbm_set_particles_ellipse(h, rows8.shape[0], _ptr(rows8)), h)
 
 
 def lbm_set_equilibrium(h, rho, ux, uy, T):
@@ -295,6 +301,9 @@ class Sim:
 
     def set_particles(self, rows7):
         lbm_set_particles(self._h, rows7)
+
+    def set_particles_ellipse(self, rows8):
+        lbm_set_particles_ellipse(self._h, rows8)
 
     def set_equilibrium(self, rho, ux, uy, T):
         lbm_set_equilibrium(self._h, rho, ux, uy, T)

@@ -73,6 +73,15 @@ WORKLOADS = {
     "e4_cavity": dict(nx=4000, ny=4000, n=4800, d=40.0, layout="grid", rows=60, cols=80,
                       spacing=50.0, rho_ratio=1.1, closed=True, steps=6000,
                       lattice=dict(nu=0.01, alpha=0.002, gravity=7.84e-6, beta=1.20e-2)),
+    # The paper's elliptical-particle case (Sec. 2.6.2 and its parameter
+    # table): closed 1000 x 2000 cavity with cold walls, 129 hot ellipses of
+    # axes 50 x 25 (6.3 % solid) in a circular cluster centred at
+    # (0.5 W, 0.75 H): one in the centre and rings of 6, 12, 18, 24, 31, 37
+    # at 60 apart, major axes horizontal; rho_p/rho_f = 1.5, Pr 5, Gr_p 10.
+    "e3_ellipses": dict(nx=1000, ny=2000, n=129, d=50.0, d_minor=25.0, layout="rings",
+                        centre=(499.5, 1499.5), rings=(6, 12, 18, 24, 31, 37), ring_spacing=60.0,
+                        rho_ratio=1.5, closed=True, steps=2000,
+                        lattice=dict(nu=0.01, alpha=0.002, gravity=9.8e-7, beta=8.16e-3)),
 }
 
 
