@@ -64,10 +64,11 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload, storage):
+def measured_traffic(workload, storage, streaming="two_sets"):
     """HBM bytes per launch of the stream-collide kernel from the committed
     rocprofv3 counter summary, if it was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", f"stream_collide_{workload}_{storage}_pmc.md")
+    tag = "" if streaming == "two_sets" else "_in_place"
+    path = os.path.join(ROOT, "profiles", f"stream_collide_{workload}_{storage}{tag}_pmc.md")
     if not os.path.exists(path):
         return None
     text = open(path).read()
@@ -200,6 +201,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="paper_scale")
     ap.add_argument("--storage", default="f64", choices=sorted(STORE_BYTES))
+    ap.add_argument("--streaming", default="two_sets", choices=["two_sets", "in_place"],
+                    help="population layout: two sets (pull) or one set in place (AA pattern)")
     ap.add_argument("--phase-steps", type=int, default=100)
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -228,7 +231,8 @@ def main():
 
     w = params.WORKLOADS[args.workload]
     nx, ny = w["nx"], w["ny"]
-    p = lbm.lbm_params_default(**params.workload_params(args.workload, lbm.STORE[args.storage]))
+    p = lbm.lbm_params_default(**params.workload_params(args.workload, lbm.STORE[args.storage]),
+                               streaming=args.streaming)
     log(f"[bench] {args.workload} {nx}x{ny} n={w['n']} d={w['d']} storage={args.storage}")
     import lbm_inputs
     sim = lbm.Sim(p)
@@ -256,7 +260,7 @@ def main():
     alg_bytes = nx * ny * 28 * es
     lat_ms = phases["lattice_overlapped"]   # as the kernel runs in the timed steps
     achieved = alg_bytes / (lat_ms * 1e-3) / 1e9
-    traffic = measured_traffic(args.workload, args.storage)
+    traffic = measured_traffic(args.workload, args.storage, args.streaming)
     log(f"[bench] phases (ms/step): {phases}")
 
     out = {
@@ -274,13 +278,15 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": describe(args.workload, args.storage)
-                        + ("" if args.addressing == "indirect" else ", direct link addressing"),
+                        + ("" if args.addressing == "indirect" else ", direct link addressing")
+                        + ("" if args.streaming == "two_sets" else ", in-place (AA) streaming"),
             "nx": nx, "ny": ny, "particles": w["n"], "diameter": w["d"], "storage": args.storage,
+            "streaming": args.streaming, "device_bytes": lbm.lbm_bytes_required(p),
             "parallelism": "single GPU",
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_stream_collide",
+            "kernel": "k_stream_collide" if args.streaming == "two_sets" else "k_stream_collide_aa",
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",

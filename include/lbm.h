@@ -55,7 +55,7 @@
 extern "C" {
 #endif
 
-#define LBM_ABI_VERSION 2
+#define LBM_ABI_VERSION 3
 
 typedef struct lbm_sim* lbm_handle;
 
@@ -77,6 +77,15 @@ enum {
     LBM_STORE_SHIFT_F32 = 2,
     LBM_STORE_SHIFT_F16 = 3,
     LBM_STORE_SHIFT_BF16 = 4,
+};
+
+/* Population layout.  TWO_SETS streams from one set of 14 arrays into the
+ * other (pull); IN_PLACE keeps one set and alternates the AA pattern's two
+ * kernels (half the population memory, the same bytes per lattice update,
+ * the same results bit for bit). */
+enum {
+    LBM_STREAM_TWO_SETS = 0,
+    LBM_STREAM_IN_PLACE = 1,
 };
 
 /* Simulation parameters, all in lattice units.  Fill with lbm_params_default
@@ -111,6 +120,7 @@ typedef struct {
     int32_t max_particles; /* capacity for particles (>= 0) */
     double max_diameter;   /* largest particle diameter the buffers are sized for */
     double side_T[2];      /* periodic_x = 0: Dirichlet temperature of the [left, right] wall */
+    int32_t streaming;     /* LBM_STREAM_* */
 } lbm_params;
 
 /* Phases reported by lbm_time_phases, in the order of a sequential step.
@@ -119,9 +129,9 @@ typedef struct {
 enum {
     LBM_PHASE_LINKS = 0,     /* bounce-back, thermal wall, momentum exchange per link */
     LBM_PHASE_PARTICLES = 1, /* per-particle sums, repulsion, net weight, Newton-Euler */
-    LBM_PHASE_MASK = 2,      /* solid map at the new positions */
+    LBM_PHASE_MASK = 2,      /* solid map at the new positions (in place: and the refill's values) */
     LBM_PHASE_LATTICE = 3,   /* fused stream + collide over the lattice */
-    LBM_PHASE_REFILL = 4,    /* refilling of newborn nodes */
+    LBM_PHASE_REFILL = 4,    /* refilling of newborn nodes (in place: their store) */
     LBM_PHASE_COLLECT = 5,   /* link collection of the next step into the index array */
     LBM_NPHASES = 6
 };

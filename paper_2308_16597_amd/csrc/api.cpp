@@ -4,6 +4,7 @@
 // particles.hip.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -51,8 +52,13 @@ Layout make_layout(const lbm_params& p) {
     L.array_stride = round_up(L.npitched * es, kArrayAlign) + kStagger;
     L.state_bytes = round_up(14 * L.array_stride, kArrayAlign);
     size_t off = 0;
+    const bool aa = p.streaming == LBM_STREAM_IN_PLACE;
     L.off_S[0] = off; off += L.state_bytes;
-    L.off_S[1] = off; off += L.state_bytes;
+    L.off_S[1] = L.off_S[0];
+    if (!aa) {
+        L.off_S[1] = off;
+        off += L.state_bytes;
+    }
     L.off_O[0] = off; off = round_up(off + L.npitched * 4, kArrayAlign);
     L.off_O[1] = off; off = round_up(off + L.npitched * 4, kArrayAlign);
     const size_t cap = (size_t)(p.max_particles > 0 ? p.max_particles : 0);
@@ -78,6 +84,14 @@ Layout make_layout(const lbm_params& p) {
     }
     L.off_cand = off; off = round_up(off + cap * 4 * (size_t)L.nwin * sizeof(unsigned), kAlign);
     L.off_ncand = off; off = round_up(off + cap * sizeof(unsigned), kAlign);
+    // field upload / read-back: the second population set of the two-set
+    // layout; in place a scratch of 4 FP64 planes over an eighth of the rows
+    L.field_rows = p.ny;
+    if (aa) {
+        L.field_rows = (p.ny + 7) / 8;
+        L.off_rbuf = off; off = round_up(off + cap * 4 * (size_t)L.nwin * 16 * sizeof(double), kAlign);
+        L.off_fscratch = off; off = round_up(off + 4 * (size_t)p.nx * L.field_rows * sizeof(double), kAlign);
+    }
     L.total = off;
     return L;
 }
@@ -118,6 +132,8 @@ bool validate(const lbm_params* p, std::string& why) {
     if (p->periodic_x != 0 && p->periodic_x != 1) return bad("periodic_x must be 0 or 1");
     if (p->periodic_y != 0 && p->periodic_y != 1) return bad("periodic_y must be 0 or 1");
     if (elem_size(p->storage) == 0) return bad("unknown storage mode");
+    if (p->streaming != LBM_STREAM_TWO_SETS && p->streaming != LBM_STREAM_IN_PLACE)
+        return bad("unknown streaming layout");
     if (!(p->rho0 > 0) || !(p->nu > 0) || !(p->alpha > 0)) return bad("rho0, nu and alpha must be > 0");
     if (!(p->a_T > -4.0 && p->a_T <= 1.0)) return bad("a_T must lie in (-4, 1]");
     const double rates[5] = {p->s_e, p->s_eps, p->s_q, p->sT_e, p->sT_p};
@@ -186,6 +202,7 @@ void fill_lp(lbm_sim* h) {
     lp.nwin = h->L.nwin;
     lp.link_cap = (int)h->L.link_cap;
     lp.direct = 0;
+    lp.aa = p.streaming == LBM_STREAM_IN_PLACE ? 1 : 0;
     lp.ncx = h->L.ncx;
     lp.ncy = h->L.ncy;
     lp.ncells = p.max_particles > 0 ? h->L.ncx * h->L.ncy : 0;
@@ -229,6 +246,7 @@ int create_common(const lbm_params* p, void* dev_ptr, size_t bytes, void* stream
         hipError_t e = hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_side, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_mask, hipEventDisableTiming);
         if (e != hipSuccess) {
             lbm_destroy(h);
             return fail(nullptr, LBM_EDEVICE, "side stream / events: %s", hipGetErrorString(e));
@@ -254,6 +272,7 @@ int create_common(const lbm_params* p, void* dev_ptr, size_t bytes, void* stream
     }
     d.cand = (unsigned*)(h->base + L.off_cand);
     d.ncand = (unsigned*)(h->base + L.off_ncand);
+    d.rbuf = L.off_rbuf ? (double*)(h->base + L.off_rbuf) : nullptr;
     fill_lp(h);
     *out = h;
     int rc = lbm_set_particles(h, 0, nullptr);
@@ -288,6 +307,7 @@ RunStep make_runstep(const lbm_sim* h, int c, int r, int bp) {
     const DevState& d = h->d;
     RunStep R{};
     R.lp = d.lp;
+    R.parity = c;
     for (int i = 0; i < 14; ++i) {
         R.A[i] = d.S[c][i];
         R.B[i] = d.S[1 - c][i];
@@ -308,6 +328,7 @@ RunStep make_runstep(const lbm_sim* h, int c, int r, int bp) {
     R.cnt_next = d.bcnt[1 - bp];
     R.cand = d.cand;
     R.ncand = d.ncand;
+    R.rbuf = d.rbuf;
     return R;
 }
 
@@ -334,6 +355,11 @@ namespace {
 // event operation costs the main stream a few microseconds of idle time):
 //   main: link pass -> [fork] -> lattice -> wait(side) -> refill
 //   side: wait(fork) -> particles -> mask -> links of t_n+1 -> [side]
+// In place the refill's values are computed with the owner map, before the
+// lattice kernel overwrites the state they are pulled from, so the lattice
+// kernel waits for that part of the side stream:
+//   main: link pass -> [fork] -> wait(mask) -> lattice -> refill store -> wait(side)
+//   side: wait(fork) -> particles -> mask + refill values -> [mask] -> links of t_n+1 -> [side]
 int enqueue_step(lbm_sim* h, hipEvent_t* ev, hipEvent_t* lat = nullptr) {
     hipStream_t st = h->stream;
     const RunStep R = current_runstep(h);
@@ -352,19 +378,31 @@ int enqueue_step(lbm_sim* h, hipEvent_t* ev, hipEvent_t* lat = nullptr) {
         HIPCHK(h, hipStreamWaitEvent(sd, h->ev_fork, 0));
         HIPCHK(h, launch_step(SK_PARTICLES, R, mode, sd));
         HIPCHK(h, launch_step(SK_MASK, R, mode, sd));
+        const bool aa = h->d.lp.aa != 0;
+        if (aa) HIPCHK(h, hipEventRecord(h->ev_mask, sd));
         HIPCHK(h, launch_step(SK_COLLECT, Rn, mode, sd));
         HIPCHK(h, hipEventRecord(h->ev_side, sd));
+        if (aa) HIPCHK(h, hipStreamWaitEvent(st, h->ev_mask, 0));
         if (lat) HIPCHK(h, hipEventRecord(lat[0], st));
         HIPCHK(h, launch_step(SK_LATTICE, R, mode, st));
         if (lat) HIPCHK(h, hipEventRecord(lat[1], st));
-        HIPCHK(h, hipStreamWaitEvent(st, h->ev_side, 0));
-        HIPCHK(h, launch_step(SK_REFILL, R, mode, st));
+        if (aa) {
+            HIPCHK(h, launch_step(SK_REFILL, R, mode, st));
+            HIPCHK(h, hipStreamWaitEvent(st, h->ev_side, 0));
+        } else {
+            HIPCHK(h, hipStreamWaitEvent(st, h->ev_side, 0));
+            HIPCHK(h, launch_step(SK_REFILL, R, mode, st));
+        }
     }
     advance_state(h);
     return LBM_OK;
 }
 
-void* scratch_of(lbm_sim* h) { return h->d.S[1 - h->cur][0]; }
+// Device scratch for field uploads and read-backs of L.field_rows rows: the
+// idle population set of the two-set layout, a buffer of its own in place.
+void* scratch_of(lbm_sim* h) {
+    return h->d.lp.aa ? (void*)(h->base + h->L.off_fscratch) : h->d.S[1 - h->cur][0];
+}
 
 void drop_cycle_graph(lbm_sim* h) {
     if (h->cycle_graph) (void)hipGraphExecDestroy(h->cycle_graph);
@@ -453,7 +491,7 @@ void lbm_destroy(lbm_handle h) {
     if (h->side) (void)hipStreamSynchronize(h->side);
     drop_cycle_graph(h);
     if (h->own_mem && h->base) (void)hipFree(h->base);
-    for (hipEvent_t e : {h->ev_fork, h->ev_side})
+    for (hipEvent_t e : {h->ev_fork, h->ev_side, h->ev_mask})
         if (e) (void)hipEventDestroy(e);
     if (h->side) (void)hipStreamDestroy(h->side);
     if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
@@ -608,7 +646,7 @@ int set_particles_rows(lbm_handle h, int32_t n, const double* rows, int cols) {
         HIPCHK(h, launch_bin_init(d, d.P[0], 0, st));
         HIPCHK(h, launch_step(SK_COLLECT, current_runstep(h), d.mode, st));   // links of t_0
     }
-    HIPCHK(h, launch_init(d, 0, nullptr, nullptr, nullptr, nullptr, true, h->p.rho0, h->p.T_fluid0, st));
+    HIPCHK(h, launch_init(d, 0, 0, h->p.ny, nullptr, nullptr, nullptr, nullptr, true, h->p.rho0, h->p.T_fluid0, st));
     HIPCHK(h, hipStreamSynchronize(st));
     h->steps = 0;
     return LBM_OK;
@@ -644,26 +682,30 @@ int lbm_set_addressing(lbm_handle h, int32_t mode) {
 int lbm_set_equilibrium(lbm_handle h, const double* rho, const double* ux, const double* uy, const double* T) {
     if (!h) return LBM_EINVAL;
     if (!rho || !ux || !uy || !T) return fail(h, LBM_EINVAL, "null field");
-    const size_t n = (size_t)h->p.nx * h->p.ny;
+    const size_t nx = (size_t)h->p.nx;
     const bool f64 = h->p.storage == LBM_STORE_F64;
+    const size_t es = f64 ? 8 : 4;
     char* scr = (char*)scratch_of(h);
     const double* src[4] = {rho, ux, uy, T};
     HIPCHK(h, hipStreamSynchronize(h->stream));
-    if (f64) {
-        for (int c = 0; c < 4; ++c)
-            HIPCHK(h, hipMemcpyAsync(scr + c * n * 8, src[c], n * 8, hipMemcpyHostToDevice, h->stream));
-        HIPCHK(h, hipStreamSynchronize(h->stream));
-    } else {
-        std::vector<float> tmp(4 * n);
-        for (int c = 0; c < 4; ++c)
-            for (size_t k = 0; k < n; ++k) tmp[c * n + k] = (float)src[c][k];
-        HIPCHK(h, hipMemcpyAsync(scr, tmp.data(), 4 * n * 4, hipMemcpyHostToDevice, h->stream));
+    std::vector<float> tmp;
+    // in chunks of L.field_rows rows (the whole lattice with two sets)
+    for (int y0 = 0; y0 < h->p.ny; y0 += h->L.field_rows) {
+        const int rows = std::min(h->L.field_rows, h->p.ny - y0);
+        const size_t n = nx * rows, off = nx * y0;
+        if (f64) {
+            for (int c = 0; c < 4; ++c)
+                HIPCHK(h, hipMemcpyAsync(scr + c * n * 8, src[c] + off, n * 8, hipMemcpyHostToDevice, h->stream));
+        } else {
+            tmp.resize(4 * n);
+            for (int c = 0; c < 4; ++c)
+                for (size_t k = 0; k < n; ++k) tmp[c * n + k] = (float)src[c][off + k];
+            HIPCHK(h, hipMemcpyAsync(scr, tmp.data(), 4 * n * 4, hipMemcpyHostToDevice, h->stream));
+        }
+        HIPCHK(h, launch_init(h->d, h->cur, y0, rows, scr, scr + n * es, scr + 2 * n * es, scr + 3 * n * es, f64,
+                              0.0, 0.0, h->stream));
         HIPCHK(h, hipStreamSynchronize(h->stream));
     }
-    const size_t es = f64 ? 8 : 4;
-    HIPCHK(h, launch_init(h->d, h->cur, scr, scr + n * es, scr + 2 * n * es, scr + 3 * n * es, f64, 0.0, 0.0,
-                          h->stream));
-    HIPCHK(h, hipStreamSynchronize(h->stream));
     h->steps = 0;
     return LBM_OK;
 }
@@ -704,23 +746,30 @@ int lbm_read_fields(lbm_handle h, double* rho, double* ux, double* uy, double* T
     if (!h) return LBM_EINVAL;
     int rc = lbm_sync(h);
     if (rc != LBM_OK && rc != LBM_EUNSTABLE) return rc;
-    const size_t n = (size_t)h->p.nx * h->p.ny;
+    const size_t nx = (size_t)h->p.nx;
     const bool f64 = h->p.storage == LBM_STORE_F64;
     void* scr = scratch_of(h);
-    HIPCHK(h, launch_macros(h->d, h->cur, scr, h->stream));
     double* outs[4] = {rho, ux, uy, T};
-    if (f64) {
-        for (int c = 0; c < 4; ++c)
-            if (outs[c])
-                HIPCHK(h, hipMemcpyAsync(outs[c], (char*)scr + c * n * 8, n * 8, hipMemcpyDeviceToHost, h->stream));
-        HIPCHK(h, hipStreamSynchronize(h->stream));
-    } else {
-        std::vector<float> tmp(n);
-        for (int c = 0; c < 4; ++c) {
-            if (!outs[c]) continue;
-            HIPCHK(h, hipMemcpyAsync(tmp.data(), (char*)scr + c * n * 4, n * 4, hipMemcpyDeviceToHost, h->stream));
+    std::vector<float> tmp;
+    // in chunks of L.field_rows rows (the whole lattice with two sets)
+    for (int y0 = 0; y0 < h->p.ny; y0 += h->L.field_rows) {
+        const int rows = std::min(h->L.field_rows, h->p.ny - y0);
+        const size_t n = nx * rows, off = nx * y0;
+        HIPCHK(h, launch_macros(h->d, h->cur, y0, rows, scr, h->stream));
+        if (f64) {
+            for (int c = 0; c < 4; ++c)
+                if (outs[c])
+                    HIPCHK(h, hipMemcpyAsync(outs[c] + off, (char*)scr + c * n * 8, n * 8, hipMemcpyDeviceToHost,
+                                             h->stream));
             HIPCHK(h, hipStreamSynchronize(h->stream));
-            for (size_t k = 0; k < n; ++k) outs[c][k] = tmp[k];
+        } else {
+            tmp.resize(n);
+            for (int c = 0; c < 4; ++c) {
+                if (!outs[c]) continue;
+                HIPCHK(h, hipMemcpyAsync(tmp.data(), (char*)scr + c * n * 4, n * 4, hipMemcpyDeviceToHost, h->stream));
+                HIPCHK(h, hipStreamSynchronize(h->stream));
+                for (size_t k = 0; k < n; ++k) outs[c][off + k] = tmp[k];
+            }
         }
     }
     HIPCHK(h, hipStreamSynchronize(h->stream));

@@ -94,6 +94,7 @@ struct LP {
     int repulsion, np, nwin;           // particles, window edge capacity
     int link_cap;
     int direct;                        // link pass by direct addressing (ablation)
+    int aa;                            // in-place (AA) streaming in one population set
     int ncx, ncy, ncells;              // neighbour-search cell grid
 };
 
@@ -299,6 +300,130 @@ __device__ __forceinline__ void store_node(const Pops<typename S::T>& B, const L
     for (int k5 = 0; k5 < 5; ++k5) {
         if (NT) S::st_nt(B.g[k5] + k, t[k5]);
         else S::st(B.g[k5] + k, t[k5]);
+    }
+}
+
+// ------------------------------------------------ in-place (AA) streaming ----
+// One population set F holds the state.  After an even kernel (and after
+// initialisation) the post-collision value f_k*(y) sits in slot kbar of y
+// itself (parity 0, "reversed"); the odd kernel pulls from there and pushes
+// f_k*(x) to slot k of x + e_k, or to slot kbar of x where x + e_k is beyond
+// a wall (parity 1, "pushed"); the even kernel then reads slot k of x in
+// place, which is f_k(x) after streaming, with the wall rules applied at
+// read time, and writes f_k* reversed into x.  Each location is read and
+// written by one thread only, so the update is in place.  A parity-0 state
+// is the two-set state with slots k and kbar exchanged: every reader and
+// writer of the two-set layout works on it through opp_view.
+__device__ __forceinline__ constexpr int OPP5d(int k) { return k == 0 ? 0 : ((k + 1) % 4 + 1); }
+template <class T> __host__ __device__ Pops<T> opp_view(const Pops<T>& F) {
+    Pops<T> v;
+    for (int i = 0; i < 9; ++i) v.f[i] = F.f[i == 0 ? 0 : (i <= 4 ? ((i + 1) % 4 + 1) : ((i - 5 + 2) % 4 + 5))];
+    for (int k = 0; k < 5; ++k) v.g[k] = F.g[k == 0 ? 0 : ((k + 1) % 4 + 1)];
+    return v;
+}
+
+// Whether node (x, y) + e_k lies beyond a flat wall (not a node).
+__device__ __forceinline__ bool beyond_wall(const LP& lp, int x, int y, int k) {
+    const int x2 = x + EXd(k), y2 = y + EYd(k);
+    return (!lp.periodic_y && (y2 < 0 || y2 >= lp.ny)) || (!lp.periodic_x && (x2 < 0 || x2 >= lp.nx));
+}
+// Index of node (x, y) + e_k with the periodic axes wrapped (a node).
+__device__ __forceinline__ size_t node_plus(const LP& lp, int x, int y, int k) {
+    int x2 = x + EXd(k), y2 = y + EYd(k);
+    x2 = x2 < 0 ? x2 + lp.nx : (x2 >= lp.nx ? x2 - lp.nx : x2);
+    y2 = y2 < 0 ? y2 + lp.ny : (y2 >= lp.ny ? y2 - lp.ny : y2);
+    return (size_t)y2 * lp.pitch + x2;
+}
+// Where the pushed (parity-1) state keeps f_k*(x, y): slot *slot at the
+// returned node index.
+__device__ __forceinline__ size_t pushed_at(const LP& lp, int x, int y, int k, int& slot) {
+    if (beyond_wall(lp, x, y, k)) {
+        slot = OPPd(k);
+        return (size_t)y * lp.pitch + x;
+    }
+    slot = k;
+    return node_plus(lp, x, y, k);
+}
+// The same as an address, for a population index k known at compile time
+// (after unrolling), so that no pointer table is indexed at run time.
+template <class T>
+__device__ __forceinline__ PT_GLOBAL T* pushed_ptr(PT_GLOBAL T* own, PT_GLOBAL T* opp, const LP& lp, int x, int y,
+                                                    int k) {
+    if (beyond_wall(lp, x, y, k)) return opp + ((size_t)y * lp.pitch + x);
+    return own + node_plus(lp, x, y, k);
+}
+
+// The even kernel's read of node (x, y) from a pushed state: every slot in
+// place; where the upstream node is beyond a wall the slot holds the
+// node's own outgoing post-collision value and the wall rule of pull_node
+// applies to it (with the same arithmetic, so both layouts give the same
+// bits).
+template <class S, bool NTL = false>
+__device__ __forceinline__ void pull_node_pushed(const Pops<typename S::T>& F, const LP& lp, int x, int y,
+                                                 typename S::R (&s)[9], typename S::R (&t)[5]) {
+    using R = typename S::R;
+    auto ld = [](const PT_GLOBAL typename S::T* q) { return NTL ? S::ld_nt(q) : S::ld(q); };
+    const bool bot = !lp.periodic_y && y == 0;
+    const bool top = !lp.periodic_y && y == lp.ny - 1;
+    const bool lft = !lp.periodic_x && x == 0;
+    const bool rgt = !lp.periodic_x && x == lp.nx - 1;
+    const size_t k = (size_t)y * lp.pitch + x;
+    R fs[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) fs[i] = S::shifted ? (R)0 : w9<R>(i) * (R)lp.rho0;
+    const R w5k = (R)lp.w5_k;
+    s[0] = ld(F.f[0] + k) - fs[0];
+    s[1] = ld(F.f[1] + k) - fs[1];
+    s[3] = ld(F.f[3] + k) - fs[3];
+    t[0] = ld(F.g[0] + k);
+    const R g1 = ld(F.g[1] + k);
+    const R g3 = ld(F.g[3] + k);
+    t[1] = lft ? (R)2 * w5k * ((R)lp.side_T[0] - (R)lp.T_sh) - g1 : g1;
+    t[3] = rgt ? (R)2 * w5k * ((R)lp.side_T[1] - (R)lp.T_sh) - g3 : g3;
+    if (bot) {
+        const R u = (R)lp.wall_ux[0] * (R)lp.rho0 * (R)(1.0 / 6.0);
+        s[2] = ld(F.f[2] + k) - fs[4];
+        s[5] = (ld(F.f[5] + k) - fs[7]) + u;
+        s[6] = (ld(F.f[6] + k) - fs[8]) - u;
+        t[2] = -ld(F.g[2] + k) + (R)2 * w5k * ((R)lp.wall_T[0] - (R)lp.T_sh);
+    } else {
+        s[2] = ld(F.f[2] + k) - fs[2];
+        s[5] = ld(F.f[5] + k) - fs[5];
+        s[6] = ld(F.f[6] + k) - fs[6];
+        t[2] = ld(F.g[2] + k);
+    }
+    if (top) {
+        const R u = (R)lp.wall_ux[1] * (R)lp.rho0 * (R)(1.0 / 6.0);
+        s[4] = ld(F.f[4] + k) - fs[2];
+        s[7] = (ld(F.f[7] + k) - fs[5]) - u;
+        s[8] = (ld(F.f[8] + k) - fs[6]) + u;
+        t[4] = -ld(F.g[4] + k) + (R)2 * w5k * ((R)lp.wall_T[1] - (R)lp.T_sh);
+    } else {
+        s[4] = ld(F.f[4] + k) - fs[4];
+        s[7] = ld(F.f[7] + k) - fs[7];
+        s[8] = ld(F.f[8] + k) - fs[8];
+        t[4] = ld(F.g[4] + k);
+    }
+}
+
+// The odd kernel's store: f_k*(x, y) pushed to slot k of (x, y) + e_k, or to
+// slot kbar of (x, y) where that node is beyond a wall.
+template <class S, bool NT = false>
+__device__ __forceinline__ void store_node_pushed(const Pops<typename S::T>& F, const LP& lp, int x, int y,
+                                                  const typename S::R (&s)[9], const typename S::R (&t)[5]) {
+    using R = typename S::R;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const R v = s[i] + (S::shifted ? (R)0 : w9<R>(i) * (R)lp.rho0);
+        PT_GLOBAL typename S::T* q = pushed_ptr(F.f[i], F.f[OPPd(i)], lp, x, y, i);
+        if (NT) S::st_nt(q, v);
+        else S::st(q, v);
+    }
+#pragma unroll
+    for (int k5 = 0; k5 < 5; ++k5) {
+        PT_GLOBAL typename S::T* q = pushed_ptr(F.g[k5], F.g[OPPd(k5)], lp, x, y, k5);
+        if (NT) S::st_nt(q, t[k5]);
+        else S::st(q, t[k5]);
     }
 }
 

@@ -50,20 +50,54 @@ __device__ __forceinline__ void stream_collide_body(const RunStep& rs, unsigned 
     store_node<S, true>(B, lp, k, s, t);
 }
 
-// Equilibrium of the given macroscopic fields (host layout j*nx + i; NULL
-// pointers select the uniform rest state), collided once: the
-// post-collision state of t_0.
+// The same step in place (AA streaming, one population set F = A = B).
+// ODD: from a reversed (parity-0) state, the pull of pull_node through
+// opp_view, the post-collision values pushed to the neighbours (parity 1
+// after it).  EVEN: from a pushed state, every slot read in place
+// (pull_node_pushed) and written back reversed into the node (parity 0).
+// Same collision, same wall rules, same values as the two-set kernel.
+template <int MODE, bool ODD>
+__device__ __forceinline__ void stream_collide_aa_body(const RunStep& rs, unsigned bid) {
+    using S = Store<MODE>;
+    using R = typename S::R;
+    const LP& lp = rs.lp;
+    const Pops<ST<MODE>> F = pops_of<MODE>(rs.A);
+    const size_t n0 = (size_t)bid * LAT_BLOCK + threadIdx.x;
+    const int y = (int)(n0 / (unsigned)lp.pitch);
+    const int x = (int)(n0 - (size_t)y * lp.pitch);
+    if (x >= lp.nx || y >= lp.ny) return;
+    const size_t k = (size_t)y * lp.pitch + x;
+    R s[9], t[5];
+    if (ODD) pull_node<S, true>(opp_view(F), lp, x, y, s, t);
+    else pull_node_pushed<S, true>(F, lp, x, y, s, t);
+    const CC<R> c(lp);
+    R rho, ux, uy, T;
+    collide<R>(c, s, t, rho, ux, uy, T);
+    if (!(isfinite(rho) && isfinite(T) && isfinite(ux) && isfinite(uy)) && gl(rs.Ocur)[k] == -1) {
+        const unsigned long long m = __ballot(1);
+        if ((threadIdx.x & 63) == (unsigned)(__ffsll((long long)m) - 1) && !(gl(rs.status)[0] & ST_NONFINITE))
+            atomicOr(rs.status, ST_NONFINITE);
+    }
+    if (ODD) store_node_pushed<S, true>(F, lp, x, y, s, t);
+    else store_node<S, true>(opp_view(F), lp, k, s, t);
+}
+
+// Equilibrium of the given macroscopic fields (host layout j*nx + i over
+// rows y0.., NULL pointers select the uniform rest state), collided once:
+// the post-collision state of t_0, in the two-set layout or, in place, in
+// the layout of the given parity.
 template <int MODE, class FT>
 __global__ __launch_bounds__(LAT_BLOCK) void k_init(Pops<ST<MODE>> A, const int32_t* __restrict__ owner,
                                                     const FT* rho_f, const FT* ux_f, const FT* uy_f,
-                                                    const FT* T_f, double rho_u, double T_u, LP lp) {
+                                                    const FT* T_f, double rho_u, double T_u, int y0, int parity,
+                                                    LP lp) {
     using S = Store<MODE>;
     using R = typename S::R;
     const int x = blockIdx.x * LAT_BLOCK + threadIdx.x;
-    const int y = blockIdx.y;
+    const int y = y0 + (int)blockIdx.y;
     if (x >= lp.nx) return;
     const size_t k = (size_t)y * lp.pitch + x;
-    const size_t h = (size_t)y * lp.nx + x;
+    const size_t h = (size_t)blockIdx.y * lp.nx + x;
     R s[9], t[5];
     if (owner[k] >= 0) {
         for (int i = 0; i < 9; ++i) s[i] = (R)0;
@@ -79,22 +113,26 @@ __global__ __launch_bounds__(LAT_BLOCK) void k_init(Pops<ST<MODE>> A, const int3
         R r_, u_, v_, T_;
         collide<R>(c, s, t, r_, u_, v_, T_);
     }
-    store_node<S>(A, lp, k, s, t);
+    if (!lp.aa) store_node<S>(A, lp, k, s, t);
+    else if (parity == 0) store_node<S>(opp_view(A), lp, k, s, t);
+    else store_node_pushed<S>(A, lp, x, y, s, t);
 }
 
 // Pre-collision macroscopics from the post-collision state: rho and T are
 // collision invariants and the momentum gained the force, so
-// u = (j+ - F/2)/rho.  NaN inside solids.  Output: 4 planes of nx*ny (OT).
+// u = (j+ - F/2)/rho.  NaN inside solids.  Output: 4 planes of nx * rows
+// (OT) for rows y0..; the state in either layout.
 template <int MODE, class OT>
 __global__ __launch_bounds__(LAT_BLOCK) void k_macros(Pops<ST<MODE>> A, const int32_t* __restrict__ owner,
-                                                      OT* out, LP lp) {
+                                                      OT* out, int y0, int rows, int parity, LP lp) {
     using S = Store<MODE>;
     using R = typename S::R;
     const int x = blockIdx.x * LAT_BLOCK + threadIdx.x;
-    const int y = blockIdx.y;
+    const int y = y0 + (int)blockIdx.y;
     if (x >= lp.nx) return;
     const size_t k = (size_t)y * lp.pitch + x;
-    const size_t n = (size_t)lp.nx * lp.ny, h = (size_t)y * lp.nx + x;
+    const size_t n = (size_t)lp.nx * rows, h = (size_t)blockIdx.y * lp.nx + x;
+    if (lp.aa && parity == 0) A = opp_view(A);
     if (owner[k] >= 0) {
         const OT nan = (OT)NAN;
         out[h] = nan;
@@ -104,10 +142,19 @@ __global__ __launch_bounds__(LAT_BLOCK) void k_macros(Pops<ST<MODE>> A, const in
         return;
     }
     R s[9], t[5];
+    if (lp.aa && parity == 1) {   // pushed: f_k* sits at the neighbour (or reversed at a wall)
 #pragma unroll
-    for (int i = 0; i < 9; ++i) s[i] = S::ld(A.f[i] + k) - (S::shifted ? (R)0 : w9<R>(i) * (R)lp.rho0);
+        for (int i = 0; i < 9; ++i)
+            s[i] = S::ld(pushed_ptr(A.f[i], A.f[OPPd(i)], lp, x, y, i)) -
+                   (S::shifted ? (R)0 : w9<R>(i) * (R)lp.rho0);
 #pragma unroll
-    for (int i = 0; i < 5; ++i) t[i] = S::ld(A.g[i] + k);
+        for (int i = 0; i < 5; ++i) t[i] = S::ld(pushed_ptr(A.g[i], A.g[OPPd(i)], lp, x, y, i));
+    } else {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) s[i] = S::ld(A.f[i] + k) - (S::shifted ? (R)0 : w9<R>(i) * (R)lp.rho0);
+#pragma unroll
+        for (int i = 0; i < 5; ++i) t[i] = S::ld(A.g[i] + k);
+    }
     R drho = (R)0, jx = (R)0, jy = (R)0, dT = (R)0;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
@@ -140,43 +187,65 @@ __global__ __launch_bounds__(LAT_BLOCK) void k_stream_collide_b(const RunStep* _
     const uint2 m = bmap[blockIdx.x];
     stream_collide_body<MODE>(tab[m.x], m.y);
 }
+template <int MODE, bool ODD>
+__global__ __launch_bounds__(LAT_BLOCK) void k_stream_collide_aa(RunStep rs) {
+    stream_collide_aa_body<MODE, ODD>(rs, blockIdx.x);
+}
+// batched in place: each run at its own parity (one branch per block)
+template <int MODE>
+__global__ __launch_bounds__(LAT_BLOCK) void k_stream_collide_aa_b(const RunStep* __restrict__ tab,
+                                                                   const uint2* __restrict__ bmap) {
+    const uint2 m = bmap[blockIdx.x];
+    if (tab[m.x].parity == 0) stream_collide_aa_body<MODE, true>(tab[m.x], m.y);
+    else stream_collide_aa_body<MODE, false>(tab[m.x], m.y);
+}
 
 // -------------------------------------------------------------- launchers ----
 
-static dim3 lattice_grid(const LP& lp) { return dim3((lp.nx + LAT_BLOCK - 1) / LAT_BLOCK, lp.ny); }
+static dim3 lattice_grid(const LP& lp, int rows) { return dim3((lp.nx + LAT_BLOCK - 1) / LAT_BLOCK, rows); }
 
 hipError_t launch_lattice(const RunStep& R, int mode, unsigned nblocks, hipStream_t st) {
-    PTLBM_DISPATCH(mode, (k_stream_collide<M><<<nblocks, LAT_BLOCK, 0, st>>>(R)));
-    return hipGetLastError();
-}
-
-hipError_t launch_lattice_batch(const RunStep* tab, const uint2* bmap, unsigned nblocks, int mode,
-                                hipStream_t st) {
-    PTLBM_DISPATCH(mode, (k_stream_collide_b<M><<<nblocks, LAT_BLOCK, 0, st>>>(tab, bmap)));
-    return hipGetLastError();
-}
-
-hipError_t launch_init(const DevState& d, int cur, const void* rho, const void* ux, const void* uy,
-                       const void* T, bool f64, double rho_u, double T_u, hipStream_t st) {
-    if (f64) {
-        PTLBM_DISPATCH(d.mode, (k_init<M, double><<<lattice_grid(d.lp), LAT_BLOCK, 0, st>>>(
-                                   pops_of<M>(d.S[cur]), d.O[cur], (const double*)rho, (const double*)ux,
-                                   (const double*)uy, (const double*)T, rho_u, T_u, d.lp)));
+    if (!R.lp.aa) {
+        PTLBM_DISPATCH(mode, (k_stream_collide<M><<<nblocks, LAT_BLOCK, 0, st>>>(R)));
+    } else if (R.parity == 0) {
+        PTLBM_DISPATCH(mode, (k_stream_collide_aa<M, true><<<nblocks, LAT_BLOCK, 0, st>>>(R)));
     } else {
-        PTLBM_DISPATCH(d.mode, (k_init<M, float><<<lattice_grid(d.lp), LAT_BLOCK, 0, st>>>(
-                                   pops_of<M>(d.S[cur]), d.O[cur], (const float*)rho, (const float*)ux,
-                                   (const float*)uy, (const float*)T, rho_u, T_u, d.lp)));
+        PTLBM_DISPATCH(mode, (k_stream_collide_aa<M, false><<<nblocks, LAT_BLOCK, 0, st>>>(R)));
     }
     return hipGetLastError();
 }
 
-hipError_t launch_macros(const DevState& d, int cur, void* out, hipStream_t st) {
-    if (d.mode == LBM_STORE_F64) {
-        k_macros<LBM_STORE_F64, double><<<lattice_grid(d.lp), LAT_BLOCK, 0, st>>>(
-            pops_of<LBM_STORE_F64>(d.S[cur]), d.O[cur], (double*)out, d.lp);
+hipError_t launch_lattice_batch(const RunStep* tab, const uint2* bmap, unsigned nblocks, int mode, bool aa,
+                                hipStream_t st) {
+    if (aa) {
+        PTLBM_DISPATCH(mode, (k_stream_collide_aa_b<M><<<nblocks, LAT_BLOCK, 0, st>>>(tab, bmap)));
     } else {
-        PTLBM_DISPATCH(d.mode, (k_macros<M, float><<<lattice_grid(d.lp), LAT_BLOCK, 0, st>>>(
-                                   pops_of<M>(d.S[cur]), d.O[cur], (float*)out, d.lp)));
+        PTLBM_DISPATCH(mode, (k_stream_collide_b<M><<<nblocks, LAT_BLOCK, 0, st>>>(tab, bmap)));
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_init(const DevState& d, int cur, int y0, int rows, const void* rho, const void* ux,
+                       const void* uy, const void* T, bool f64, double rho_u, double T_u, hipStream_t st) {
+    if (f64) {
+        PTLBM_DISPATCH(d.mode, (k_init<M, double><<<lattice_grid(d.lp, rows), LAT_BLOCK, 0, st>>>(
+                                   pops_of<M>(d.S[cur]), d.O[cur], (const double*)rho, (const double*)ux,
+                                   (const double*)uy, (const double*)T, rho_u, T_u, y0, cur, d.lp)));
+    } else {
+        PTLBM_DISPATCH(d.mode, (k_init<M, float><<<lattice_grid(d.lp, rows), LAT_BLOCK, 0, st>>>(
+                                   pops_of<M>(d.S[cur]), d.O[cur], (const float*)rho, (const float*)ux,
+                                   (const float*)uy, (const float*)T, rho_u, T_u, y0, cur, d.lp)));
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_macros(const DevState& d, int cur, int y0, int rows, void* out, hipStream_t st) {
+    if (d.mode == LBM_STORE_F64) {
+        k_macros<LBM_STORE_F64, double><<<lattice_grid(d.lp, rows), LAT_BLOCK, 0, st>>>(
+            pops_of<LBM_STORE_F64>(d.S[cur]), d.O[cur], (double*)out, y0, rows, cur, d.lp);
+    } else {
+        PTLBM_DISPATCH(d.mode, (k_macros<M, float><<<lattice_grid(d.lp, rows), LAT_BLOCK, 0, st>>>(
+                                   pops_of<M>(d.S[cur]), d.O[cur], (float*)out, y0, rows, cur, d.lp)));
     }
     return hipGetLastError();
 }

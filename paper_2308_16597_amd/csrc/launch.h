@@ -15,7 +15,7 @@ namespace ptlbm {
 struct DevState {
     LP lp;
     int mode;
-    void* S[2][14];              // population arrays of the two time levels
+    void* S[2][14];              // population arrays of the two time levels (one set, twice, in place)
     int32_t* O[2];               // owner maps
     PState* P[3];                // particle ring (old, current, next rotate)
     double* Fh;                  // per-particle momentum-exchange force/torque (x, y, z, pad)
@@ -27,6 +27,7 @@ struct DevState {
     unsigned* bcnt[2];           // particles per cell
     unsigned* cand;              // newborn-node candidates, 4 nwin per particle (x | y << 16)
     unsigned* ncand;             // candidates per particle
+    double* rbuf;                // in place: refilled post-collision values per candidate (16 each)
 };
 
 // Everything the step kernels need of one run at one step: its lattice
@@ -35,8 +36,9 @@ struct DevState {
 // single-run launch; an array of them (one per run) drives a batched launch.
 struct RunStep {
     LP lp;
+    int parity;                  // in place: 0 reversed state (odd kernel next), 1 pushed (even next)
     void* A[14];                 // post-collision state of t_n
-    void* B[14];                 // state of t_n+1 being written
+    void* B[14];                 // state of t_n+1 being written (A itself in place)
     int32_t* Ocur;               // owner map of t_n
     int32_t* Onext;              // owner map of t_n+1 (holds t_n-1 until cleared)
     const PState* Pold;          // particles at t_n-1
@@ -53,6 +55,7 @@ struct RunStep {
     unsigned* cnt_next;
     unsigned* cand;
     unsigned* ncand;
+    double* rbuf;
 };
 
 // The six step kernels, in the order of a sequential step; SK_COLLECT
@@ -76,6 +79,7 @@ struct BatchLaunch {
     int ppb;                     // particles per block of the link collection
     size_t lds;                  // its dynamic LDS bytes
     int mode;
+    bool aa;                     // every run of the batch streams in place
 };
 
 enum StatusBits : unsigned {
@@ -94,17 +98,20 @@ int links_particles_per_block(int nwin);
 size_t links_block_lds(int nwin, int ppb);
 
 hipError_t launch_step(int k, const RunStep& R, int mode, hipStream_t st);
-// The lattice kernel alone (lattice.hip), for one run or batched.
+// The lattice kernel alone (lattice.hip), for one run or batched (two-set
+// or in place, at each run's parity).
 hipError_t launch_lattice(const RunStep& R, int mode, unsigned nblocks, hipStream_t st);
-hipError_t launch_lattice_batch(const RunStep* tab, const uint2* bmap, unsigned nblocks, int mode,
+hipError_t launch_lattice_batch(const RunStep* tab, const uint2* bmap, unsigned nblocks, int mode, bool aa,
                                 hipStream_t st);
 hipError_t launch_step_batch(int k, const BatchLaunch& b, hipStream_t st);
 // Owner map of R.Pn into R.Onext with no previous time level (set-up).
 hipError_t launch_mask_setup(const RunStep& R, hipStream_t st);
 
-hipError_t launch_init(const DevState& d, int cur, const void* rho, const void* ux, const void* uy,
-                       const void* T, bool fields_f64, double rho_u, double T_u, hipStream_t st);
-hipError_t launch_macros(const DevState& d, int cur, void* out, hipStream_t st);
+// Initial state and macroscopic read-back over rows y0 .. y0 + rows - 1 (the
+// host fields and the output are nx x rows planes).
+hipError_t launch_init(const DevState& d, int cur, int y0, int rows, const void* rho, const void* ux,
+                       const void* uy, const void* T, bool fields_f64, double rho_u, double T_u, hipStream_t st);
+hipError_t launch_macros(const DevState& d, int cur, int y0, int rows, void* out, hipStream_t st);
 hipError_t launch_bin_init(const DevState& d, const PState* P, int bin_parity, hipStream_t st);
 hipError_t launch_link_q(const DevState& d, int ring, const uint2* links, int nlinks, int32_t* node,
                          int32_t* dir, int32_t* part, double* q, hipStream_t st);

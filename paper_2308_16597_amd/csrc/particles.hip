@@ -216,14 +216,46 @@ __device__ __forceinline__ void link_pass_link(const RunStep& rs, const PState& 
     const size_t k1 = in1 ? (size_t)y1 * pitch + x1 : k;
     const size_t k2 = in2 ? (size_t)y2 * pitch + x2 : k;
     const int32_t o1 = Ocur[k1], o2 = Ocur[k2];
-    const double fi = (double)S::ld(F(i) + k), fib = (double)S::ld(F(ib) + k);
-    const double fi1 = (double)S::ld(F(i) + k1), fib1 = (double)S::ld(F(ib) + k1);
-    const double fi2 = (double)S::ld(F(i) + k2);
-    double gi = 0.0, gib = 0.0, gi1 = 0.0;
-    if (i <= 4) {
-        gi = (double)S::ld(F(9 + i) + k);
-        gib = (double)S::ld(F(9 + ib) + k);
-        gi1 = (double)S::ld(F(9 + i) + k1);
+    // where the post-collision state keeps f_a*(node): slot a at the node
+    // (two sets), slot abar at the node (in place, reversed), or slot a at
+    // the node + e_a (in place, pushed; slot abar at the node at a wall)
+    const int lay = lp.aa ? 1 + rs.parity : 0;
+    double fi, fib, fi1, fib1, fi2, gi = 0.0, gib = 0.0, gi1 = 0.0;
+    if (lay != 2) {
+        const int si = lay ? ib : i, sib = lay ? i : ib;
+        fi = (double)S::ld(F(si) + k);
+        fib = (double)S::ld(F(sib) + k);
+        fi1 = (double)S::ld(F(si) + k1);
+        fib1 = (double)S::ld(F(sib) + k1);
+        fi2 = (double)S::ld(F(si) + k2);
+        if (i <= 4) {
+            gi = (double)S::ld(F(9 + si) + k);
+            gib = (double)S::ld(F(9 + sib) + k);
+            gi1 = (double)S::ld(F(9 + si) + k1);
+        }
+    } else {
+        int sl;
+        size_t at;
+        at = pushed_at(lp, x, y, i, sl);
+        fi = (double)S::ld(F(sl) + at);
+        if (i <= 4) gi = (double)S::ld(F(9 + sl) + at);
+        at = pushed_at(lp, x, y, ib, sl);
+        fib = (double)S::ld(F(sl) + at);
+        if (i <= 4) gib = (double)S::ld(F(9 + sl) + at);
+        fi1 = fi;
+        fib1 = fib;
+        fi2 = fi;
+        if (in1) {
+            at = pushed_at(lp, x1, y1, i, sl);
+            fi1 = (double)S::ld(F(sl) + at);
+            if (i <= 4) gi1 = (double)S::ld(F(9 + sl) + at);
+            at = pushed_at(lp, x1, y1, ib, sl);
+            fib1 = (double)S::ld(F(sl) + at);
+        }
+        if (in2) {
+            at = pushed_at(lp, x2, y2, i, sl);
+            fi2 = (double)S::ld(F(sl) + at);
+        }
     }
     const bool have1 = in1 && o1 == -1;
     const bool have2 = have1 && in2 && o2 == -1;
@@ -235,11 +267,16 @@ __device__ __forceinline__ void link_pass_link(const RunStep& rs, const PState& 
     const double w9i = i <= 4 ? 1.0 / 9.0 : 1.0 / 36.0;
     const double wall = 6.0 * w9i * lp.rho0 * (-(ex * uwx) - ey * uwy);
     const double fnew = bouzidi(q, fi, fi1, fi2, fib, fib1, have1, have2, wall);
+    // f_ibar(x_f) goes where the next lattice kernel reads it: slot ibar of
+    // the solid node x_f + e_i (two sets), slot i there (in place, before
+    // the odd kernel), slot ibar of x_f itself (in place, before the even one)
     const size_t kb = (size_t)(y + ey) * pitch + col_of(x + ex, lp);   // a node of P
-    S::st(Fw(ib) + kb, (typename S::R)fnew);
+    const size_t ko = lay == 2 ? k : kb;
+    const int so = lay == 1 ? i : ib;
+    S::st(Fw(so) + ko, (typename S::R)fnew);
     if (i <= 4) {
         const double gnew = thermal_link(q, gi, gi1, gib, have1, lp.w5_k, lp.particle_T - lp.T_sh);
-        S::st(Fw(9 + ib) + kb, (typename S::R)gnew);
+        S::st(Fw(9 + so) + ko, (typename S::R)gnew);
     }
     // Eq. (13) on full populations (stored value + rest part w rho0)
     const double shf = S::shifted ? lp.rho0 : 0.0;
@@ -604,12 +641,14 @@ __device__ __forceinline__ void mask_body(const RunStep& rs, unsigned bid) {
 // index); pre-collision f at x + m e_c (m = 1..3, nodes fluid at t_n and
 // t_n+1) rebuilt by pulling from A; Eq. (16) extrapolation (lower order when
 // fewer points are fluid, equilibrium at rho0 with none); momentum set so
-// that u = u_w; g = g^eq(T_w, u_w) (Eq. (17)); then collided into B.  The
-// node is skipped unless p owned it at t_n and it is fluid at t_n+1.
+// that u = u_w; g = g^eq(T_w, u_w) (Eq. (17)); then collided: the node's
+// post-collision values of t_n+1 in s, t.  Returns false (nothing to
+// refill) unless p owned the node at t_n and it is fluid at t_n+1.  lay:
+// the layout of A (0 two sets, 1 in place reversed, 2 in place pushed).
 template <int MODE>
-__device__ void refill_node(const Pops<ST<MODE>>& A, const Pops<ST<MODE>>& B, const PT_GLOBAL int32_t* Ocur,
+__device__ bool refill_node(const Pops<ST<MODE>>& A, int lay, const PT_GLOBAL int32_t* Ocur,
                             const PT_GLOBAL int32_t* Onext, const PState& P, const Shape& sh, int p, int x,
-                            int y, const LP& lp) {
+                            int y, const LP& lp, typename Store<MODE>::R (&s)[9], typename Store<MODE>::R (&t)[5]) {
     using S = Store<MODE>;
     using R = typename S::R;
     const size_t k0 = (size_t)y * lp.pitch + x;
@@ -647,13 +686,14 @@ __device__ void refill_node(const Pops<ST<MODE>>& A, const Pops<ST<MODE>>& B, co
             const size_t km = (size_t)ys[m] * lp.pitch + xs[m];
             fl[m] = Ocur[km] == -1 && Onext[km] == -1;
             R tt[5];
-            pull_node<S>(A, lp, xs[m], ys[m], sm[m], tt);
+            if (lay == 0) pull_node<S>(A, lp, xs[m], ys[m], sm[m], tt);
+            else if (lay == 1) pull_node<S>(opp_view(A), lp, xs[m], ys[m], sm[m], tt);
+            else pull_node_pushed<S>(A, lp, xs[m], ys[m], sm[m], tt);
         }
     }
-    if (!mine) return;
+    if (!mine) return false;
     const int K = !fl[0] ? 0 : (!fl[1] ? 1 : (!fl[2] ? 2 : 3));
     const double uwx = P.ux - P.om * dy, uwy = P.uy + P.om * dx;
-    R s[9], t[5];
     if (K == 3) {
         for (int a = 0; a < 9; ++a) s[a] = (R)3 * sm[0][a] - (R)3 * sm[1][a] + sm[2][a];
     } else if (K == 2) {
@@ -679,13 +719,21 @@ __device__ void refill_node(const Pops<ST<MODE>>& A, const Pops<ST<MODE>>& B, co
     const CC<R> cc(lp);
     R r_, u_, v_, T_;
     collide<R>(cc, s, t, r_, u_, v_, T_);
-    store_node<S>(B, lp, k0, s, t);
+    return true;
 }
 
 // Refill of particle p's newborn nodes, one wavefront per particle and one
-// lane per candidate from k_mask_mark.
-template <int MODE>
+// lane per candidate from k_mask_mark.  Two sets: after the lattice kernel,
+// pulling from A and storing into B.  In place the lattice kernel overwrites
+// what the stencil pulls read, so the refill is split: REFILL_COMPUTE runs
+// before it (the refilled post-collision values of each candidate into
+// rbuf, 16 doubles: 14 values and a flag), REFILL_STORE after it (into the
+// node's slots of the new state's layout).
+enum RefillPart { REFILL_TWO_SETS = 0, REFILL_COMPUTE, REFILL_STORE };
+template <int MODE, int PART>
 __device__ __forceinline__ void refill_body(const RunStep& rs, unsigned bid) {
+    using S = Store<MODE>;
+    using R = typename S::R;
     const LP& lp = rs.lp;
     const int lane = threadIdx.x & 63;
     const int p = (int)bid * 4 + (threadIdx.x >> 6);
@@ -694,12 +742,33 @@ __device__ __forceinline__ void refill_body(const RunStep& rs, unsigned bid) {
     const unsigned n = min(gl(rs.ncand)[p], ccap);
     if (n == 0) return;
     const Pops<ST<MODE>> A = pops_of<MODE>(rs.A), B = pops_of<MODE>(rs.B);
+    PT_GLOBAL double* buf = gl(rs.rbuf);
     const PState P1 = ld_state(rs.Pn + p);
     const Shape sh = shape_of(P1);
     for (unsigned i = lane; i < n; i += 64) {
         const unsigned code = gl(rs.cand)[(size_t)p * ccap + i];
-        refill_node<MODE>(A, B, gl(rs.Ocur), gl(rs.Onext), P1, sh, p, (int)(code & 0xffffu), (int)(code >> 16),
-                          lp);
+        const int x = (int)(code & 0xffffu), y = (int)(code >> 16);
+        const size_t slot = ((size_t)p * ccap + i) * 16;
+        R s[9], t[5];
+        if (PART == REFILL_STORE) {
+            if (buf[slot + 14] == 0.0) continue;
+            for (int a = 0; a < 9; ++a) s[a] = (R)buf[slot + a];
+            for (int a = 0; a < 5; ++a) t[a] = (R)buf[slot + 9 + a];
+            if (rs.parity == 0) store_node_pushed<S>(A, lp, x, y, s, t);   // the odd kernel ran
+            else store_node<S>(opp_view(A), lp, (size_t)y * lp.pitch + x, s, t);
+            continue;
+        }
+        const int lay = lp.aa ? 1 + rs.parity : 0;
+        const bool mine = refill_node<MODE>(A, lay, gl(rs.Ocur), gl(rs.Onext), P1, sh, p, x, y, lp, s, t);
+        if (PART == REFILL_TWO_SETS) {
+            if (mine) store_node<S>(B, lp, (size_t)y * lp.pitch + x, s, t);
+        } else {
+            if (mine) {
+                for (int a = 0; a < 9; ++a) buf[slot + a] = (double)s[a];
+                for (int a = 0; a < 5; ++a) buf[slot + 9 + a] = (double)t[a];
+            }
+            buf[slot + 14] = mine ? 1.0 : 0.0;
+        }
     }
 }
 
@@ -744,12 +813,12 @@ __global__ __launch_bounds__(256) void k_mask_mark_b(const RunStep* __restrict__
     mask_body(tab[m.x], m.y);
 }
 
-template <int MODE>
-__global__ __launch_bounds__(256) void k_refill(RunStep rs) { refill_body<MODE>(rs, blockIdx.x); }
-template <int MODE>
+template <int MODE, int PART>
+__global__ __launch_bounds__(256) void k_refill(RunStep rs) { refill_body<MODE, PART>(rs, blockIdx.x); }
+template <int MODE, int PART>
 __global__ __launch_bounds__(256) void k_refill_b(const RunStep* __restrict__ tab, const uint2* __restrict__ bmap) {
     const uint2 m = bmap[blockIdx.x];
-    refill_body<MODE>(tab[m.x], m.y);
+    refill_body<MODE, PART>(tab[m.x], m.y);
 }
 
 __global__ void k_link_q(const PState* __restrict__ Pc, const uint2* __restrict__ links, int n, int32_t* node,
@@ -803,9 +872,20 @@ hipError_t launch_step(int k, const RunStep& R, int mode, hipStream_t st) {
             break;
         case SK_PASS: PTLBM_DISPATCH(mode, (k_link_pass<M><<<nb, PASS_BLOCK, 0, st>>>(R))); break;
         case SK_PARTICLES: k_particles<<<nb, 256, 0, st>>>(R); break;
-        case SK_MASK: k_mask_mark<<<nb, 256, 0, st>>>(R); break;
+        case SK_MASK:   // in place, the refill is computed here, before the lattice kernel
+            k_mask_mark<<<nb, 256, 0, st>>>(R);
+            if (R.lp.aa) {
+                PTLBM_DISPATCH(mode, (k_refill<M, REFILL_COMPUTE><<<nb, 256, 0, st>>>(R)));
+            }
+            break;
         case SK_LATTICE: return launch_lattice(R, mode, nb, st);
-        case SK_REFILL: PTLBM_DISPATCH(mode, (k_refill<M><<<nb, 256, 0, st>>>(R))); break;
+        case SK_REFILL:
+            if (R.lp.aa) {
+                PTLBM_DISPATCH(mode, (k_refill<M, REFILL_STORE><<<nb, 256, 0, st>>>(R)));
+            } else {
+                PTLBM_DISPATCH(mode, (k_refill<M, REFILL_TWO_SETS><<<nb, 256, 0, st>>>(R)));
+            }
+            break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -820,9 +900,20 @@ hipError_t launch_step_batch(int k, const BatchLaunch& b, hipStream_t st) {
         case SK_COLLECT: k_links_b<<<nb, 64 * b.ppb, b.lds, st>>>(b.tab_next, bm, b.ppb); break;
         case SK_PASS: PTLBM_DISPATCH(b.mode, (k_link_pass_b<M><<<nb, PASS_BLOCK, 0, st>>>(b.tab, bm))); break;
         case SK_PARTICLES: k_particles_b<<<nb, 256, 0, st>>>(b.tab, bm); break;
-        case SK_MASK: k_mask_mark_b<<<nb, 256, 0, st>>>(b.tab, bm); break;
-        case SK_LATTICE: return launch_lattice_batch(b.tab, bm, nb, b.mode, st);
-        case SK_REFILL: PTLBM_DISPATCH(b.mode, (k_refill_b<M><<<nb, 256, 0, st>>>(b.tab, bm))); break;
+        case SK_MASK:
+            k_mask_mark_b<<<nb, 256, 0, st>>>(b.tab, bm);
+            if (b.aa) {
+                PTLBM_DISPATCH(b.mode, (k_refill_b<M, REFILL_COMPUTE><<<nb, 256, 0, st>>>(b.tab, bm)));
+            }
+            break;
+        case SK_LATTICE: return launch_lattice_batch(b.tab, bm, nb, b.mode, b.aa, st);
+        case SK_REFILL:
+            if (b.aa) {
+                PTLBM_DISPATCH(b.mode, (k_refill_b<M, REFILL_STORE><<<nb, 256, 0, st>>>(b.tab, bm)));
+            } else {
+                PTLBM_DISPATCH(b.mode, (k_refill_b<M, REFILL_TWO_SETS><<<nb, 256, 0, st>>>(b.tab, bm)));
+            }
+            break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -119,6 +119,7 @@ int build(Batch& b, lbm_sim* const* runs, int n, lbm_sim* herr) {
         L.ppb = ppb;
         L.lds = links_block_lds(maxwin, ppb);
         L.mode = b.mode;
+        L.aa = runs[0]->d.lp.aa != 0;
     }
     return LBM_OK;
 }
@@ -257,6 +258,8 @@ extern "C" int lbm_step_many(lbm_handle* hs, int32_t count, const int32_t* nstep
         if (nsteps[i] < 0) return fail(h0, LBM_EINVAL, "lbm_step_many: negative step count at %d", i);
         if (hs[i]->d.mode != h0->d.mode)
             return fail(h0, LBM_EINVAL, "lbm_step_many: runs of one call must share the storage mode");
+        if (hs[i]->d.lp.aa != h0->d.lp.aa)
+            return fail(h0, LBM_EINVAL, "lbm_step_many: runs of one call must share the streaming layout");
         if (hs[i]->d.lp.direct)
             return fail(h0, LBM_EINVAL, "lbm_step_many: direct link addressing is for single runs only");
     }

@@ -19,7 +19,8 @@ struct Layout {
     size_t npitched = 0, array_stride = 0, state_bytes = 0;
     size_t off_S[2] = {0, 0}, off_O[2] = {0, 0}, off_P = 0, off_Fh = 0, off_Fa = 0, off_seg = 0,
            off_links = 0, off_lscratch = 0, off_counter = 0, off_status = 0, off_bins[2] = {0, 0},
-           off_bcnt[2] = {0, 0}, off_cand = 0, off_ncand = 0, total = 0;
+           off_bcnt[2] = {0, 0}, off_cand = 0, off_ncand = 0, off_rbuf = 0, off_fscratch = 0, total = 0;
+    int field_rows = 0;   // rows per chunk of the field upload / read-back scratch
     int nwin = 0;
     size_t link_cap = 0;
     int ncx = 1, ncy = 1;
@@ -35,9 +36,10 @@ struct lbm_sim {
     bool own_stream = false;
     hipStream_t side = nullptr;  // particle kernels, concurrent with the lattice kernel
     hipEvent_t ev_fork = nullptr, ev_side = nullptr;
+    hipEvent_t ev_mask = nullptr;  // in place: the owner map and refill values of t_n+1 are ready
     char* base = nullptr;
     bool own_mem = false;
-    int cur = 0;         // time level holding the current (post-collision) state
+    int cur = 0;         // time level holding the current (post-collision) state; in place its parity
     int ring = 0;        // particle slot of the current time level
     int bin_parity = 0;  // cell grid holding the particles of the current time level
     int np = 0;

@@ -27,6 +27,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "lbm.h")
 
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_ESEED, LBM_EUNSTABLE, LBM_ESTATE = 0, -1, -2, -3, -4, -5, -6
 STORE = {"f64": 0, "f32": 1, "shift_f32": 2, "shift_f16": 3, "shift_bf16": 4}
+STREAMING = {"two_sets": 0, "in_place": 1}
 LBM_LINKS_INDIRECT, LBM_LINKS_DIRECT = 0, 1
 PHASES = ("links", "particles", "mask", "lattice", "refill", "collect")
 
@@ -41,7 +42,7 @@ class LbmParams(ctypes.Structure):
         ("sT_e", _d), ("sT_p", _d), ("wall_T", _d * 2), ("wall_ux", _d * 2), ("T_fluid0", _d),
         ("particle_T", _d), ("rho_ratio", _d), ("repulsion", _i), ("rep_eps", _d),
         ("rep_range", _d), ("T_shift", _d), ("max_particles", _i), ("max_diameter", _d),
-        ("side_T", _d * 2),
+        ("side_T", _d * 2), ("streaming", _i),
     ]
 
 
@@ -119,6 +120,8 @@ def lbm_params_default(**overrides):
             getattr(p, k)[0], getattr(p, k)[1] = float(v[0]), float(v[1])
         elif k == "storage" and isinstance(v, str):
             p.storage = STORE[v]
+        elif k == "streaming" and isinstance(v, str):
+            p.streaming = STREAMING[v]
         elif not hasattr(p, k):
             raise KeyError(k)
         else:

@@ -19,16 +19,18 @@ def test_every_declared_function_is_exported():
 
 
 def test_abi_version_and_defaults():
-    assert lbm.lbm_abi_version() == 2
+    assert lbm.lbm_abi_version() == 3
     p = lbm.lbm_params_default()
-    assert (p.abi_version, p.nx, p.ny, p.periodic_x, p.periodic_y, p.storage) == (2, 64, 64, 1, 0, 0)
+    assert (p.abi_version, p.nx, p.ny, p.periodic_x, p.periodic_y, p.storage) == (3, 64, 64, 1, 0, 0)
+    assert p.streaming == lbm.STREAMING["two_sets"]
     assert (p.rho0, p.a_T, p.rep_eps, p.rep_range, p.repulsion) == (1.0, -2.0, 1e-3, 3.0, 1)
     assert tuple(p.side_T) == (0.0, 0.0)
 
 
 def test_params_struct_matches_the_header_layout():
-    # side_T is the last field: its offset is the size of every field before it
-    assert lbm.LbmParams.side_T.offset == 232 and ctypes.sizeof(lbm.LbmParams) == 248
+    # the offsets of the fields added last, as the C compiler lays them out
+    assert lbm.LbmParams.side_T.offset == 232 and lbm.LbmParams.streaming.offset == 248
+    assert ctypes.sizeof(lbm.LbmParams) == 256
 
 
 @pytest.mark.parametrize("bad", [dict(nx=4), dict(ny=70000), dict(periodic_x=2), dict(storage=9),
@@ -38,7 +40,8 @@ def test_params_struct_matches_the_header_layout():
                                  dict(max_particles=10, max_diameter=12.0, periodic_y=1),
                                  dict(nx=16, max_particles=10, max_diameter=14.0),
                                  dict(gravity=float("inf")), dict(abi_version=7),
-                                 dict(abi_version=1), dict(periodic_x=0, side_T=(float("nan"), 0.0))])
+                                 dict(abi_version=2), dict(periodic_x=0, side_T=(float("nan"), 0.0)),
+                                 dict(streaming=2)])
 def test_invalid_parameters_rejected_on_the_host(bad):
     p = lbm.lbm_params_default(**bad)
     assert lbm.lbm_bytes_required(p) == 0
@@ -46,6 +49,14 @@ def test_invalid_parameters_rejected_on_the_host(bad):
         lbm.lbm_create(p)
     assert e.value.rc == lbm.LBM_EINVAL
     assert lbm.lbm_last_error()
+
+
+def test_in_place_streaming_halves_the_population_memory():
+    kw = dict(nx=4000, ny=4000, max_particles=4800, max_diameter=20.0)
+    two = lbm.lbm_bytes_required(lbm.lbm_params_default(**kw))
+    one = lbm.lbm_bytes_required(lbm.lbm_params_default(streaming="in_place", **kw))
+    pops = 14 * 4000 * 4096 * 8
+    assert two - one > 0.85 * pops and one < 0.6 * two
 
 
 def test_bytes_required_grows_with_the_lattice_and_storage():
