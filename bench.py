@@ -156,11 +156,11 @@ def paper_workload(steps, warmup, storage):
                 paper_hardware="NVIDIA A100 40 GB (named for the paper's cluster), precision not stated")
 
 
-def serving(n_req, budget_gib, chunk):
+def serving(n_req, budget_gib, chunk, streaming="two_sets"):
     import lbm_inputs
     from paper_2308_16597_amd import serve
     reqs = lbm_inputs.serving_requests(n_req, seed=4)
-    srv = serve.Server(int(budget_gib * (1 << 30)), storage="shift_bf16", chunk=chunk)
+    srv = serve.Server(int(budget_gib * (1 << 30)), storage="shift_bf16", chunk=chunk, streaming=streaming)
     t0 = time.perf_counter()
     prog = lambda k, n: log(f"[bench] serving: {k}/{n} requests done")  # noqa: E731
     closed = srv.run(reqs, np.zeros(n_req), prog)
@@ -173,6 +173,7 @@ def serving(n_req, budget_gib, chunk):
     s = serve.summarize(opened, time.perf_counter() - t0)
     log(f"[bench] serving open loop at {lam:.2f} req/s: {s}")
     return dict(requests=n_req, budget_gib=budget_gib, storage="shift_bf16", chunk_steps=chunk,
+                streaming=streaming,
                 closed_loop=dict(wall_s=round(closed_sum["wall_s"], 3),
                                  req_per_s=round(closed_sum["req_per_s"], 3),
                                  mlups=round(closed_sum["mlups"], 1), failed=closed_sum["failed"]),
@@ -217,6 +218,7 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--serve-budget-gib", type=float, default=2.0)
     ap.add_argument("--serve-chunk", type=int, default=120)
+    ap.add_argument("--serve-streaming", default="two_sets", choices=["two_sets", "in_place"])
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path "
@@ -309,7 +311,8 @@ def main():
     if args.workload == "paper_scale" and not args.no_paper_workload:
         out["paper_workload"] = paper_workload(args.paper_steps, 20, args.storage)
     if not args.no_serve:
-        out["serving"] = serving(args.serve_requests, args.serve_budget_gib, args.serve_chunk)
+        out["serving"] = serving(args.serve_requests, args.serve_budget_gib, args.serve_chunk,
+                                 args.serve_streaming)
     if not args.no_cpu_baseline:
         log(f"[bench] cpu baseline: oracle, {args.cpu_steps} steps")
         out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_steps)

@@ -203,6 +203,7 @@ void fill_lp(lbm_sim* h) {
     lp.link_cap = (int)h->L.link_cap;
     lp.direct = 0;
     lp.aa = p.streaming == LBM_STREAM_IN_PLACE ? 1 : 0;
+    lp.lpp = lanes_per_particle(h->L.nwin, 0);
     lp.ncx = h->L.ncx;
     lp.ncy = h->L.ncy;
     lp.ncells = p.max_particles > 0 ? h->L.ncx * h->L.ncy : 0;
@@ -625,6 +626,7 @@ int set_particles_rows(lbm_handle h, int32_t n, const double* rows, int cols) {
     h->np = n;
     h->generation += 1;
     d.lp.np = n;
+    d.lp.lpp = lanes_per_particle(h->L.nwin, n);
     h->cur = 0;
     h->ring = 0;
     h->bin_parity = 0;

@@ -95,6 +95,7 @@ struct LP {
     int link_cap;
     int direct;                        // link pass by direct addressing (ablation)
     int aa;                            // in-place (AA) streaming in one population set
+    int lpp;                           // lanes per particle of the per-particle kernels (64, 256)
     int ncx, ncy, ncells;              // neighbour-search cell grid
 };
 

@@ -76,8 +76,7 @@ struct BatchLaunch {
     const RunStep* tab_next;
     const uint2* bmap[GC_COUNT];
     unsigned nblk[GC_COUNT];
-    int ppb;                     // particles per block of the link collection
-    size_t lds;                  // its dynamic LDS bytes
+    size_t lds;                  // dynamic LDS bytes of the link collection's blocks
     int mode;
     bool aa;                     // every run of the batch streams in place
 };
@@ -91,11 +90,13 @@ enum StatusBits : unsigned {
     ST_CAND_OVERFLOW = 32u, // more newborn nodes for one particle than its candidate list holds
 };
 
-// Blocks one run needs for a kernel of class c (ppb: particles per block of
-// the link collection).
-unsigned run_blocks(int c, const LP& lp, int ppb);
-int links_particles_per_block(int nwin);
-size_t links_block_lds(int nwin, int ppb);
+// Blocks one run needs for a kernel of class c.  The per-particle kernels
+// give each particle a wavefront (4 per block), or the whole block of 256
+// (lp.lpp) when its window is 32 nodes wide or more and there are at most
+// 1024 particles.
+unsigned run_blocks(int c, const LP& lp);
+int lanes_per_particle(int nwin, int np);
+size_t links_block_lds(const LP& lp);
 
 hipError_t launch_step(int k, const RunStep& R, int mode, hipStream_t st);
 // The lattice kernel alone (lattice.hip), for one run or batched (two-set

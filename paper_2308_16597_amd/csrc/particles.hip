@@ -41,17 +41,66 @@ constexpr double kPi = 3.14159265358979323846;
 constexpr int OUTSIDE = -2;
 
 // ----------------------------------------------------- particle kernels ----
-// The per-particle kernels run one wavefront per particle (PPB particles per
-// block) so that a particle's window, slots, neighbours and newborn nodes
-// stay inside one wavefront and need no block-wide barrier.
+// The per-particle kernels run one wavefront per particle (4 particles per
+// block), so that a particle's window, slots, neighbours and newborn nodes
+// stay inside one wavefront and need no block-wide barrier; particles whose
+// windows are 32 nodes wide or more get the whole block of 256 lanes when
+// there are few of them (lp.lpp), with block barriers between the phases.
 
 __device__ __forceinline__ bool in_rows(int y, const LP& lp) { return y >= 0 && y < lp.ny; }
+
+// Lanes of one particle: a wavefront (4 particles per block of 256) or, for
+// particles whose windows are large (lp.lpp == 256), the whole block.
+struct PartLanes {
+    int p;       // particle
+    int lane;    // lane within the particle's lanes
+    int nl;      // lanes per particle
+    bool blk;    // the block is the particle's
+};
+__device__ __forceinline__ PartLanes part_lanes(const LP& lp, unsigned bid) {
+    PartLanes q;
+    q.blk = lp.lpp > 64;
+    q.nl = q.blk ? 256 : 64;
+    q.lane = q.blk ? (int)threadIdx.x : (int)(threadIdx.x & 63);
+    q.p = q.blk ? (int)bid : (int)bid * 4 + (int)(threadIdx.x >> 6);
+    return q;
+}
 
 // Orders the LDS accesses of the lanes of one wavefront.
 __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+// ... of a particle's lanes (the block in block mode; every lane of the
+// block must reach it).
+__device__ __forceinline__ void part_sync(bool blk) {
+    if (blk) __syncthreads();
+    else wave_lds_sync();
+}
+// Compaction step over the particle's lanes: v is this lane's flag; returns
+// the number of flagged lanes before it (in lane order) and sets total.
+// In block mode every lane of the block takes part.
+__device__ __forceinline__ unsigned part_prefix(bool v, bool blk, unsigned& total) {
+    __shared__ unsigned wcnt[4];
+    const unsigned long long m = __ballot(v);
+    const unsigned wl = threadIdx.x & 63;
+    const unsigned mine = (unsigned)__popcll(m & ((1ull << wl) - 1ull));
+    if (!blk) {
+        total = (unsigned)__popcll(m);
+        return mine;
+    }
+    const int w = (int)(threadIdx.x >> 6);
+    if (wl == 0) wcnt[w] = (unsigned)__popcll(m);
+    __syncthreads();
+    unsigned before = 0, all = 0;
+    for (int j = 0; j < 4; ++j) {
+        before += j < w ? wcnt[j] : 0u;
+        all += wcnt[j];
+    }
+    __syncthreads();   // wcnt is reused by the next step
+    total = all;
+    return before + mine;
 }
 
 // The fixed link mapping of Sec. 3: a particle's window of nxw x nyw nodes
@@ -105,7 +154,7 @@ __host__ __device__ inline size_t links_wave_lds(int nwin) {
 //      count within the wavefront);
 //  (c) the list goes to the particle's fixed segment of the link array,
 //      12 N - 12 entries from p (12 N - 12): no atomics between particles.
-__device__ __forceinline__ void links_body(const RunStep& rs, unsigned bid, int ppb) {
+__device__ __forceinline__ void links_body(const RunStep& rs, unsigned bid) {
     extern __shared__ uint2 smem[];
     const LP& lp = rs.lp;
     const PT_GLOBAL int32_t* __restrict__ Ocur = gl(rs.Ocur);
@@ -113,9 +162,10 @@ __device__ __forceinline__ void links_body(const RunStep& rs, unsigned bid, int 
     uint2* links = rs.links;
     int2* seg = rs.seg;
     unsigned* status = rs.status;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int p = (int)bid * ppb + w;
-    const bool have_p = w < ppb && p < lp.np;
+    const PartLanes pl = part_lanes(lp, bid);
+    const int lane = pl.lane, nl = pl.nl, p = pl.p;
+    const int w = pl.blk ? 0 : (int)(threadIdx.x >> 6);   // the particle's LDS area in the block
+    const bool have_p = p < lp.np;
     const int pitch = lp.pitch;
 
     const size_t wl = links_wave_lds(lp.nwin) / sizeof(uint2);
@@ -135,24 +185,24 @@ __device__ __forceinline__ void links_body(const RunStep& rs, unsigned bid, int 
     if (ok) {
         const int nw = wn.nxw * wn.nyw;
         const int nslots = 6 * (wn.nxw + wn.nyw) - 12;
-        for (int base = 0; base < nw; base += 8 * 64) {   // 8 loads in flight per lane
+        for (int base = 0; base < nw; base += 8 * nl) {   // 8 loads in flight per lane
             int v[8];
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
-                const int idx = base + u * 64 + lane;
+                const int idx = base + u * nl + lane;
                 const int b = idx / wn.nxw, a = idx - b * wn.nxw;
                 const int yy = wn.y0 + b, xx = col_of(wn.x0 + a, lp);
                 v[u] = (idx < nw && in_rows(yy, lp) && xx >= 0) ? Ocur[(size_t)yy * pitch + xx] : OUTSIDE;
             }
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
-                const int idx = base + u * 64 + lane;
+                const int idx = base + u * nl + lane;
                 if (idx < nw) win[idx] = v[u];
             }
         }
-        for (int s = lane; s < nslots; s += 64) slot[s] = 0xffffffffu;
-        wave_lds_sync();
-        for (int idx = lane; idx < nw; idx += 64) {
+        for (int s = lane; s < nslots; s += nl) slot[s] = 0xffffffffu;
+        part_sync(pl.blk);
+        for (int idx = lane; idx < nw; idx += nl) {
             const int b = idx / wn.nxw, a = idx - b * wn.nxw;
             if (win[idx] != -1) continue;
             const unsigned code = (unsigned)col_of(wn.x0 + a, lp) | ((unsigned)(wn.y0 + b) << 16);
@@ -163,23 +213,24 @@ __device__ __forceinline__ void links_body(const RunStep& rs, unsigned bid, int 
                 if (win[tb * wn.nxw + ta] == p) slot[link_slot(d, a, b, wn.nxw, wn.nyw)] = code;
             }
         }
-        wave_lds_sync();
-        for (int s0 = 0; s0 < nslots; s0 += 64) {
+        part_sync(pl.blk);
+        for (int s0 = 0; s0 < nslots; s0 += nl) {
             const int s = s0 + lane;
             const unsigned code = s < nslots ? slot[s] : 0xffffffffu;
             const bool v = code != 0xffffffffu;
-            const unsigned long long m = __ballot(v);
+            unsigned total;
+            const unsigned before = part_prefix(v, pl.blk, total);
             if (v) {
                 const unsigned d = (unsigned)slot_direction(s, wn.nxw, wn.nyw);
-                lk[count + __popcll(m & ((1ull << lane) - 1ull))] = make_uint2(code, d | ((unsigned)p << 4));
+                lk[count + before] = make_uint2(code, d | ((unsigned)p << 4));
             }
-            count += (unsigned)__popcll(m);
+            count += total;
         }
-        wave_lds_sync();
+        part_sync(pl.blk);
     }
     if (!have_p) return;
     const size_t start = (size_t)p * links_slots(lp.nwin);
-    for (unsigned i = lane; i < count; i += 64) st_u2(links + start + i, lk[i]);
+    for (unsigned i = lane; i < count; i += nl) st_u2(links + start + i, lk[i]);
     if (lane == 0) st_i2(seg + p, make_int2((int)start, (int)count));
 }
 
@@ -420,8 +471,8 @@ __device__ __forceinline__ void particles_body(const RunStep& rs, unsigned bid) 
     const PT_GLOBAL unsigned* __restrict__ bins_cur = gl(rs.bins_cur);
     const PT_GLOBAL unsigned* __restrict__ cnt_cur = gl(rs.cnt_cur);
     unsigned* status = rs.status;
-    const int lane = threadIdx.x & 63;
-    const int p = (int)bid * 4 + (threadIdx.x >> 6);
+    const PartLanes pl = part_lanes(lp, bid);
+    const int p = pl.p;
     if (p >= lp.np) return;
     {   // the owner-map buffer that will hold t_n+1 still holds t_n-1: clear
         // this particle's marks there (its window at t_n-1)
@@ -429,12 +480,14 @@ __device__ __forceinline__ void particles_body(const RunStep& rs, unsigned bid) 
         const Win wo = window_of(po);
         PT_GLOBAL int32_t* Onext = gl(rs.Onext);
         if (particle_ok(po, lp) && wo.nxw <= lp.nwin && wo.nyw <= lp.nwin)
-            for (int idx = lane; idx < wo.nxw * wo.nyw; idx += 64) {
+            for (int idx = pl.lane; idx < wo.nxw * wo.nyw; idx += pl.nl) {
                 const int b = idx / wo.nxw, a = idx - b * wo.nxw;
                 const int yy = wo.y0 + b, xx = col_of(wo.x0 + a, lp);
                 if (in_rows(yy, lp) && xx >= 0) Onext[(size_t)yy * lp.pitch + xx] = -1;
             }
     }
+    if (threadIdx.x >= 64 && pl.blk) return;   // the rest on the first wavefront
+    const int lane = threadIdx.x & 63;
     const PState P = ld_state(Pc + p);
     const Shape sh = shape_of(P);
     PT_GLOBAL double* Fa = gl(rs.Fa);
@@ -567,12 +620,12 @@ __device__ __forceinline__ void mask_body(const RunStep& rs, unsigned bid) {
     PT_GLOBAL unsigned* cand = gl(rs.cand);
     PT_GLOBAL unsigned* ncand = gl(rs.ncand);
     unsigned* status = rs.status;
-    if (rs.cnt_cur) {
-        const int nthreads = (int)(((unsigned)lp.np + 3u) / 4u * 256u);
-        for (int c = (int)bid * 256 + threadIdx.x; c < lp.ncells; c += nthreads) gl(rs.cnt_cur)[c] = 0u;
+    const PartLanes pl = part_lanes(lp, bid);
+    if (rs.cnt_cur) {   // every thread of the run's grid clears a share of the counts
+        const int nblocks = pl.blk ? lp.np : (lp.np + 3) / 4;
+        for (int c = (int)bid * 256 + threadIdx.x; c < lp.ncells; c += nblocks * 256) gl(rs.cnt_cur)[c] = 0u;
     }
-    const int lane = threadIdx.x & 63;
-    const int p = (int)bid * 4 + (threadIdx.x >> 6);
+    const int lane = pl.lane, p = pl.p;
     if (p >= lp.np) return;
     const PState P = ld_state(Pp + p);
     if (!particle_ok(P, lp)) return;
@@ -598,7 +651,7 @@ __device__ __forceinline__ void mask_body(const RunStep& rs, unsigned bid) {
     const Shape sp = shape_of(P), sq = shape_of(Q);
     unsigned nc = 0;
     const unsigned ccap = (unsigned)(4 * lp.nwin);
-    for (int base = 0; base < bw * bh; base += 64) {
+    for (int base = 0; base < bw * bh; base += pl.nl) {
         const int idx = base + lane;
         bool nb = false;
         unsigned code = 0;
@@ -620,12 +673,13 @@ __device__ __forceinline__ void mask_body(const RunStep& rs, unsigned bid) {
                 }
             }
         }
-        const unsigned long long m = __ballot(nb);
+        unsigned total;
+        const unsigned before = part_prefix(nb, pl.blk, total);
         if (nb) {
-            const unsigned at = nc + (unsigned)__popcll(m & ((1ull << lane) - 1ull));
+            const unsigned at = nc + before;
             if (at < ccap) cand[(size_t)p * ccap + at] = code;
         }
-        nc += (unsigned)__popcll(m);
+        nc += total;
     }
     if (lane == 0) {
         if (nc > ccap) {
@@ -735,8 +789,8 @@ __device__ __forceinline__ void refill_body(const RunStep& rs, unsigned bid) {
     using S = Store<MODE>;
     using R = typename S::R;
     const LP& lp = rs.lp;
-    const int lane = threadIdx.x & 63;
-    const int p = (int)bid * 4 + (threadIdx.x >> 6);
+    const PartLanes pl = part_lanes(lp, bid);
+    const int lane = pl.lane, p = pl.p;
     if (p >= lp.np) return;
     const unsigned ccap = (unsigned)(4 * lp.nwin);
     const unsigned n = min(gl(rs.ncand)[p], ccap);
@@ -745,7 +799,7 @@ __device__ __forceinline__ void refill_body(const RunStep& rs, unsigned bid) {
     PT_GLOBAL double* buf = gl(rs.rbuf);
     const PState P1 = ld_state(rs.Pn + p);
     const Shape sh = shape_of(P1);
-    for (unsigned i = lane; i < n; i += 64) {
+    for (unsigned i = lane; i < n; i += pl.nl) {
         const unsigned code = gl(rs.cand)[(size_t)p * ccap + i];
         const int x = (int)(code & 0xffffu), y = (int)(code >> 16);
         const size_t slot = ((size_t)p * ccap + i) * 16;
@@ -779,11 +833,10 @@ __device__ __forceinline__ void refill_body(const RunStep& rs, unsigned bid) {
 // tab[bmap[b].x]).  Both call the same body, so a run computes the same bits
 // alone and in a batch.
 
-__global__ __launch_bounds__(256) void k_links(RunStep rs, int ppb) { links_body(rs, blockIdx.x, ppb); }
-__global__ __launch_bounds__(256) void k_links_b(const RunStep* __restrict__ tab, const uint2* __restrict__ bmap,
-                                                 int ppb) {
+__global__ __launch_bounds__(256) void k_links(RunStep rs) { links_body(rs, blockIdx.x); }
+__global__ __launch_bounds__(256) void k_links_b(const RunStep* __restrict__ tab, const uint2* __restrict__ bmap) {
     const uint2 m = bmap[blockIdx.x];
-    links_body(tab[m.x], m.y, ppb);
+    links_body(tab[m.x], m.y);
 }
 
 template <int MODE>
@@ -838,19 +891,19 @@ __global__ void k_link_q(const PState* __restrict__ Pc, const uint2* __restrict_
 
 // -------------------------------------------------------------- launchers ----
 
-int links_particles_per_block(int nwin) {
-    const size_t per = links_wave_lds(nwin);
-    int ppb = (int)(65536 / per);
-    return ppb < 1 ? 1 : (ppb > 4 ? 4 : ppb);
-}
+// A block per particle pays off when the windows are large and there are
+// too few particles to fill the GPU with wavefronts (with thousands of
+// particles the wavefronts already do, and whole blocks would take more of
+// the GPU from the lattice kernel running beside them).
+int lanes_per_particle(int nwin, int np) { return nwin >= 32 && np <= 1024 ? 256 : 64; }
 
-size_t links_block_lds(int nwin, int ppb) { return (size_t)ppb * links_wave_lds(nwin); }
+size_t links_block_lds(const LP& lp) { return (size_t)(lp.lpp > 64 ? 1 : 4) * links_wave_lds(lp.nwin); }
 
-unsigned run_blocks(int c, const LP& lp, int ppb) {
+unsigned run_blocks(int c, const LP& lp) {
     switch (c) {
-        case GC_LINKS: return lp.np > 0 ? (unsigned)((lp.np + ppb - 1) / ppb) : 0u;
+        case GC_LINKS:
+        case GC_WAVE: return (unsigned)(lp.lpp > 64 ? lp.np : (lp.np + 3) / 4);
         case GC_PASS: return (unsigned)lp.np;   // a block per particle
-        case GC_WAVE: return (unsigned)((lp.np + 3) / 4);
         default: return (unsigned)(((size_t)lp.pitch * lp.ny + LAT_BLOCK - 1) / LAT_BLOCK);
     }
 }
@@ -859,16 +912,15 @@ hipError_t launch_step(int k, const RunStep& R, int mode, hipStream_t st) {
     if (R.lp.direct && R.lp.np > 0) {   // direct addressing: no collection, a thread per node
         if (k == SK_COLLECT) return hipSuccess;
         if (k == SK_PASS) {
-            PTLBM_DISPATCH(mode, (k_link_pass_direct<M><<<run_blocks(GC_LAT, R.lp, 1), LAT_BLOCK, 0, st>>>(R)));
+            PTLBM_DISPATCH(mode, (k_link_pass_direct<M><<<run_blocks(GC_LAT, R.lp), LAT_BLOCK, 0, st>>>(R)));
             return hipGetLastError();
         }
     }
-    const int ppb = links_particles_per_block(R.lp.nwin);
-    const unsigned nb = run_blocks(grid_class(k), R.lp, ppb);
+    const unsigned nb = run_blocks(grid_class(k), R.lp);
     if (nb == 0) return hipSuccess;
     switch (k) {
         case SK_COLLECT:   // R: the RunStep of the step whose links are collected
-            k_links<<<nb, 64 * ppb, links_block_lds(R.lp.nwin, ppb), st>>>(R, ppb);
+            k_links<<<nb, 256, links_block_lds(R.lp), st>>>(R);
             break;
         case SK_PASS: PTLBM_DISPATCH(mode, (k_link_pass<M><<<nb, PASS_BLOCK, 0, st>>>(R))); break;
         case SK_PARTICLES: k_particles<<<nb, 256, 0, st>>>(R); break;
@@ -897,7 +949,7 @@ hipError_t launch_step_batch(int k, const BatchLaunch& b, hipStream_t st) {
     if (nb == 0) return hipSuccess;
     const uint2* bm = b.bmap[c];
     switch (k) {
-        case SK_COLLECT: k_links_b<<<nb, 64 * b.ppb, b.lds, st>>>(b.tab_next, bm, b.ppb); break;
+        case SK_COLLECT: k_links_b<<<nb, 256, b.lds, st>>>(b.tab_next, bm); break;
         case SK_PASS: PTLBM_DISPATCH(b.mode, (k_link_pass_b<M><<<nb, PASS_BLOCK, 0, st>>>(b.tab, bm))); break;
         case SK_PARTICLES: k_particles_b<<<nb, 256, 0, st>>>(b.tab, bm); break;
         case SK_MASK:
@@ -923,7 +975,7 @@ hipError_t launch_mask_setup(const RunStep& R, hipStream_t st) {
     RunStep S = R;
     S.Pc = nullptr;       // no previous time level: no newborn candidates
     S.cnt_cur = nullptr;  // no cell counts to clear
-    const unsigned nb = run_blocks(GC_WAVE, S.lp, 1);
+    const unsigned nb = run_blocks(GC_WAVE, S.lp);
     if (nb == 0) return hipSuccess;
     k_mask_mark<<<nb, 256, 0, st>>>(S);
     return hipGetLastError();

@@ -79,17 +79,16 @@ int build(Batch& b, lbm_sim* const* runs, int n, lbm_sim* herr) {
         for (int j = 0; j < kCycle; ++j) b.one[j] = runstep_at(runs[0], b.key[0].state, j);
         return LBM_OK;
     }
-    int maxwin = 2;
-    for (int i = 0; i < n; ++i) maxwin = std::max(maxwin, runs[i]->d.lp.nwin);
-    const int ppb = links_particles_per_block(maxwin);
+    size_t lds = 0;
+    for (int i = 0; i < n; ++i) lds = std::max(lds, links_block_lds(runs[i]->d.lp));
     std::vector<uint2> bm[GC_COUNT];
     for (int c = 0; c < GC_COUNT; ++c) {
         size_t tot = 0;
-        for (int i = 0; i < n; ++i) tot += run_blocks(c, runs[i]->d.lp, ppb);
+        for (int i = 0; i < n; ++i) tot += run_blocks(c, runs[i]->d.lp);
         if (tot > 0x7fffffffu) return fail(herr, LBM_EINVAL, "batch grid too large");
         bm[c].reserve(tot);
         for (int i = 0; i < n; ++i) {
-            const unsigned nb = run_blocks(c, runs[i]->d.lp, ppb);
+            const unsigned nb = run_blocks(c, runs[i]->d.lp);
             for (unsigned k = 0; k < nb; ++k) bm[c].push_back(make_uint2((unsigned)i, k));
         }
     }
@@ -116,8 +115,7 @@ int build(Batch& b, lbm_sim* const* runs, int n, lbm_sim* herr) {
             L.bmap[c] = (const uint2*)(b.dev + off_bm[c]);
             L.nblk[c] = (unsigned)bm[c].size();
         }
-        L.ppb = ppb;
-        L.lds = links_block_lds(maxwin, ppb);
+        L.lds = lds;
         L.mode = b.mode;
         L.aa = runs[0]->d.lp.aa != 0;
     }

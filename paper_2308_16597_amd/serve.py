@@ -29,7 +29,7 @@ NU_MIN = 0.01
 ALIGN = 1 << 16
 
 
-def request_params(req, storage=lbm.STORE["shift_bf16"]):
+def request_params(req, storage=lbm.STORE["shift_bf16"], streaming=lbm.STREAMING["two_sets"]):
     """lbm_params of one request: hot particles (T = 1) in a cold channel,
     parameters from (H = ny, Ra, Pr 0.7, d, density ratio 1.5) at Ma 0.1."""
     phys = params.from_dimensionless(req["ny"], req["Ra"], 0.7, req["d"], 1.5)
@@ -39,7 +39,7 @@ def request_params(req, storage=lbm.STORE["shift_bf16"]):
         nx=req["nx"], ny=req["ny"], storage=storage, rho0=1.0, nu=nu, alpha=nu / 0.7,
         gravity=phys["gravity"], beta=phys["beta"], T_ref=0.0, wall_T=(0.0, 0.0), T_fluid0=0.0,
         particle_T=1.0, rho_ratio=1.5, repulsion=1, rep_eps=1e-3, rep_range=3.0, T_shift=0.0,
-        max_particles=max(req["n"], 1), max_diameter=req["d"])
+        max_particles=max(req["n"], 1), max_diameter=req["d"], streaming=streaming)
     return p, capped
 
 
@@ -87,16 +87,20 @@ class Arena(FirstFit):
 
 
 class Server:
-    def __init__(self, budget_bytes, storage="shift_bf16", chunk=120, gap=3.0):
+    """`streaming`: "two_sets" or "in_place" (one population set per run, so
+    about twice the runs fit the budget)."""
+
+    def __init__(self, budget_bytes, storage="shift_bf16", chunk=120, gap=3.0, streaming="two_sets"):
         import torch
         self.storage = lbm.STORE[storage]
+        self.streaming = lbm.STREAMING[streaming]
         self.arena = Arena(budget_bytes)
         self.chunk = int(chunk)
         self.gap = gap
         self.stream = torch.cuda.Stream()
 
     def footprint(self, req):
-        p, _ = request_params(req, self.storage)
+        p, _ = request_params(req, self.storage, self.streaming)
         return lbm.lbm_bytes_required(p)
 
     def run(self, requests, arrivals, progress=None):
@@ -118,7 +122,7 @@ class Server:
             while queue:   # first come, first served while the footprint fits
                 i = queue[0]
                 req = requests[i]
-                p, capped = request_params(req, self.storage)
+                p, capped = request_params(req, self.storage, self.streaming)
                 need = lbm.lbm_bytes_required(p)
                 if need == 0 or need > self.arena.nbytes:
                     queue.pop(0)
