@@ -243,8 +243,8 @@ __device__ __forceinline__ void links_body(const RunStep& rs, unsigned bid) {
 // x_f reads; the link's momentum exchange f_i^+ (e_i - u_w) -
 // f_ibar (e_ibar - u_w) and its torque about X_c, summed in FP64 over the
 // particle in a fixed order (each thread over its links, a butterfly in each
-// wavefront, the wavefronts in order) into Fh[p].  All gathers of a link are
-// issued before any arithmetic.
+// wavefront, the wavefronts in order) into Fh[p].  The gathers of a link
+// are issued together, after its (arithmetic-only) link fraction.
 constexpr int PASS_BLOCK = 256;
 
 // One link: fluid node (x, y), direction i towards particle P.
@@ -271,14 +271,24 @@ __device__ __forceinline__ void link_pass_link(const RunStep& rs, const PState& 
     // (two sets), slot abar at the node (in place, reversed), or slot a at
     // the node + e_a (in place, pushed; slot abar at the node at a wall)
     const int lay = lp.aa ? 1 + rs.parity : 0;
-    double fi, fib, fi1, fib1, fi2, gi = 0.0, gib = 0.0, gi1 = 0.0;
+    // q first: the two branches of Eqs. (9)-(10) read different populations
+    // (q <= 1/2: f_i at x_f, x_f - e_i, x_f - 2 e_i; q > 1/2: f_i at x_f and
+    // f_ibar at x_f, x_f - e_i), so only those are gathered
+    const double dx = min_image_x((double)x - P.x, lp);
+    const double dy = (double)y - P.y;
+    const double q = link_q_shape(sh, dx, dy, i);
+    const bool lo = q <= 0.5;
+    double fi, fib = 0.0, fi1 = 0.0, fib1 = 0.0, fi2 = 0.0, gi = 0.0, gib = 0.0, gi1 = 0.0;
     if (lay != 2) {
         const int si = lay ? ib : i, sib = lay ? i : ib;
         fi = (double)S::ld(F(si) + k);
-        fib = (double)S::ld(F(sib) + k);
-        fi1 = (double)S::ld(F(si) + k1);
-        fib1 = (double)S::ld(F(sib) + k1);
-        fi2 = (double)S::ld(F(si) + k2);
+        if (lo) {
+            fi1 = (double)S::ld(F(si) + k1);
+            fi2 = (double)S::ld(F(si) + k2);
+        } else {
+            fib = (double)S::ld(F(sib) + k);
+            fib1 = (double)S::ld(F(sib) + k1);
+        }
         if (i <= 4) {
             gi = (double)S::ld(F(9 + si) + k);
             gib = (double)S::ld(F(9 + sib) + k);
@@ -291,28 +301,24 @@ __device__ __forceinline__ void link_pass_link(const RunStep& rs, const PState& 
         fi = (double)S::ld(F(sl) + at);
         if (i <= 4) gi = (double)S::ld(F(9 + sl) + at);
         at = pushed_at(lp, x, y, ib, sl);
-        fib = (double)S::ld(F(sl) + at);
+        if (!lo) fib = (double)S::ld(F(sl) + at);
         if (i <= 4) gib = (double)S::ld(F(9 + sl) + at);
-        fi1 = fi;
-        fib1 = fib;
-        fi2 = fi;
         if (in1) {
             at = pushed_at(lp, x1, y1, i, sl);
-            fi1 = (double)S::ld(F(sl) + at);
+            if (lo) fi1 = (double)S::ld(F(sl) + at);
             if (i <= 4) gi1 = (double)S::ld(F(9 + sl) + at);
-            at = pushed_at(lp, x1, y1, ib, sl);
-            fib1 = (double)S::ld(F(sl) + at);
+            if (!lo) {
+                at = pushed_at(lp, x1, y1, ib, sl);
+                fib1 = (double)S::ld(F(sl) + at);
+            }
         }
-        if (in2) {
+        if (in2 && lo) {
             at = pushed_at(lp, x2, y2, i, sl);
             fi2 = (double)S::ld(F(sl) + at);
         }
     }
     const bool have1 = in1 && o1 == -1;
     const bool have2 = have1 && in2 && o2 == -1;
-    const double dx = min_image_x((double)x - P.x, lp);
-    const double dy = (double)y - P.y;
-    const double q = link_q_shape(sh, dx, dy, i);
     const double rx = dx + q * ex, ry = dy + q * ey;   // x_w - X_c
     const double uwx = P.ux - P.om * ry, uwy = P.uy + P.om * rx;
     const double w9i = i <= 4 ? 1.0 / 9.0 : 1.0 / 36.0;
