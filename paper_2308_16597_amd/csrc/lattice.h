@@ -315,7 +315,6 @@ __device__ __forceinline__ void store_node(const Pops<typename S::T>& B, const L
 // written by one thread only, so the update is in place.  A parity-0 state
 // is the two-set state with slots k and kbar exchanged: every reader and
 // writer of the two-set layout works on it through opp_view.
-__device__ __forceinline__ constexpr int OPP5d(int k) { return k == 0 ? 0 : ((k + 1) % 4 + 1); }
 template <class T> __host__ __device__ Pops<T> opp_view(const Pops<T>& F) {
     Pops<T> v;
     for (int i = 0; i < 9; ++i) v.f[i] = F.f[i == 0 ? 0 : (i <= 4 ? ((i + 1) % 4 + 1) : ((i - 5 + 2) % 4 + 5))];
