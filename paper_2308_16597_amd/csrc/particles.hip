@@ -5,26 +5,29 @@
 //
 // One step n -> n+1 (cur = time level n, ring = particle slot of t_n); the
 // links of t_n were collected at the end of the step before:
+// (the per-particle kernels below give a particle a wavefront, or a whole
+// block when its window is wide and the particles are few)
 //   k_link_pass     one block per particle, a thread per link: q, wall
 //                   velocity, Bouzidi bounce-back (Eqs. (9)-(10)) and the
-//                   thermal wall (Eqs. (11)-(12)) written into the solid
-//                   slots of the post-collision state; the momentum exchange
-//                   (Eqs. (13)-(14)) summed over the particle in FP64 in a
-//                   fixed order.
-//   k_particles     one wavefront per particle: clear its t_n-1 marks in the
+//                   thermal wall (Eqs. (11)-(12)) written where the lattice
+//                   kernel pulls them; the momentum exchange (Eqs. (13)-(14))
+//                   summed over the particle in FP64 in a fixed order.
+//   k_particles     per particle: clear its t_n-1 marks in the
 //                   owner-map buffer of t_n+1; repulsion (Eq. (15)) summed
 //                   in ascending partner order over a cell grid, net weight,
 //                   Newton-Euler update.
-//   k_mask_mark     one wavefront per particle: owner map of t_n+1 by atomic
+//   k_mask_mark     per particle: owner map of t_n+1 by atomic
 //                   min; newborn-node candidates.
 //   k_stream_collide  one thread per node: fused pull-stream + D2Q9/D2Q5 MRT
-//                   collision with buoyancy (Sec. 2.1) of the whole lattice.
-//   k_refill        one wavefront per particle: refilling + collision of the
-//                   newborn nodes (Sec. 2.5), over the lattice kernel's output.
-//   k_links         one wavefront per particle: the links of t_n+1 from its
+//                   collision with buoyancy (Sec. 2.1) of the whole lattice
+//                   (two kernels in place, lattice.hip).
+//   k_refill        per particle: refilling + collision of the newborn nodes
+//                   (Sec. 2.5), over the lattice kernel's output (in place:
+//                   computed before it, stored after it).
+//   k_links         per particle: the links of t_n+1 from its
 //                   owner map, collected into LDS in the fixed slot order of
-//                   Sec. 3 (one slot per lattice line and direction), wave
-//                   ballot + prefix count, compacted to the front of the
+//                   Sec. 3 (one slot per lattice line and direction), ballot
+//                   + prefix count, compacted to the front of the
 //                   particle's own segment of 12 N - 12 entries.
 // k_particles, k_mask_mark and k_links touch nothing k_stream_collide reads
 // or writes, so a single run launches them on a second stream, concurrent
@@ -133,7 +136,7 @@ __device__ __forceinline__ int slot_direction(int s, int nxw, int nyw) {
     return 5 + (s - base) / nd;
 }
 
-// LDS of one wavefront of k_links: the owner map over the window, the slot
+// LDS of one particle of k_links: the owner map over the window, the slot
 // array, then the compacted link list.  links_slots is also the length of
 // each particle's segment of the link array.
 __host__ __device__ inline size_t links_win_ints(int nwin) { return (size_t)nwin * nwin; }
@@ -145,13 +148,13 @@ __host__ __device__ inline size_t links_wave_lds(int nwin) {
     return links_list_offset(nwin) + links_slots(nwin) * sizeof(uint2);
 }
 
-// Link collection (Sec. 3) from the owner map of t_n, one wavefront per
+// Link collection (Sec. 3) from the owner map of t_n, the lanes of one
 // particle (it runs at the end of the step before, once that map is built):
 //  (a) load the window of the owner map of t_n into LDS;
 //  (b) every fluid node of the window tests its 8 neighbours in parallel; a
 //      neighbour owned by this particle is a link, written into its fixed
 //      slot; the slots are then compacted in slot order (ballot + prefix
-//      count within the wavefront);
+//      count within each wavefront, and across the wavefronts of a block);
 //  (c) the list goes to the particle's fixed segment of the link array,
 //      12 N - 12 entries from p (12 N - 12): no atomics between particles.
 __device__ __forceinline__ void links_body(const RunStep& rs, unsigned bid) {
@@ -465,7 +468,8 @@ __global__ __launch_bounds__(256) void k_bin_init(const PState* __restrict__ P, 
     if (p < lp.np) bin_insert(P[p], p, bins, cnt, status, lp);
 }
 
-// Particle update, one wavefront per particle (Sec. 2.2, 2.4):
+// Particle update, per particle (Sec. 2.2, 2.4; the repulsion and the
+// update on its first wavefront):
 //  - the momentum-exchange force and torque of the link pass, Fh[p];
 //  - repulsion: partners from the cell grid of t_n (lane = one slot of the
 //    3 x 3 cells around the particle), summed in ascending partner index (the
@@ -611,7 +615,7 @@ __device__ __forceinline__ void particles_body(const RunStep& rs, unsigned bid) 
     bin_insert(N, p, rs.bins_next, rs.cnt_next, status, lp);
 }
 
-// Owner map of t_n+1, one wavefront per particle, over the
+// Owner map of t_n+1, per particle, over the
 // union of the particle's windows at t_n and t_n+1: a node inside the disk at
 // t_n+1 gets owner = the lowest index whose disk holds it (atomic min, exact
 // solid test); a node inside the disk at t_n but not at t_n+1 is a newborn
@@ -782,7 +786,7 @@ __device__ bool refill_node(const Pops<ST<MODE>>& A, int lay, const PT_GLOBAL in
     return true;
 }
 
-// Refill of particle p's newborn nodes, one wavefront per particle and one
+// Refill of particle p's newborn nodes, the particle's lanes and one
 // lane per candidate from k_mask_mark.  Two sets: after the lattice kernel,
 // pulling from A and storing into B.  In place the lattice kernel overwrites
 // what the stencil pulls read, so the refill is split: REFILL_COMPUTE runs
