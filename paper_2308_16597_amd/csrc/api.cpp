@@ -73,6 +73,7 @@ Layout make_layout(const lbm_params& p) {
     L.off_lscratch = off;
     off = round_up(off + L.link_cap * (sizeof(uint2) + 3 * sizeof(int32_t) + sizeof(double)) + 16, kAlign);
     L.off_status = off; off = round_up(off + 64, kAlign);
+    L.off_cc = off; off = round_up(off + sizeof(CC<float>), kAlign);
     // neighbour-search cells at least 2 r_max + s wide
     const double cell = (p.max_diameter > 0 ? p.max_diameter : 2.0) + (p.rep_range > 0 ? p.rep_range : 0.0);
     L.ncx = std::max(1, (int)std::floor(p.nx / cell));
@@ -207,6 +208,7 @@ void fill_lp(lbm_sim* h) {
     lp.ncx = h->L.ncx;
     lp.ncy = h->L.ncy;
     lp.ncells = p.max_particles > 0 ? h->L.ncx * h->L.ncy : 0;
+    lp.cf = (const PT_GLOBAL CC<float>*)(h->base + h->L.off_cc);
 }
 
 int create_common(const lbm_params* p, void* dev_ptr, size_t bytes, void* stream, lbm_handle* out) {
@@ -275,6 +277,16 @@ int create_common(const lbm_params* p, void* dev_ptr, size_t bytes, void* stream
     d.ncand = (unsigned*)(h->base + L.off_ncand);
     d.rbuf = L.off_rbuf ? (double*)(h->base + L.off_rbuf) : nullptr;
     fill_lp(h);
+    {
+        const CC<float> cc = round_cc(make_cc(d.lp));
+        hipError_t e = hipMemcpy(h->base + L.off_cc, &cc, sizeof cc, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            hip_fail(h, e, "upload of the lattice constants");
+            g_create_error = h->err;
+            lbm_destroy(h);
+            return LBM_EDEVICE;
+        }
+    }
     *out = h;
     int rc = lbm_set_particles(h, 0, nullptr);
     if (rc != LBM_OK) {

@@ -31,12 +31,9 @@ template <class T> __device__ __forceinline__ PT_GLOBAL T* gl(T* p) { return (PT
 __device__ __forceinline__ float bf16_to_f32(uint16_t b) {
     return __uint_as_float(((uint32_t)b) << 16);
 }
-__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
+// Round to nearest even: gfx950 converts in one instruction
+// (v_cvt_pk_bf16_f32); a NaN stays a NaN.
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 
 template <int MODE> struct Store;
 template <> struct Store<LBM_STORE_F64> {
@@ -80,6 +77,22 @@ template <class T> struct Pops {
     PT_GLOBAL T* g[5];
 };
 
+// Collision and wall constants in the compute type R, derived in FP64 (in
+// the order the kernels would take them).  FP64 kernels derive them from
+// their arguments; FP32 arithmetic reads a copy rounded once on the host and
+// spends no instruction on them.
+template <class R> struct CC {
+    R rho0, gbeta, T_ref, body_fx;
+    R s_e, s_eps, s_q, s_nu;        // D2Q9 rates
+    R h_e, h_eps, h_q, h_nu;        // 1 - s/2 of the same rates (forcing terms)
+    R s_a, s_Te, s_Tp, a_T;         // D2Q5 rates and equilibrium constant
+    R w5_0, w5_k, T_sh;
+    R fsw[9];                       // rest state w_i rho0
+    R u_wall[2];                    // wall_ux rho0 / 6 of the moving walls [bottom, top]
+    R g_wall[2];                    // 2 w5_k (wall_T - T_sh) [bottom, top]
+    R g_side[2];                    // 2 w5_k (side_T - T_sh) [left, right]
+};
+
 // Lattice constants handed to every kernel (host-filled, FP64).
 struct LP {
     int nx, ny, pitch, periodic_x, periodic_y;   // periodic_x = 0: closed cavity
@@ -97,16 +110,87 @@ struct LP {
     int aa;                            // in-place (AA) streaming in one population set
     int lpp;                           // lanes per particle of the per-particle kernels (64, 256)
     int ncx, ncy, ncells;              // neighbour-search cell grid
+    // the constants above rounded for FP32 arithmetic, in device memory
+    // next to the run's buffers (read with scalar loads; kept out of the
+    // kernel arguments, which they would make 20 % larger)
+    const PT_GLOBAL CC<float>* cf;
 };
 
-// Collision constants in the compute type.
-template <class R> struct CC {
-    R rho0, gbeta, T_ref, body_fx, s_e, s_eps, s_q, s_nu, s_a, s_Te, s_Tp, a_T, T_sh;
-    __device__ explicit CC(const LP& p)
-        : rho0((R)p.rho0), gbeta((R)p.gbeta), T_ref((R)p.T_ref), body_fx((R)p.body_fx),
-          s_e((R)p.s_e), s_eps((R)p.s_eps), s_q((R)p.s_q), s_nu((R)p.s_nu), s_a((R)p.s_a),
-          s_Te((R)p.s_Te), s_Tp((R)p.s_Tp), a_T((R)p.a_T), T_sh((R)p.T_sh) {}
-};
+// The constants of lp for FP64 arithmetic, derived in the order the kernels
+// would take (host and device compute the same bits).
+__host__ __device__ inline CC<double> make_cc(const LP& lp) {
+    CC<double> c;
+    c.rho0 = lp.rho0;
+    c.gbeta = lp.gbeta;
+    c.T_ref = lp.T_ref;
+    c.body_fx = lp.body_fx;
+    c.s_e = lp.s_e;
+    c.s_eps = lp.s_eps;
+    c.s_q = lp.s_q;
+    c.s_nu = lp.s_nu;
+    c.h_e = 1.0 - 0.5 * lp.s_e;
+    c.h_eps = 1.0 - 0.5 * lp.s_eps;
+    c.h_q = 1.0 - 0.5 * lp.s_q;
+    c.h_nu = 1.0 - 0.5 * lp.s_nu;
+    c.s_a = lp.s_a;
+    c.s_Te = lp.s_Te;
+    c.s_Tp = lp.s_Tp;
+    c.a_T = lp.a_T;
+    c.w5_0 = lp.w5_0;
+    c.w5_k = lp.w5_k;
+    c.T_sh = lp.T_sh;
+    for (int i = 0; i < 9; ++i) c.fsw[i] = (i == 0 ? 4.0 / 9.0 : (i < 5 ? 1.0 / 9.0 : 1.0 / 36.0)) * lp.rho0;
+    for (int w = 0; w < 2; ++w) {
+        c.u_wall[w] = lp.wall_ux[w] * lp.rho0 * (1.0 / 6.0);
+        c.g_wall[w] = 2.0 * lp.w5_k * (lp.wall_T[w] - lp.T_sh);
+        c.g_side[w] = 2.0 * lp.w5_k * (lp.side_T[w] - lp.T_sh);
+    }
+    return c;
+}
+
+// The same rounded once to FP32 (on the host for lp.cf).
+__host__ __device__ inline CC<float> round_cc(const CC<double>& c) {
+    CC<float> f;
+    f.rho0 = (float)c.rho0;
+    f.gbeta = (float)c.gbeta;
+    f.T_ref = (float)c.T_ref;
+    f.body_fx = (float)c.body_fx;
+    f.s_e = (float)c.s_e;
+    f.s_eps = (float)c.s_eps;
+    f.s_q = (float)c.s_q;
+    f.s_nu = (float)c.s_nu;
+    f.h_e = (float)c.h_e;
+    f.h_eps = (float)c.h_eps;
+    f.h_q = (float)c.h_q;
+    f.h_nu = (float)c.h_nu;
+    f.s_a = (float)c.s_a;
+    f.s_Te = (float)c.s_Te;
+    f.s_Tp = (float)c.s_Tp;
+    f.a_T = (float)c.a_T;
+    f.w5_0 = (float)c.w5_0;
+    f.w5_k = (float)c.w5_k;
+    f.T_sh = (float)c.T_sh;
+    for (int i = 0; i < 9; ++i) f.fsw[i] = (float)c.fsw[i];
+    for (int w = 0; w < 2; ++w) {
+        f.u_wall[w] = (float)c.u_wall[w];
+        f.g_wall[w] = (float)c.g_wall[w];
+        f.g_side[w] = (float)c.g_side[w];
+    }
+    return f;
+}
+
+// The run's constants in the compute type R.  FP64: derived from the
+// kernel arguments where used.  FP32: one copy taken from lp.cf, before any
+// store and any divergent branch of the kernel, so that the loads are
+// scalar; the pull, collision and store helpers receive it.
+template <class R> __device__ __forceinline__ CC<R> lp_cc(const LP& lp);
+template <> __device__ __forceinline__ CC<double> lp_cc<double>(const LP& lp) { return make_cc(lp); }
+template <> __device__ __forceinline__ CC<float> lp_cc<float>(const LP& lp) { return *(const CC<float>*)lp.cf; }
+// The same values derived from the kernel arguments alone (for kernels that
+// would otherwise hold the copy in scalar registers across their stores).
+template <class R> __device__ __forceinline__ CC<R> args_cc(const LP& lp);
+template <> __device__ __forceinline__ CC<double> args_cc<double>(const LP& lp) { return make_cc(lp); }
+template <> __device__ __forceinline__ CC<float> args_cc<float>(const LP& lp) { return round_cc(make_cc(lp)); }
 
 // D2Q9 weights.
 template <class R> __device__ __forceinline__ R w9(int i) {
@@ -159,14 +243,14 @@ __device__ __forceinline__ void collide(const CC<R>& c, R (&s)[9], R (&t)[5], R&
     const R uF = ux * Fx + uy * Fy;
 
     // dm = S (m - m^eq) - (I - S/2) Fbar, moment by moment
-    const R de = c.s_e * ((e_s + (R)2 * drho) - (R)3 * rho * usq) - ((R)1 - (R)0.5 * c.s_e) * ((R)6 * uF);
-    const R deps = c.s_eps * ((eps_s - drho) + (R)3 * rho * usq) + ((R)1 - (R)0.5 * c.s_eps) * ((R)6 * uF);
+    const R de = c.s_e * ((e_s + (R)2 * drho) - (R)3 * rho * usq) - c.h_e * ((R)6 * uF);
+    const R deps = c.s_eps * ((eps_s - drho) + (R)3 * rho * usq) + c.h_eps * ((R)6 * uF);
     const R djx = -Fx, djy = -Fy;
-    const R dqx = c.s_q * (qx + jx + (R)0.5 * Fx) + ((R)1 - (R)0.5 * c.s_q) * Fx;
-    const R dqy = c.s_q * (qy + jy + (R)0.5 * Fy) + ((R)1 - (R)0.5 * c.s_q) * Fy;
+    const R dqx = c.s_q * (qx + jx + (R)0.5 * Fx) + c.h_q * Fx;
+    const R dqy = c.s_q * (qy + jy + (R)0.5 * Fy) + c.h_q * Fy;
     const R dpxx = c.s_nu * (pxx - rho * (ux * ux - uy * uy)) -
-                   ((R)1 - (R)0.5 * c.s_nu) * ((R)2 * (ux * Fx - uy * Fy));
-    const R dpxy = c.s_nu * (pxy - rho * ux * uy) - ((R)1 - (R)0.5 * c.s_nu) * (ux * Fy + uy * Fx);
+                   c.h_nu * ((R)2 * (ux * Fx - uy * Fy));
+    const R dpxy = c.s_nu * (pxy - rho * ux * uy) - c.h_nu * (ux * Fy + uy * Fx);
 
     // f+ = f - M^-1 dm
     const R A = -de * (R)(1.0 / 36.0) - deps * (R)(1.0 / 18.0);
@@ -218,6 +302,31 @@ __device__ __forceinline__ void geq_dev(R T, R Tsh, R ux, R uy, R w0, R wk, R (&
 }
 
 // ------------------------------------------------------------ streaming ----
+// Addressing.  2- and 4-byte values: a wavefront covers 64 consecutive nodes
+// of one row (the pitch is a multiple of 64); with the row taken from the
+// wavefront's first lane, the byte offset of the row is added to the array
+// base in scalar registers and each lane adds only the 32-bit byte offset of
+// its column, so every load and store is one global instruction with a
+// scalar base and no per-lane 64-bit address arithmetic.  8-byte values:
+// per-lane element indices (row + column, shared by the 14 arrays).
+template <class T> __device__ __forceinline__ constexpr bool byte_offsets() { return sizeof(T) < 8; }
+template <class T> __device__ __forceinline__ size_t row_off(const LP& lp, int y) {
+    return byte_offsets<T>() ? (size_t)y * (size_t)lp.pitch * sizeof(T) : (size_t)y * (size_t)lp.pitch;
+}
+template <class T> __device__ __forceinline__ uint32_t col_off(int x) {
+    return byte_offsets<T>() ? (uint32_t)x * (uint32_t)sizeof(T) : (uint32_t)x;
+}
+template <class T>
+__device__ __forceinline__ PT_GLOBAL T* at_rc(PT_GLOBAL T* a, size_t row, uint32_t col) {
+    if (byte_offsets<T>()) return (PT_GLOBAL T*)(((PT_GLOBAL char*)a + row) + col);
+    return a + (row + (size_t)col);
+}
+template <class T>
+__device__ __forceinline__ const PT_GLOBAL T* at_rc(const PT_GLOBAL T* a, size_t row, uint32_t col) {
+    if (byte_offsets<T>()) return (const PT_GLOBAL T*)(((const PT_GLOBAL char*)a + row) + col);
+    return a + (row + (size_t)col);
+}
+
 // Pull of the 9 + 5 populations arriving at node (x, y) from the
 // post-collision state A, as deviations: flat walls in y by halfway
 // bounce-back (moving tangentially at wall_ux) for f and anti-bounce-back
@@ -227,80 +336,87 @@ __device__ __forceinline__ void geq_dev(R T, R Tsh, R ux, R uy, R w0, R wk, R (&
 // wall at once takes the y wall's rule.  Solid upstream nodes hold the
 // bounce-back values written by the link pass.  Plain modes store f (the
 // rest part w_i rho0 is removed here) and g with T_sh = 0; shifted modes
-// store the deviations.
-template <class S, bool NTL = false>
-__device__ __forceinline__ void pull_node(const Pops<typename S::T>& A, const LP& lp, int x, int y,
-                                          typename S::R (&s)[9], typename S::R (&t)[5]) {
+// store the deviations.  WALLS = false: the caller knows that (x, y) is
+// next to no wall, and the wall rules are compiled out (the pull is then
+// one straight run of loads with scalar bases).
+template <class S, bool NTL = false, bool WALLS = true>
+__device__ __forceinline__ void pull_node(const Pops<typename S::T>& A, const LP& lp,
+                                          const CC<typename S::R>& c, int x, int y, typename S::R (&s)[9],
+                                          typename S::R (&t)[5]) {
     using R = typename S::R;
+    using T = typename S::T;
     // NTL: non-temporal loads (the lattice kernel reads each value once)
-    auto ld = [](const PT_GLOBAL typename S::T* q) { return NTL ? S::ld_nt(q) : S::ld(q); };
-    const int nx = lp.nx, ny = lp.ny, pitch = lp.pitch;
+    auto ld = [](const PT_GLOBAL T* q) { return NTL ? S::ld_nt(q) : S::ld(q); };
+    const int nx = lp.nx, ny = lp.ny;
     const int xm = x == 0 ? nx - 1 : x - 1;
     const int xp = x == nx - 1 ? 0 : x + 1;
-    const bool bot = !lp.periodic_y && y == 0;
-    const bool top = !lp.periodic_y && y == ny - 1;
-    const bool lft = !lp.periodic_x && x == 0;
-    const bool rgt = !lp.periodic_x && x == nx - 1;
+    const bool bot = WALLS && !lp.periodic_y && y == 0;
+    const bool top = WALLS && !lp.periodic_y && y == ny - 1;
+    const bool lft = WALLS && !lp.periodic_x && x == 0;
+    const bool rgt = WALLS && !lp.periodic_x && x == nx - 1;
     const int ym = y == 0 ? ny - 1 : y - 1;
     const int yp = y == ny - 1 ? 0 : y + 1;
-    const size_t r0 = (size_t)y * pitch, rm = (size_t)ym * pitch, rp = (size_t)yp * pitch;
-    const size_t k = r0 + x;
+    const size_t r0 = row_off<T>(lp, y), rm = row_off<T>(lp, ym), rp = row_off<T>(lp, yp);
+    const uint32_t c0 = col_off<T>(x), cm = col_off<T>(xm), cp = col_off<T>(xp);
     R fs[9];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) fs[i] = S::shifted ? (R)0 : w9<R>(i) * (R)lp.rho0;
+    for (int i = 0; i < 9; ++i) fs[i] = S::shifted ? (R)0 : c.fsw[i];
     // at a side wall the address moves to the node's own opposite population
     // (the pairs share their rest weight, so fs stays the same)
-    const R w5k = (R)lp.w5_k;
-    s[0] = ld(A.f[0] + k) - fs[0];
-    s[1] = ld(lft ? A.f[3] + k : A.f[1] + r0 + xm) - fs[1];
-    s[3] = ld(rgt ? A.f[1] + k : A.f[3] + r0 + xp) - fs[3];
-    t[0] = ld(A.g[0] + k);
-    const R g1 = ld(lft ? A.g[3] + k : A.g[1] + r0 + xm);
-    const R g3 = ld(rgt ? A.g[1] + k : A.g[3] + r0 + xp);
-    t[1] = lft ? (R)2 * w5k * ((R)lp.side_T[0] - (R)lp.T_sh) - g1 : g1;
-    t[3] = rgt ? (R)2 * w5k * ((R)lp.side_T[1] - (R)lp.T_sh) - g3 : g3;
+    s[0] = ld(at_rc(A.f[0], r0, c0)) - fs[0];
+    s[1] = ld(lft ? at_rc(A.f[3], r0, c0) : at_rc(A.f[1], r0, cm)) - fs[1];
+    s[3] = ld(rgt ? at_rc(A.f[1], r0, c0) : at_rc(A.f[3], r0, cp)) - fs[3];
+    t[0] = ld(at_rc(A.g[0], r0, c0));
+    const R g1 = ld(lft ? at_rc(A.g[3], r0, c0) : at_rc(A.g[1], r0, cm));
+    const R g3 = ld(rgt ? at_rc(A.g[1], r0, c0) : at_rc(A.g[3], r0, cp));
+    t[1] = lft ? c.g_side[0] - g1 : g1;
+    t[3] = rgt ? c.g_side[1] - g3 : g3;
     if (bot) {
-        const R u = (R)lp.wall_ux[0] * (R)lp.rho0 * (R)(1.0 / 6.0);
-        s[2] = ld(A.f[4] + k) - fs[4];
-        s[5] = (ld(A.f[7] + k) - fs[7]) + u;
-        s[6] = (ld(A.f[8] + k) - fs[8]) - u;
-        t[2] = -ld(A.g[4] + k) + (R)2 * w5k * ((R)lp.wall_T[0] - (R)lp.T_sh);
+        const R u = c.u_wall[0];
+        s[2] = ld(at_rc(A.f[4], r0, c0)) - fs[4];
+        s[5] = (ld(at_rc(A.f[7], r0, c0)) - fs[7]) + u;
+        s[6] = (ld(at_rc(A.f[8], r0, c0)) - fs[8]) - u;
+        t[2] = -ld(at_rc(A.g[4], r0, c0)) + c.g_wall[0];
     } else {
-        s[2] = ld(A.f[2] + rm + x) - fs[2];
-        s[5] = ld(lft ? A.f[7] + k : A.f[5] + rm + xm) - fs[5];
-        s[6] = ld(rgt ? A.f[8] + k : A.f[6] + rm + xp) - fs[6];
-        t[2] = ld(A.g[2] + rm + x);
+        s[2] = ld(at_rc(A.f[2], rm, c0)) - fs[2];
+        s[5] = ld(lft ? at_rc(A.f[7], r0, c0) : at_rc(A.f[5], rm, cm)) - fs[5];
+        s[6] = ld(rgt ? at_rc(A.f[8], r0, c0) : at_rc(A.f[6], rm, cp)) - fs[6];
+        t[2] = ld(at_rc(A.g[2], rm, c0));
     }
     if (top) {
-        const R u = (R)lp.wall_ux[1] * (R)lp.rho0 * (R)(1.0 / 6.0);
-        s[4] = ld(A.f[2] + k) - fs[2];
-        s[7] = (ld(A.f[5] + k) - fs[5]) - u;
-        s[8] = (ld(A.f[6] + k) - fs[6]) + u;
-        t[4] = -ld(A.g[2] + k) + (R)2 * w5k * ((R)lp.wall_T[1] - (R)lp.T_sh);
+        const R u = c.u_wall[1];
+        s[4] = ld(at_rc(A.f[2], r0, c0)) - fs[2];
+        s[7] = (ld(at_rc(A.f[5], r0, c0)) - fs[5]) - u;
+        s[8] = (ld(at_rc(A.f[6], r0, c0)) - fs[6]) + u;
+        t[4] = -ld(at_rc(A.g[2], r0, c0)) + c.g_wall[1];
     } else {
-        s[4] = ld(A.f[4] + rp + x) - fs[4];
-        s[7] = ld(rgt ? A.f[5] + k : A.f[7] + rp + xp) - fs[7];
-        s[8] = ld(lft ? A.f[6] + k : A.f[8] + rp + xm) - fs[8];
-        t[4] = ld(A.g[4] + rp + x);
+        s[4] = ld(at_rc(A.f[4], rp, c0)) - fs[4];
+        s[7] = ld(rgt ? at_rc(A.f[5], r0, c0) : at_rc(A.f[7], rp, cp)) - fs[7];
+        s[8] = ld(lft ? at_rc(A.f[6], r0, c0) : at_rc(A.f[8], rp, cm)) - fs[8];
+        t[4] = ld(at_rc(A.g[4], rp, c0));
     }
 }
 
-// Store of the 14 post-collision values of node k; NT selects non-temporal
-// (streaming) stores.
+// Store of the 14 post-collision values of node (x, y); NT selects
+// non-temporal (streaming) stores.
 template <class S, bool NT = false>
-__device__ __forceinline__ void store_node(const Pops<typename S::T>& B, const LP& lp, size_t k,
-                                           const typename S::R (&s)[9], const typename S::R (&t)[5]) {
+__device__ __forceinline__ void store_node(const Pops<typename S::T>& B, const LP& lp,
+                                           const CC<typename S::R>& c, int x, int y, const typename S::R (&s)[9],
+                                           const typename S::R (&t)[5]) {
     using R = typename S::R;
+    using T = typename S::T;
+    const size_t r0 = row_off<T>(lp, y);
+    const uint32_t c0 = col_off<T>(x);
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-        const R v = s[i] + (S::shifted ? (R)0 : w9<R>(i) * (R)lp.rho0);
-        if (NT) S::st_nt(B.f[i] + k, v);
-        else S::st(B.f[i] + k, v);
+        const R v = s[i] + (S::shifted ? (R)0 : c.fsw[i]);
+        if (NT) S::st_nt(at_rc(B.f[i], r0, c0), v);
+        else S::st(at_rc(B.f[i], r0, c0), v);
     }
 #pragma unroll
     for (int k5 = 0; k5 < 5; ++k5) {
-        if (NT) S::st_nt(B.g[k5] + k, t[k5]);
-        else S::st(B.g[k5] + k, t[k5]);
+        if (NT) S::st_nt(at_rc(B.g[k5], r0, c0), t[k5]);
+        else S::st(at_rc(B.g[k5], r0, c0), t[k5]);
     }
 }
 
@@ -357,71 +473,90 @@ __device__ __forceinline__ PT_GLOBAL T* pushed_ptr(PT_GLOBAL T* own, PT_GLOBAL T
 // place; where the upstream node is beyond a wall the slot holds the
 // node's own outgoing post-collision value and the wall rule of pull_node
 // applies to it (with the same arithmetic, so both layouts give the same
-// bits).
-template <class S, bool NTL = false>
-__device__ __forceinline__ void pull_node_pushed(const Pops<typename S::T>& F, const LP& lp, int x, int y,
-                                                 typename S::R (&s)[9], typename S::R (&t)[5]) {
+// bits).  WALLS as for pull_node.
+template <class S, bool NTL = false, bool WALLS = true>
+__device__ __forceinline__ void pull_node_pushed(const Pops<typename S::T>& F, const LP& lp,
+                                                 const CC<typename S::R>& c, int x, int y, typename S::R (&s)[9],
+                                                 typename S::R (&t)[5]) {
     using R = typename S::R;
-    auto ld = [](const PT_GLOBAL typename S::T* q) { return NTL ? S::ld_nt(q) : S::ld(q); };
-    const bool bot = !lp.periodic_y && y == 0;
-    const bool top = !lp.periodic_y && y == lp.ny - 1;
-    const bool lft = !lp.periodic_x && x == 0;
-    const bool rgt = !lp.periodic_x && x == lp.nx - 1;
-    const size_t k = (size_t)y * lp.pitch + x;
+    using T = typename S::T;
+    auto ld = [](const PT_GLOBAL T* q) { return NTL ? S::ld_nt(q) : S::ld(q); };
+    const bool bot = WALLS && !lp.periodic_y && y == 0;
+    const bool top = WALLS && !lp.periodic_y && y == lp.ny - 1;
+    const bool lft = WALLS && !lp.periodic_x && x == 0;
+    const bool rgt = WALLS && !lp.periodic_x && x == lp.nx - 1;
+    const size_t r0 = row_off<T>(lp, y);
+    const uint32_t c0 = col_off<T>(x);
+    auto L = [&](const PT_GLOBAL T* a) { return ld(at_rc(a, r0, c0)); };
     R fs[9];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) fs[i] = S::shifted ? (R)0 : w9<R>(i) * (R)lp.rho0;
-    const R w5k = (R)lp.w5_k;
-    s[0] = ld(F.f[0] + k) - fs[0];
-    s[1] = ld(F.f[1] + k) - fs[1];
-    s[3] = ld(F.f[3] + k) - fs[3];
-    t[0] = ld(F.g[0] + k);
-    const R g1 = ld(F.g[1] + k);
-    const R g3 = ld(F.g[3] + k);
-    t[1] = lft ? (R)2 * w5k * ((R)lp.side_T[0] - (R)lp.T_sh) - g1 : g1;
-    t[3] = rgt ? (R)2 * w5k * ((R)lp.side_T[1] - (R)lp.T_sh) - g3 : g3;
+    for (int i = 0; i < 9; ++i) fs[i] = S::shifted ? (R)0 : c.fsw[i];
+    s[0] = L(F.f[0]) - fs[0];
+    s[1] = L(F.f[1]) - fs[1];
+    s[3] = L(F.f[3]) - fs[3];
+    t[0] = L(F.g[0]);
+    const R g1 = L(F.g[1]);
+    const R g3 = L(F.g[3]);
+    t[1] = lft ? c.g_side[0] - g1 : g1;
+    t[3] = rgt ? c.g_side[1] - g3 : g3;
     if (bot) {
-        const R u = (R)lp.wall_ux[0] * (R)lp.rho0 * (R)(1.0 / 6.0);
-        s[2] = ld(F.f[2] + k) - fs[4];
-        s[5] = (ld(F.f[5] + k) - fs[7]) + u;
-        s[6] = (ld(F.f[6] + k) - fs[8]) - u;
-        t[2] = -ld(F.g[2] + k) + (R)2 * w5k * ((R)lp.wall_T[0] - (R)lp.T_sh);
+        const R u = c.u_wall[0];
+        s[2] = L(F.f[2]) - fs[4];
+        s[5] = (L(F.f[5]) - fs[7]) + u;
+        s[6] = (L(F.f[6]) - fs[8]) - u;
+        t[2] = -L(F.g[2]) + c.g_wall[0];
     } else {
-        s[2] = ld(F.f[2] + k) - fs[2];
-        s[5] = ld(F.f[5] + k) - fs[5];
-        s[6] = ld(F.f[6] + k) - fs[6];
-        t[2] = ld(F.g[2] + k);
+        s[2] = L(F.f[2]) - fs[2];
+        s[5] = L(F.f[5]) - fs[5];
+        s[6] = L(F.f[6]) - fs[6];
+        t[2] = L(F.g[2]);
     }
     if (top) {
-        const R u = (R)lp.wall_ux[1] * (R)lp.rho0 * (R)(1.0 / 6.0);
-        s[4] = ld(F.f[4] + k) - fs[2];
-        s[7] = (ld(F.f[7] + k) - fs[5]) - u;
-        s[8] = (ld(F.f[8] + k) - fs[6]) + u;
-        t[4] = -ld(F.g[4] + k) + (R)2 * w5k * ((R)lp.wall_T[1] - (R)lp.T_sh);
+        const R u = c.u_wall[1];
+        s[4] = L(F.f[4]) - fs[2];
+        s[7] = (L(F.f[7]) - fs[5]) - u;
+        s[8] = (L(F.f[8]) - fs[6]) + u;
+        t[4] = -L(F.g[4]) + c.g_wall[1];
     } else {
-        s[4] = ld(F.f[4] + k) - fs[4];
-        s[7] = ld(F.f[7] + k) - fs[7];
-        s[8] = ld(F.f[8] + k) - fs[8];
-        t[4] = ld(F.g[4] + k);
+        s[4] = L(F.f[4]) - fs[4];
+        s[7] = L(F.f[7]) - fs[7];
+        s[8] = L(F.f[8]) - fs[8];
+        t[4] = L(F.g[4]);
     }
+}
+
+// Where the odd kernel pushes population k of node (x, y): slot k of
+// (x, y) + e_k, or slot kbar of (x, y) itself where that node is beyond a
+// wall.  WALLS = false: (x, y) is next to no wall.
+template <class T, bool WALLS = true>
+__device__ __forceinline__ PT_GLOBAL T* push_ptr(PT_GLOBAL T* own, PT_GLOBAL T* opp, const LP& lp, int x, int y,
+                                                 int k) {
+    const int x2 = x + EXd(k), y2 = y + EYd(k);
+    const bool beyond = WALLS && ((!lp.periodic_y && (y2 < 0 || y2 >= lp.ny)) ||
+                                  (!lp.periodic_x && (x2 < 0 || x2 >= lp.nx)));
+    const int yw = y2 < 0 ? y2 + lp.ny : (y2 >= lp.ny ? y2 - lp.ny : y2);
+    const int xw = x2 < 0 ? x2 + lp.nx : (x2 >= lp.nx ? x2 - lp.nx : x2);
+    return beyond ? at_rc(opp, row_off<T>(lp, y), col_off<T>(x)) : at_rc(own, row_off<T>(lp, yw), col_off<T>(xw));
 }
 
 // The odd kernel's store: f_k*(x, y) pushed to slot k of (x, y) + e_k, or to
 // slot kbar of (x, y) where that node is beyond a wall.
-template <class S, bool NT = false>
-__device__ __forceinline__ void store_node_pushed(const Pops<typename S::T>& F, const LP& lp, int x, int y,
+template <class S, bool NT = false, bool WALLS = true>
+__device__ __forceinline__ void store_node_pushed(const Pops<typename S::T>& F, const LP& lp,
+                                                  const CC<typename S::R>& c, int x, int y,
                                                   const typename S::R (&s)[9], const typename S::R (&t)[5]) {
     using R = typename S::R;
+    using T = typename S::T;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-        const R v = s[i] + (S::shifted ? (R)0 : w9<R>(i) * (R)lp.rho0);
-        PT_GLOBAL typename S::T* q = pushed_ptr(F.f[i], F.f[OPPd(i)], lp, x, y, i);
+        const R v = s[i] + (S::shifted ? (R)0 : c.fsw[i]);
+        PT_GLOBAL T* q = push_ptr<T, WALLS>(F.f[i], F.f[OPPd(i)], lp, x, y, i);
         if (NT) S::st_nt(q, v);
         else S::st(q, v);
     }
 #pragma unroll
     for (int k5 = 0; k5 < 5; ++k5) {
-        PT_GLOBAL typename S::T* q = pushed_ptr(F.g[k5], F.g[OPPd(k5)], lp, x, y, k5);
+        PT_GLOBAL T* q = push_ptr<T, WALLS>(F.g[k5], F.g[OPPd(k5)], lp, x, y, k5);
         if (NT) S::st_nt(q, t[k5]);
         else S::st(q, t[k5]);
     }

@@ -12,6 +12,50 @@ namespace ptlbm {
 
 // ------------------------------------------------------ lattice kernels ----
 
+// Node of lane `threadIdx.x` in block `bid` of the flat grid.  ROW: the row
+// is the same for the whole wavefront (the pitch is a multiple of 64) and is
+// taken from its first lane, so that it lives in scalar registers and every
+// access has a scalar base (the pitched lattice has fewer than 2^32 nodes:
+// both edges are below 2^16).  Otherwise each lane divides for itself.
+template <bool ROW>
+__device__ __forceinline__ void lattice_node(const LP& lp, unsigned bid, int& x, int& y) {
+    if (ROW) {
+        const unsigned w0 = (unsigned)__builtin_amdgcn_readfirstlane((int)threadIdx.x);   // first lane of the wave
+        const unsigned n0 = bid * (unsigned)LAT_BLOCK + w0;
+        y = (int)(n0 / (unsigned)lp.pitch);
+        x = (int)(n0 - (unsigned)y * (unsigned)lp.pitch) + (int)(threadIdx.x - w0);
+    } else {
+        const size_t n0 = (size_t)bid * LAT_BLOCK + threadIdx.x;
+        y = (int)(n0 / (unsigned)lp.pitch);
+        x = (int)(n0 - (size_t)y * lp.pitch);
+    }
+}
+
+// Scalar row bases and a wall-free pull for the nodes next to no wall pay
+// off where the kernel's arithmetic limits it (FP32 arithmetic on 2- and
+// 4-byte values: 45 % fewer instructions per node); with 8-byte values the
+// kernel moves the same bytes 2.5 % faster with per-lane addresses and the
+// wall rules evaluated in every node (both measured at 4000^2).
+template <int MODE> constexpr bool row_addressing() { return sizeof(ST<MODE>) < 8; }
+
+// A node next to a wall: a side wall of the closed cavity or a flat wall in
+// y.  The pulls and pushes take the wall rules there; everywhere else they
+// are compiled out.
+__device__ __forceinline__ bool next_to_wall(const LP& lp, int x, int y) {
+    return (!lp.periodic_x && (x == 0 || x == lp.nx - 1)) || (!lp.periodic_y && (y == 0 || y == lp.ny - 1));
+}
+
+template <class R>
+__device__ __forceinline__ void check_finite(const RunStep& rs, int x, int y, R rho, R ux, R uy, R T) {
+    if (isfinite(rho) && isfinite(T) && isfinite(ux) && isfinite(uy)) return;
+    if (gl(rs.Ocur)[(size_t)y * rs.lp.pitch + x] != -1) return;
+    // one report per wavefront, none once the bit is set: a run that has
+    // gone non-finite must not serialise on its status word
+    const unsigned long long m = __ballot(1);
+    if ((threadIdx.x & 63) == (unsigned)(__ffsll((long long)m) - 1) && !(gl(rs.status)[0] & ST_NONFINITE))
+        atomicOr(rs.status, ST_NONFINITE);
+}
+
 // Fused pull-stream + collide of every node of the lattice, one thread per
 // node of the pitched layout (flat 1-D grid, rows padded to the pitch).
 // Every node is written, so each wavefront stores whole cache lines: nodes
@@ -23,31 +67,32 @@ namespace ptlbm {
 // pulls from inside the particle); the owner map is read only for a node
 // whose value is non-finite, so the check costs no traffic while the run is
 // sound.  The kernel reads nothing that the particle kernels of the same
-// step write, so those may run concurrently with it.
-template <int MODE>
-__device__ __forceinline__ void stream_collide_body(const RunStep& rs, unsigned bid) {
+// step write, so those may run concurrently with it.  The nodes next to no
+// wall (all but a few wavefronts) take a pull without wall rules.
+template <int MODE, bool WALLS>
+__device__ __forceinline__ void two_sets_node(const RunStep& rs, const CC<typename Store<MODE>::R>& c, int x,
+                                              int y) {
     using S = Store<MODE>;
     using R = typename S::R;
     const LP& lp = rs.lp;
     const Pops<ST<MODE>> A = pops_of<MODE>(rs.A), B = pops_of<MODE>(rs.B);
-    const size_t n0 = (size_t)bid * LAT_BLOCK + threadIdx.x;
-    const int y = (int)(n0 / (unsigned)lp.pitch);
-    const int x = (int)(n0 - (size_t)y * lp.pitch);
-    if (x >= lp.nx || y >= lp.ny) return;
-    const size_t k = (size_t)y * lp.pitch + x;
     R s[9], t[5];
-    pull_node<S, true>(A, lp, x, y, s, t);
-    const CC<R> c(lp);
+    pull_node<S, true, WALLS>(A, lp, c, x, y, s, t);
     R rho, ux, uy, T;
     collide<R>(c, s, t, rho, ux, uy, T);
-    if (!(isfinite(rho) && isfinite(T) && isfinite(ux) && isfinite(uy)) && gl(rs.Ocur)[k] == -1) {
-        // one report per wavefront, none once the bit is set: a run that
-        // has gone non-finite must not serialise on its status word
-        const unsigned long long m = __ballot(1);
-        if ((threadIdx.x & 63) == (unsigned)(__ffsll((long long)m) - 1) && !(gl(rs.status)[0] & ST_NONFINITE))
-            atomicOr(rs.status, ST_NONFINITE);
-    }
-    store_node<S, true>(B, lp, k, s, t);
+    store_node<S, true>(B, lp, c, x, y, s, t);
+    check_finite<R>(rs, x, y, rho, ux, uy, T);
+}
+
+template <int MODE>
+__device__ __forceinline__ void stream_collide_body(const RunStep& rs, unsigned bid) {
+    constexpr bool ROW = row_addressing<MODE>();
+    int x, y;
+    lattice_node<ROW>(rs.lp, bid, x, y);
+    if (x >= rs.lp.nx || y >= rs.lp.ny) return;
+    const CC<typename Store<MODE>::R> c = lp_cc<typename Store<MODE>::R>(rs.lp);
+    if (!ROW || next_to_wall(rs.lp, x, y)) two_sets_node<MODE, true>(rs, c, x, y);
+    else two_sets_node<MODE, false>(rs, c, x, y);
 }
 
 // The same step in place (AA streaming, one population set F = A = B).
@@ -56,30 +101,32 @@ __device__ __forceinline__ void stream_collide_body(const RunStep& rs, unsigned 
 // after it).  EVEN: from a pushed state, every slot read in place
 // (pull_node_pushed) and written back reversed into the node (parity 0).
 // Same collision, same wall rules, same values as the two-set kernel.
-template <int MODE, bool ODD>
-__device__ __forceinline__ void stream_collide_aa_body(const RunStep& rs, unsigned bid) {
+template <int MODE, bool ODD, bool WALLS>
+__device__ __forceinline__ void in_place_node(const RunStep& rs, const CC<typename Store<MODE>::R>& c, int x,
+                                              int y) {
     using S = Store<MODE>;
     using R = typename S::R;
     const LP& lp = rs.lp;
     const Pops<ST<MODE>> F = pops_of<MODE>(rs.A);
-    const size_t n0 = (size_t)bid * LAT_BLOCK + threadIdx.x;
-    const int y = (int)(n0 / (unsigned)lp.pitch);
-    const int x = (int)(n0 - (size_t)y * lp.pitch);
-    if (x >= lp.nx || y >= lp.ny) return;
-    const size_t k = (size_t)y * lp.pitch + x;
     R s[9], t[5];
-    if (ODD) pull_node<S, true>(opp_view(F), lp, x, y, s, t);
-    else pull_node_pushed<S, true>(F, lp, x, y, s, t);
-    const CC<R> c(lp);
+    if (ODD) pull_node<S, true, WALLS>(opp_view(F), lp, c, x, y, s, t);
+    else pull_node_pushed<S, true, WALLS>(F, lp, c, x, y, s, t);
     R rho, ux, uy, T;
     collide<R>(c, s, t, rho, ux, uy, T);
-    if (!(isfinite(rho) && isfinite(T) && isfinite(ux) && isfinite(uy)) && gl(rs.Ocur)[k] == -1) {
-        const unsigned long long m = __ballot(1);
-        if ((threadIdx.x & 63) == (unsigned)(__ffsll((long long)m) - 1) && !(gl(rs.status)[0] & ST_NONFINITE))
-            atomicOr(rs.status, ST_NONFINITE);
-    }
-    if (ODD) store_node_pushed<S, true>(F, lp, x, y, s, t);
-    else store_node<S, true>(opp_view(F), lp, k, s, t);
+    if (ODD) store_node_pushed<S, true, WALLS>(F, lp, c, x, y, s, t);
+    else store_node<S, true>(opp_view(F), lp, c, x, y, s, t);
+    check_finite<R>(rs, x, y, rho, ux, uy, T);
+}
+
+template <int MODE, bool ODD>
+__device__ __forceinline__ void stream_collide_aa_body(const RunStep& rs, unsigned bid) {
+    constexpr bool ROW = row_addressing<MODE>();
+    int x, y;
+    lattice_node<ROW>(rs.lp, bid, x, y);
+    if (x >= rs.lp.nx || y >= rs.lp.ny) return;
+    const CC<typename Store<MODE>::R> c = lp_cc<typename Store<MODE>::R>(rs.lp);
+    if (!ROW || next_to_wall(rs.lp, x, y)) in_place_node<MODE, ODD, true>(rs, c, x, y);
+    else in_place_node<MODE, ODD, false>(rs, c, x, y);
 }
 
 // Equilibrium of the given macroscopic fields (host layout j*nx + i over
@@ -98,6 +145,7 @@ __global__ __launch_bounds__(LAT_BLOCK) void k_init(Pops<ST<MODE>> A, const int3
     if (x >= lp.nx) return;
     const size_t k = (size_t)y * lp.pitch + x;
     const size_t h = (size_t)blockIdx.y * lp.nx + x;
+    const CC<R> c = lp_cc<R>(lp);
     R s[9], t[5];
     if (owner[k] >= 0) {
         for (int i = 0; i < 9; ++i) s[i] = (R)0;
@@ -109,13 +157,12 @@ __global__ __launch_bounds__(LAT_BLOCK) void k_init(Pops<ST<MODE>> A, const int3
         const R T = T_f ? (R)T_f[h] : (R)T_u;
         feq_dev<R>(rho, (R)lp.rho0, ux, uy, s);
         geq_dev<R>(T, (R)lp.T_sh, ux, uy, (R)lp.w5_0, (R)lp.w5_k, t);
-        const CC<R> c(lp);
         R r_, u_, v_, T_;
         collide<R>(c, s, t, r_, u_, v_, T_);
     }
-    if (!lp.aa) store_node<S>(A, lp, k, s, t);
-    else if (parity == 0) store_node<S>(opp_view(A), lp, k, s, t);
-    else store_node_pushed<S>(A, lp, x, y, s, t);
+    if (!lp.aa) store_node<S>(A, lp, c, x, y, s, t);
+    else if (parity == 0) store_node<S>(opp_view(A), lp, c, x, y, s, t);
+    else store_node_pushed<S>(A, lp, c, x, y, s, t);
 }
 
 // Pre-collision macroscopics from the post-collision state: rho and T are
@@ -177,8 +224,18 @@ __global__ __launch_bounds__(LAT_BLOCK) void k_macros(Pops<ST<MODE>> A, const in
 // The lattice step kernel for one run (RunStep by value) and batched (block
 // b works on block bmap[b].y of run bmap[b].x, whose RunStep is
 // tab[bmap[b].x]); both run the same body.
+// Wavefronts per SIMD: with 8-byte values the lattice kernels move their
+// bytes fastest at 5 (two sets), 4 (in place, odd) and 5 (in place, even),
+// the occupancies their register counts gave before the scalar row
+// addressing of the narrow types (at 4000^2: 611 us at 5 against 624 us
+// at 6 for the two-set kernel); the narrow types are not limited.
+template <int MODE> constexpr int lattice_waves(bool odd = false) {
+    return sizeof(ST<MODE>) == 8 ? (odd ? 4 : 5) : 8;
+}
+
 template <int MODE>
-__global__ __launch_bounds__(LAT_BLOCK) void k_stream_collide(RunStep rs) {
+__global__ __launch_bounds__(LAT_BLOCK) __attribute__((amdgpu_waves_per_eu(1, lattice_waves<MODE>())))
+void k_stream_collide(RunStep rs) {
     stream_collide_body<MODE>(rs, blockIdx.x);
 }
 template <int MODE>
@@ -188,7 +245,8 @@ __global__ __launch_bounds__(LAT_BLOCK) void k_stream_collide_b(const RunStep* _
     stream_collide_body<MODE>(tab[m.x], m.y);
 }
 template <int MODE, bool ODD>
-__global__ __launch_bounds__(LAT_BLOCK) void k_stream_collide_aa(RunStep rs) {
+__global__ __launch_bounds__(LAT_BLOCK) __attribute__((amdgpu_waves_per_eu(1, lattice_waves<MODE>(ODD))))
+void k_stream_collide_aa(RunStep rs) {
     stream_collide_aa_body<MODE, ODD>(rs, blockIdx.x);
 }
 // batched in place: each run at its own parity (one branch per block)

@@ -712,7 +712,8 @@ __device__ __forceinline__ void mask_body(const RunStep& rs, unsigned bid) {
 template <int MODE>
 __device__ bool refill_node(const Pops<ST<MODE>>& A, int lay, const PT_GLOBAL int32_t* Ocur,
                             const PT_GLOBAL int32_t* Onext, const PState& P, const Shape& sh, int p, int x,
-                            int y, const LP& lp, typename Store<MODE>::R (&s)[9], typename Store<MODE>::R (&t)[5]) {
+                            int y, const LP& lp, const CC<typename Store<MODE>::R>& cc,
+                            typename Store<MODE>::R (&s)[9], typename Store<MODE>::R (&t)[5]) {
     using S = Store<MODE>;
     using R = typename S::R;
     const size_t k0 = (size_t)y * lp.pitch + x;
@@ -750,9 +751,9 @@ __device__ bool refill_node(const Pops<ST<MODE>>& A, int lay, const PT_GLOBAL in
             const size_t km = (size_t)ys[m] * lp.pitch + xs[m];
             fl[m] = Ocur[km] == -1 && Onext[km] == -1;
             R tt[5];
-            if (lay == 0) pull_node<S>(A, lp, xs[m], ys[m], sm[m], tt);
-            else if (lay == 1) pull_node<S>(opp_view(A), lp, xs[m], ys[m], sm[m], tt);
-            else pull_node_pushed<S>(A, lp, xs[m], ys[m], sm[m], tt);
+            if (lay == 0) pull_node<S>(A, lp, cc, xs[m], ys[m], sm[m], tt);
+            else if (lay == 1) pull_node<S>(opp_view(A), lp, cc, xs[m], ys[m], sm[m], tt);
+            else pull_node_pushed<S>(A, lp, cc, xs[m], ys[m], sm[m], tt);
         }
     }
     if (!mine) return false;
@@ -780,7 +781,6 @@ __device__ bool refill_node(const Pops<ST<MODE>>& A, int lay, const PT_GLOBAL in
     const R djy = (rho * (R)uwy - (R)0.5 * Fy) - jy;
     for (int a = 0; a < 9; ++a) s[a] += ((R)EXd(a) * djx + (R)EYd(a) * djy) * (R)(1.0 / 6.0);
     geq_dev<R>(Tw, (R)lp.T_sh, (R)uwx, (R)uwy, (R)lp.w5_0, (R)lp.w5_k, t);
-    const CC<R> cc(lp);
     R r_, u_, v_, T_;
     collide<R>(cc, s, t, r_, u_, v_, T_);
     return true;
@@ -818,14 +818,14 @@ __device__ __forceinline__ void refill_body(const RunStep& rs, unsigned bid) {
             if (buf[slot + 14] == 0.0) continue;
             for (int a = 0; a < 9; ++a) s[a] = (R)buf[slot + a];
             for (int a = 0; a < 5; ++a) t[a] = (R)buf[slot + 9 + a];
-            if (rs.parity == 0) store_node_pushed<S>(A, lp, x, y, s, t);   // the odd kernel ran
-            else store_node<S>(opp_view(A), lp, (size_t)y * lp.pitch + x, s, t);
+            if (rs.parity == 0) store_node_pushed<S>(A, lp, args_cc<R>(lp), x, y, s, t);   // the odd kernel ran
+            else store_node<S>(opp_view(A), lp, args_cc<R>(lp), x, y, s, t);
             continue;
         }
         const int lay = lp.aa ? 1 + rs.parity : 0;
-        const bool mine = refill_node<MODE>(A, lay, gl(rs.Ocur), gl(rs.Onext), P1, sh, p, x, y, lp, s, t);
+        const bool mine = refill_node<MODE>(A, lay, gl(rs.Ocur), gl(rs.Onext), P1, sh, p, x, y, lp, args_cc<R>(lp), s, t);
         if (PART == REFILL_TWO_SETS) {
-            if (mine) store_node<S>(B, lp, (size_t)y * lp.pitch + x, s, t);
+            if (mine) store_node<S>(B, lp, args_cc<R>(lp), x, y, s, t);
         } else {
             if (mine) {
                 for (int a = 0; a < 9; ++a) buf[slot + a] = (double)s[a];
