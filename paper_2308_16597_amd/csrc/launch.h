@@ -96,6 +96,7 @@ enum StatusBits : unsigned {
 // 1024 particles.
 unsigned run_blocks(int c, const LP& lp);
 int lanes_per_particle(int nwin, int np);
+int pass_threads(int nwin, int np);
 size_t links_block_lds(const LP& lp);
 
 hipError_t launch_step(int k, const RunStep& R, int mode, hipStream_t st);

@@ -237,18 +237,20 @@ __device__ __forceinline__ void links_body(const RunStep& rs, unsigned bid) {
     if (lane == 0) st_i2(seg + p, make_int2((int)start, (int)count));
 }
 
-// The link pass, one block of PASS_BLOCK threads per particle, a thread per
-// link of its segment (Sec. 2.3-2.4): q from the circle, wall point
-// x_w = x_f + q e_i and its rigid-body velocity u_w, Bouzidi bounce-back
-// f_ibar (Eqs. (9)-(10), with the linear and halfway fallbacks) and, for
-// axis links, the thermal wall g_ibar (Eqs. (11)-(12)), both written into
-// the solid slots x_f + e_i of the post-collision state A that the pull of
-// x_f reads; the link's momentum exchange f_i^+ (e_i - u_w) -
-// f_ibar (e_ibar - u_w) and its torque about X_c, summed in FP64 over the
-// particle in a fixed order (each thread over its links, a butterfly in each
-// wavefront, the wavefronts in order) into Fh[p].  The gathers of a link
-// are issued together, after its (arithmetic-only) link fraction.
-constexpr int PASS_BLOCK = 256;
+// The link pass, one block per particle, a thread per link of its segment
+// (Sec. 2.3-2.4): q from the circle, wall point x_w = x_f + q e_i and its
+// rigid-body velocity u_w, Bouzidi bounce-back f_ibar (Eqs. (9)-(10), with
+// the linear and halfway fallbacks) and, for axis links, the thermal wall
+// g_ibar (Eqs. (11)-(12)), both written into the solid slots x_f + e_i of
+// the post-collision state A that the pull of x_f reads; the link's
+// momentum exchange f_i^+ (e_i - u_w) - f_ibar (e_ibar - u_w) and its torque
+// about X_c, summed in FP64 over the particle in a fixed order into Fh[p]:
+// the segment in chunks of 64 slots, each chunk by a butterfly in one
+// wavefront, the chunk sums in chunk order.  The order does not depend on
+// the block size, which follows the particle size (pass_threads), so a
+// run gives the same bits alone and in a batch.  The gathers of a link are
+// issued together, after its (arithmetic-only) link fraction.
+constexpr int PASS_CHUNKS = (12 * 100 - 12 + 63) / 64;   // the window edge is at most 100
 
 // One link: fluid node (x, y), direction i towards particle P.
 template <int MODE>
@@ -348,34 +350,38 @@ __device__ __forceinline__ void link_pass_link(const RunStep& rs, const PState& 
     hz += rx * dFy - ry * dFx;   // Eq. (14), z component
 }
 
-template <int MODE>
+template <int MODE, int NT>
 __device__ __forceinline__ void link_pass_body(const RunStep& rs, unsigned bid) {
-    __shared__ double part[PASS_BLOCK / 64][3];
+    __shared__ double part[PASS_CHUNKS][3];
     const int p = (int)bid;
     if (p >= rs.lp.np) return;   // the whole block
     const int2 sg = ld_i2(rs.seg + p);
     const PState P = ld_state(rs.Pc + p);
     const Shape sh = shape_of(P);
-    double hx = 0.0, hy = 0.0, hz = 0.0;
-    for (int t = (int)threadIdx.x; t < sg.y; t += PASS_BLOCK) {
-        const uint2 L = ld_u2(rs.links + sg.x + t);
-        link_pass_link<MODE>(rs, P, sh, (int)(L.x & 0xffffu), (int)(L.x >> 16), (int)(L.y & 15u), hx, hy, hz);
-    }
-    for (int off = 32; off > 0; off >>= 1) {
-        hx += __shfl_xor(hx, off);
-        hy += __shfl_xor(hy, off);
-        hz += __shfl_xor(hz, off);
-    }
-    const int w = (int)threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) {
-        part[w][0] = hx;
-        part[w][1] = hy;
-        part[w][2] = hz;
+    const int lane = (int)threadIdx.x & 63, w = (int)threadIdx.x >> 6;
+    const int nchunks = (sg.y + 63) / 64;
+    for (int c = w; c < nchunks; c += NT / 64) {   // the same trip count in all lanes of a wave
+        double hx = 0.0, hy = 0.0, hz = 0.0;
+        const int t = 64 * c + lane;
+        if (t < sg.y) {
+            const uint2 L = ld_u2(rs.links + sg.x + t);
+            link_pass_link<MODE>(rs, P, sh, (int)(L.x & 0xffffu), (int)(L.x >> 16), (int)(L.y & 15u), hx, hy, hz);
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            hx += __shfl_xor(hx, off);
+            hy += __shfl_xor(hy, off);
+            hz += __shfl_xor(hz, off);
+        }
+        if (lane == 0) {
+            part[c][0] = hx;
+            part[c][1] = hy;
+            part[c][2] = hz;
+        }
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         double sx = 0.0, sy = 0.0, sz = 0.0;
-        for (int j = 0; j < PASS_BLOCK / 64; ++j) {
+        for (int j = 0; j < nchunks; ++j) {
             sx += part[j][0];
             sy += part[j][1];
             sz += part[j][2];
@@ -849,17 +855,17 @@ __global__ __launch_bounds__(256) void k_links_b(const RunStep* __restrict__ tab
     links_body(tab[m.x], m.y);
 }
 
-template <int MODE>
-__global__ __launch_bounds__(PASS_BLOCK) void k_link_pass(RunStep rs) { link_pass_body<MODE>(rs, blockIdx.x); }
+template <int MODE, int NT>
+__global__ __launch_bounds__(NT) void k_link_pass(RunStep rs) { link_pass_body<MODE, NT>(rs, blockIdx.x); }
 template <int MODE>
 __global__ __launch_bounds__(LAT_BLOCK) void k_link_pass_direct(RunStep rs) {
     link_pass_direct_body<MODE>(rs, blockIdx.x);
 }
 template <int MODE>
-__global__ __launch_bounds__(PASS_BLOCK) void k_link_pass_b(const RunStep* __restrict__ tab,
+__global__ __launch_bounds__(256) void k_link_pass_b(const RunStep* __restrict__ tab,
                                                      const uint2* __restrict__ bmap) {
     const uint2 m = bmap[blockIdx.x];
-    link_pass_body<MODE>(tab[m.x], m.y);
+    link_pass_body<MODE, 256>(tab[m.x], m.y);
 }
 
 __global__ __launch_bounds__(256) void k_particles(RunStep rs) { particles_body(rs, blockIdx.x); }
@@ -906,6 +912,19 @@ __global__ void k_link_q(const PState* __restrict__ Pc, const uint2* __restrict_
 // particles the wavefronts already do, and whole blocks would take more of
 // the GPU from the lattice kernel running beside them).
 int lanes_per_particle(int nwin, int np) { return nwin >= 32 && np <= 1024 ? 256 : 64; }
+// Threads of a single run's link-pass block: 128 where that covers about
+// three quarters of the segment (12 N - 12 slots for window edge N; a disk
+// of diameter d has about 0.7 of that many links), so that few lanes idle;
+// 512 for large particles when they are few (at most 1024 blocks: the
+// block's lanes are the parallelism), else 256.  Measured at 4096^2 with
+// 64 000 disks d = 10: 128 against 256 threads, 338 vs 457 us (FP16); 129
+// ellipses 50 x 25: 512 against 256, 13.2 vs 15.6 us; 4800 disks d = 40:
+// 512 no faster than 256 (156 vs 152 us).
+int pass_threads(int nwin, int np) {
+    const int typical = (3 * (12 * nwin - 12)) / 4;
+    if (typical <= 128) return 128;
+    return typical > 256 && np <= 1024 ? 512 : 256;
+}
 
 size_t links_block_lds(const LP& lp) { return (size_t)(lp.lpp > 64 ? 1 : 4) * links_wave_lds(lp.nwin); }
 
@@ -932,7 +951,13 @@ hipError_t launch_step(int k, const RunStep& R, int mode, hipStream_t st) {
         case SK_COLLECT:   // R: the RunStep of the step whose links are collected
             k_links<<<nb, 256, links_block_lds(R.lp), st>>>(R);
             break;
-        case SK_PASS: PTLBM_DISPATCH(mode, (k_link_pass<M><<<nb, PASS_BLOCK, 0, st>>>(R))); break;
+        case SK_PASS:
+            switch (pass_threads(R.lp.nwin, R.lp.np)) {
+                case 128: PTLBM_DISPATCH(mode, (k_link_pass<M, 128><<<nb, 128, 0, st>>>(R))); break;
+                case 256: PTLBM_DISPATCH(mode, (k_link_pass<M, 256><<<nb, 256, 0, st>>>(R))); break;
+                default: PTLBM_DISPATCH(mode, (k_link_pass<M, 512><<<nb, 512, 0, st>>>(R))); break;
+            }
+            break;
         case SK_PARTICLES: k_particles<<<nb, 256, 0, st>>>(R); break;
         case SK_MASK:   // in place, the refill is computed here, before the lattice kernel
             k_mask_mark<<<nb, 256, 0, st>>>(R);
@@ -960,7 +985,7 @@ hipError_t launch_step_batch(int k, const BatchLaunch& b, hipStream_t st) {
     const uint2* bm = b.bmap[c];
     switch (k) {
         case SK_COLLECT: k_links_b<<<nb, 256, b.lds, st>>>(b.tab_next, bm); break;
-        case SK_PASS: PTLBM_DISPATCH(b.mode, (k_link_pass_b<M><<<nb, PASS_BLOCK, 0, st>>>(b.tab, bm))); break;
+        case SK_PASS: PTLBM_DISPATCH(b.mode, (k_link_pass_b<M><<<nb, 256, 0, st>>>(b.tab, bm))); break;
         case SK_PARTICLES: k_particles_b<<<nb, 256, 0, st>>>(b.tab, bm); break;
         case SK_MASK:
             k_mask_mark_b<<<nb, 256, 0, st>>>(b.tab, bm);
