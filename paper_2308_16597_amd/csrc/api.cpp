@@ -85,12 +85,14 @@ Layout make_layout(const lbm_params& p) {
     }
     L.off_cand = off; off = round_up(off + cap * 4 * (size_t)L.nwin * sizeof(unsigned), kAlign);
     L.off_ncand = off; off = round_up(off + cap * sizeof(unsigned), kAlign);
+    // refilled values of the newborn candidates, computed beside the lattice
+    // kernel and stored after it (16 doubles each)
+    L.off_rbuf = off; off = round_up(off + cap * 4 * (size_t)L.nwin * 16 * sizeof(double), kAlign);
     // field upload / read-back: the second population set of the two-set
     // layout; in place a scratch of 4 FP64 planes over an eighth of the rows
     L.field_rows = p.ny;
     if (aa) {
         L.field_rows = (p.ny + 7) / 8;
-        L.off_rbuf = off; off = round_up(off + cap * 4 * (size_t)L.nwin * 16 * sizeof(double), kAlign);
         L.off_fscratch = off; off = round_up(off + 4 * (size_t)p.nx * L.field_rows * sizeof(double), kAlign);
     }
     L.total = off;
@@ -389,12 +391,17 @@ int enqueue_step(lbm_sim* h, hipEvent_t* ev, hipEvent_t* lat = nullptr) {
         HIPCHK(h, launch_step(SK_PASS, R, mode, st));
         HIPCHK(h, hipEventRecord(h->ev_fork, st));
         HIPCHK(h, hipStreamWaitEvent(sd, h->ev_fork, 0));
-        HIPCHK(h, launch_step(SK_PARTICLES, R, mode, sd));
-        HIPCHK(h, launch_step(SK_MASK, R, mode, sd));
         const bool aa = h->d.lp.aa != 0;
+        HIPCHK(h, launch_step(SK_PARTICLES, R, mode, sd));
+        HIPCHK(h, launch_step(SK_MASK, R, mode, sd));   // in place: and the refilled values
         if (aa) HIPCHK(h, hipEventRecord(h->ev_mask, sd));
         HIPCHK(h, launch_step(SK_COLLECT, Rn, mode, sd));
+        // two sets: the refilled values last on the side stream (its kernel
+        // needs many registers and starts only as lattice waves retire; the
+        // link collection must not wait for it)
+        if (!aa) HIPCHK(h, launch_refill_part(R, mode, false, sd));
         HIPCHK(h, hipEventRecord(h->ev_side, sd));
+        // in place the lattice kernel overwrites what the refill reads
         if (aa) HIPCHK(h, hipStreamWaitEvent(st, h->ev_mask, 0));
         if (lat) HIPCHK(h, hipEventRecord(lat[0], st));
         HIPCHK(h, launch_step(SK_LATTICE, R, mode, st));
@@ -404,7 +411,7 @@ int enqueue_step(lbm_sim* h, hipEvent_t* ev, hipEvent_t* lat = nullptr) {
             HIPCHK(h, hipStreamWaitEvent(st, h->ev_side, 0));
         } else {
             HIPCHK(h, hipStreamWaitEvent(st, h->ev_side, 0));
-            HIPCHK(h, launch_step(SK_REFILL, R, mode, st));
+            HIPCHK(h, launch_refill_part(R, mode, true, st));
         }
     }
     advance_state(h);

@@ -27,7 +27,7 @@ struct DevState {
     unsigned* bcnt[2];           // particles per cell
     unsigned* cand;              // newborn-node candidates, 4 nwin per particle (x | y << 16)
     unsigned* ncand;             // candidates per particle
-    double* rbuf;                // in place: refilled post-collision values per candidate (16 each)
+    double* rbuf;                // refilled post-collision values per candidate (16 each)
 };
 
 // Everything the step kernels need of one run at one step: its lattice
@@ -105,6 +105,8 @@ hipError_t launch_step(int k, const RunStep& R, int mode, hipStream_t st);
 hipError_t launch_lattice(const RunStep& R, int mode, unsigned nblocks, hipStream_t st);
 hipError_t launch_lattice_batch(const RunStep* tab, const uint2* bmap, unsigned nblocks, int mode, bool aa,
                                 hipStream_t st);
+// The two halves of the split refill of one run (store = false: compute).
+hipError_t launch_refill_part(const RunStep& R, int mode, bool store, hipStream_t st);
 hipError_t launch_step_batch(int k, const BatchLaunch& b, hipStream_t st);
 // Owner map of R.Pn into R.Onext with no previous time level (set-up).
 hipError_t launch_mask_setup(const RunStep& R, hipStream_t st);

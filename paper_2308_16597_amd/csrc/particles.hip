@@ -793,12 +793,16 @@ __device__ bool refill_node(const Pops<ST<MODE>>& A, int lay, const PT_GLOBAL in
 }
 
 // Refill of particle p's newborn nodes, the particle's lanes and one
-// lane per candidate from k_mask_mark.  Two sets: after the lattice kernel,
-// pulling from A and storing into B.  In place the lattice kernel overwrites
-// what the stencil pulls read, so the refill is split: REFILL_COMPUTE runs
-// before it (the refilled post-collision values of each candidate into
-// rbuf, 16 doubles: 14 values and a flag), REFILL_STORE after it (into the
-// node's slots of the new state's layout).
+// lane per candidate from k_mask_mark.  REFILL_TWO_SETS: after the lattice
+// kernel, pulling from A and storing into B.  Split: REFILL_COMPUTE (the
+// refilled post-collision values of each candidate into rbuf, 16 doubles:
+// 14 values and a flag), REFILL_STORE (into the node's slots of the new
+// state) after the lattice kernel.  In place the split is needed: the
+// lattice kernel overwrites what the stencil pulls read, so the values are
+// computed before it.  An overlapped two-set step of a single run computes
+// them at the end of the side stream, where the kernel runs beside the
+// lattice kernel when the registers let it, and only the store waits on
+// the main stream.  The values are the same in every form.
 enum RefillPart { REFILL_TWO_SETS = 0, REFILL_COMPUTE, REFILL_STORE };
 template <int MODE, int PART>
 __device__ __forceinline__ void refill_body(const RunStep& rs, unsigned bid) {
@@ -824,7 +828,8 @@ __device__ __forceinline__ void refill_body(const RunStep& rs, unsigned bid) {
             if (buf[slot + 14] == 0.0) continue;
             for (int a = 0; a < 9; ++a) s[a] = (R)buf[slot + a];
             for (int a = 0; a < 5; ++a) t[a] = (R)buf[slot + 9 + a];
-            if (rs.parity == 0) store_node_pushed<S>(A, lp, args_cc<R>(lp), x, y, s, t);   // the odd kernel ran
+            if (!lp.aa) store_node<S>(B, lp, args_cc<R>(lp), x, y, s, t);
+            else if (rs.parity == 0) store_node_pushed<S>(A, lp, args_cc<R>(lp), x, y, s, t);   // the odd kernel ran
             else store_node<S>(opp_view(A), lp, args_cc<R>(lp), x, y, s, t);
             continue;
         }
@@ -974,6 +979,17 @@ hipError_t launch_step(int k, const RunStep& R, int mode, hipStream_t st) {
             }
             break;
         default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_refill_part(const RunStep& R, int mode, bool store, hipStream_t st) {
+    const unsigned nb = run_blocks(GC_WAVE, R.lp);
+    if (nb == 0) return hipSuccess;
+    if (store) {
+        PTLBM_DISPATCH(mode, (k_refill<M, REFILL_STORE><<<nb, 256, 0, st>>>(R)));
+    } else {
+        PTLBM_DISPATCH(mode, (k_refill<M, REFILL_COMPUTE><<<nb, 256, 0, st>>>(R)));
     }
     return hipGetLastError();
 }

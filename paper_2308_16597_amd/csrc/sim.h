@@ -37,7 +37,7 @@ struct lbm_sim {
     bool own_stream = false;
     hipStream_t side = nullptr;  // particle kernels, concurrent with the lattice kernel
     hipEvent_t ev_fork = nullptr, ev_side = nullptr;
-    hipEvent_t ev_mask = nullptr;  // in place: the owner map and refill values of t_n+1 are ready
+    hipEvent_t ev_mask = nullptr;  // in place: the owner map and refilled values of t_n+1 are ready
     char* base = nullptr;
     bool own_mem = false;
     int cur = 0;         // time level holding the current (post-collision) state; in place its parity
