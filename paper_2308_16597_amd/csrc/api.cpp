@@ -390,8 +390,16 @@ int enqueue_step(lbm_sim* h, hipEvent_t* ev, hipEvent_t* lat = nullptr) {
         hipStream_t sd = h->side;
         HIPCHK(h, launch_step(SK_PASS, R, mode, st));
         HIPCHK(h, hipEventRecord(h->ev_fork, st));
-        HIPCHK(h, hipStreamWaitEvent(sd, h->ev_fork, 0));
         const bool aa = h->d.lp.aa != 0;
+        // two sets: the lattice kernel needs nothing from the side stream and
+        // is enqueued first; in place it waits for the refilled values (it
+        // overwrites what the refill reads)
+        if (!aa) {
+            if (lat) HIPCHK(h, hipEventRecord(lat[0], st));
+            HIPCHK(h, launch_step(SK_LATTICE, R, mode, st));
+            if (lat) HIPCHK(h, hipEventRecord(lat[1], st));
+        }
+        HIPCHK(h, hipStreamWaitEvent(sd, h->ev_fork, 0));
         HIPCHK(h, launch_step(SK_PARTICLES, R, mode, sd));
         HIPCHK(h, launch_step(SK_MASK, R, mode, sd));   // in place: and the refilled values
         if (aa) HIPCHK(h, hipEventRecord(h->ev_mask, sd));
@@ -401,12 +409,11 @@ int enqueue_step(lbm_sim* h, hipEvent_t* ev, hipEvent_t* lat = nullptr) {
         // link collection must not wait for it)
         if (!aa) HIPCHK(h, launch_refill_part(R, mode, false, sd));
         HIPCHK(h, hipEventRecord(h->ev_side, sd));
-        // in place the lattice kernel overwrites what the refill reads
-        if (aa) HIPCHK(h, hipStreamWaitEvent(st, h->ev_mask, 0));
-        if (lat) HIPCHK(h, hipEventRecord(lat[0], st));
-        HIPCHK(h, launch_step(SK_LATTICE, R, mode, st));
-        if (lat) HIPCHK(h, hipEventRecord(lat[1], st));
         if (aa) {
+            HIPCHK(h, hipStreamWaitEvent(st, h->ev_mask, 0));
+            if (lat) HIPCHK(h, hipEventRecord(lat[0], st));
+            HIPCHK(h, launch_step(SK_LATTICE, R, mode, st));
+            if (lat) HIPCHK(h, hipEventRecord(lat[1], st));
             HIPCHK(h, launch_step(SK_REFILL, R, mode, st));
             HIPCHK(h, hipStreamWaitEvent(st, h->ev_side, 0));
         } else {
