@@ -7,7 +7,8 @@
 // links of t_n were collected at the end of the step before:
 // (the per-particle kernels below give a particle a wavefront, or a whole
 // block when its window is wide and the particles are few)
-//   k_link_pass     one block per particle, a thread per link: q, wall
+//   k_link_pass     one block per particle (128, 256 or 512 threads by the
+//                   particle size), a thread per link: q, wall
 //                   velocity, Bouzidi bounce-back (Eqs. (9)-(10)) and the
 //                   thermal wall (Eqs. (11)-(12)) written where the lattice
 //                   kernel pulls them; the momentum exchange (Eqs. (13)-(14))
@@ -22,16 +23,19 @@
 //                   collision with buoyancy (Sec. 2.1) of the whole lattice
 //                   (two kernels in place, lattice.hip).
 //   k_refill        per particle: refilling + collision of the newborn nodes
-//                   (Sec. 2.5), over the lattice kernel's output (in place:
-//                   computed before it, stored after it).
+//                   (Sec. 2.5): the values computed (from the state of t_n
+//                   and the owner maps) and stored over the lattice kernel's
+//                   output; a single run computes them on the second stream
+//                   (in place before the lattice kernel, with two sets beside
+//                   it) and stores them after it.
 //   k_links         per particle: the links of t_n+1 from its
 //                   owner map, collected into LDS in the fixed slot order of
 //                   Sec. 3 (one slot per lattice line and direction), ballot
 //                   + prefix count, compacted to the front of the
 //                   particle's own segment of 12 N - 12 entries.
-// k_particles, k_mask_mark and k_links touch nothing k_stream_collide reads
-// or writes, so a single run launches them on a second stream, concurrent
-// with the lattice kernel.
+// k_particles, k_mask_mark, k_links and the refill's compute half write
+// nothing k_stream_collide reads or writes (with two sets), so a single run
+// launches them on a second stream, concurrent with the lattice kernel.
 // Built with -ffp-contract=off: the solid test and link fractions must round
 // exactly as the CPU oracle rounds them.
 #include <hip/hip_runtime.h>
