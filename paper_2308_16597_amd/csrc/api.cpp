@@ -404,10 +404,14 @@ int enqueue_step(lbm_sim* h, hipEvent_t* ev, hipEvent_t* lat = nullptr) {
         HIPCHK(h, launch_step(SK_MASK, R, mode, sd));   // in place: and the refilled values
         if (aa) HIPCHK(h, hipEventRecord(h->ev_mask, sd));
         HIPCHK(h, launch_step(SK_COLLECT, Rn, mode, sd));
-        // two sets: the refilled values last on the side stream (its kernel
-        // needs many registers and starts only as lattice waves retire; the
-        // link collection must not wait for it)
-        if (!aa) HIPCHK(h, launch_refill_part(R, mode, false, sd));
+        // two sets, 2- and 4-byte values: the refilled values last on the side
+        // stream, beside the lattice kernel (their kernel needs many registers;
+        // the link collection must not wait for it).  With 8-byte values the
+        // lattice kernel leaves it no registers: it would start only as lattice
+        // waves retire and slow the lattice kernel by 1 %, so the refill runs
+        // whole after the lattice kernel.
+        const bool split = !aa && h->d.mode != LBM_STORE_F64;
+        if (split) HIPCHK(h, launch_refill_part(R, mode, false, sd));
         HIPCHK(h, hipEventRecord(h->ev_side, sd));
         if (aa) {
             HIPCHK(h, hipStreamWaitEvent(st, h->ev_mask, 0));
@@ -418,7 +422,8 @@ int enqueue_step(lbm_sim* h, hipEvent_t* ev, hipEvent_t* lat = nullptr) {
             HIPCHK(h, hipStreamWaitEvent(st, h->ev_side, 0));
         } else {
             HIPCHK(h, hipStreamWaitEvent(st, h->ev_side, 0));
-            HIPCHK(h, launch_refill_part(R, mode, true, st));
+            if (split) HIPCHK(h, launch_refill_part(R, mode, true, st));
+            else HIPCHK(h, launch_step(SK_REFILL, R, mode, st));
         }
     }
     advance_state(h);

@@ -26,8 +26,8 @@
 //                   (Sec. 2.5): the values computed (from the state of t_n
 //                   and the owner maps) and stored over the lattice kernel's
 //                   output; a single run computes them on the second stream
-//                   (in place before the lattice kernel, with two sets beside
-//                   it) and stores them after it.
+//                   (in place before the lattice kernel; with two sets and
+//                   2- or 4-byte values beside it) and stores them after it.
 //   k_links         per particle: the links of t_n+1 from its
 //                   owner map, collected into LDS in the fixed slot order of
 //                   Sec. 3 (one slot per lattice line and direction), ballot
@@ -803,10 +803,10 @@ __device__ bool refill_node(const Pops<ST<MODE>>& A, int lay, const PT_GLOBAL in
 // 14 values and a flag), REFILL_STORE (into the node's slots of the new
 // state) after the lattice kernel.  In place the split is needed: the
 // lattice kernel overwrites what the stencil pulls read, so the values are
-// computed before it.  An overlapped two-set step of a single run computes
-// them at the end of the side stream, where the kernel runs beside the
-// lattice kernel when the registers let it, and only the store waits on
-// the main stream.  The values are the same in every form.
+// computed before it.  An overlapped two-set step of a single run with 2- or
+// 4-byte values computes them at the end of the side stream, beside the
+// lattice kernel, and only the store waits on the main stream.  The values
+// are the same in every form.
 enum RefillPart { REFILL_TWO_SETS = 0, REFILL_COMPUTE, REFILL_STORE };
 template <int MODE, int PART>
 __device__ __forceinline__ void refill_body(const RunStep& rs, unsigned bid) {
