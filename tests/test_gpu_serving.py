@@ -89,6 +89,32 @@ def test_same_alone_and_in_mix(storage):
         s.close()
 
 
+def test_link_pass_block_sizes_give_the_same_bits():
+    """A run alone takes a link-pass block of 128, 256 or 512 threads by its
+    particle size (windows 12, 18 and 34 here: d = 8, 14, 30), a batch 256
+    for every run; the force and torque sums keep one order whatever the
+    block size, so every field and particle matches bit for bit."""
+    base = dict(nu=0.05, alpha=0.04, gravity=1e-4, beta=0.5, particle_T=1.0, rho_ratio=2.0)
+    runs = [(dict(base, nx=160, ny=80, max_particles=6, max_diameter=8.0),
+             lbm_inputs.rsa_particles(160, 80, 6, 8.0, 3.0, 11), None),
+            (dict(base, nx=128, ny=96, max_particles=4, max_diameter=14.0),
+             lbm_inputs.rsa_particles(128, 96, 4, 14.0, 3.0, 5), None),
+            (dict(base, nx=192, ny=128, max_particles=3, max_diameter=30.0),
+             np.array([[50.3, 60.2, 14.0, 0.02, -0.01, 0.0, 0.001],
+                       [130.6, 70.5, 12.5, -0.03, 0.02, 0.0, -0.002],
+                       [96.0, 25.3, 10.0, 0.0, 0.03, 0.0, 0.0]]), None)]
+    alone = [_make(r) for r in runs]
+    mix = [_make(r) for r in runs]
+    for n in (1, 5, 36):
+        for sim in alone:
+            sim.step(n)
+        lbm.step_many(mix, [n] * len(mix))
+        for r, (a, b) in enumerate(zip(alone, mix)):
+            _same(_state(a), _state(b), f"run {r} after +{n} steps")
+    for sim in alone + mix:
+        sim.close()
+
+
 def test_step_many_argument_errors():
     runs = _runs("f64")
     a, b = _make(runs[0]), _make(runs[1])
