@@ -256,8 +256,11 @@ __device__ __forceinline__ void links_body(const RunStep& rs, unsigned bid) {
 // issued together, after its (arithmetic-only) link fraction.
 constexpr int PASS_CHUNKS = (12 * 100 - 12 + 63) / 64;   // the window edge is at most 100
 
-// One link: fluid node (x, y), direction i towards particle P.
-template <int MODE>
+// One link: fluid node (x, y), direction i towards particle P.  QFIRST:
+// gather only what the branch of q needs (the link pass); otherwise gather
+// both branches' populations without waiting for q (the direct pass, whose
+// threads take their links one after another).
+template <int MODE, bool QFIRST = true>
 __device__ __forceinline__ void link_pass_link(const RunStep& rs, const PState& P, const Shape& sh, int x, int y,
                                                int i, double& hx, double& hy, double& hz) {
     using S = Store<MODE>;
@@ -287,14 +290,16 @@ __device__ __forceinline__ void link_pass_link(const RunStep& rs, const PState& 
     const double dy = (double)y - P.y;
     const double q = link_q_shape(sh, dx, dy, i);
     const bool lo = q <= 0.5;
+    const bool get_lo = !QFIRST || lo, get_hi = !QFIRST || !lo;
     double fi, fib = 0.0, fi1 = 0.0, fib1 = 0.0, fi2 = 0.0, gi = 0.0, gib = 0.0, gi1 = 0.0;
     if (lay != 2) {
         const int si = lay ? ib : i, sib = lay ? i : ib;
         fi = (double)S::ld(F(si) + k);
-        if (lo) {
+        if (get_lo) {
             fi1 = (double)S::ld(F(si) + k1);
             fi2 = (double)S::ld(F(si) + k2);
-        } else {
+        }
+        if (get_hi) {
             fib = (double)S::ld(F(sib) + k);
             fib1 = (double)S::ld(F(sib) + k1);
         }
@@ -310,18 +315,18 @@ __device__ __forceinline__ void link_pass_link(const RunStep& rs, const PState& 
         fi = (double)S::ld(F(sl) + at);
         if (i <= 4) gi = (double)S::ld(F(9 + sl) + at);
         at = pushed_at(lp, x, y, ib, sl);
-        if (!lo) fib = (double)S::ld(F(sl) + at);
+        if (get_hi) fib = (double)S::ld(F(sl) + at);
         if (i <= 4) gib = (double)S::ld(F(9 + sl) + at);
         if (in1) {
             at = pushed_at(lp, x1, y1, i, sl);
-            if (lo) fi1 = (double)S::ld(F(sl) + at);
+            if (get_lo) fi1 = (double)S::ld(F(sl) + at);
             if (i <= 4) gi1 = (double)S::ld(F(9 + sl) + at);
-            if (!lo) {
+            if (get_hi) {
                 at = pushed_at(lp, x1, y1, ib, sl);
                 fib1 = (double)S::ld(F(sl) + at);
             }
         }
-        if (in2 && lo) {
+        if (in2 && get_lo) {
             at = pushed_at(lp, x2, y2, i, sl);
             fi2 = (double)S::ld(F(sl) + at);
         }
@@ -423,7 +428,7 @@ __device__ __forceinline__ void link_pass_direct_body(const RunStep& rs, unsigne
         if (own[d] < 0) continue;
         const PState P = ld_state(rs.Pc + own[d]);
         double hx = 0.0, hy = 0.0, hz = 0.0;
-        link_pass_link<MODE>(rs, P, shape_of(P), x, y, d, hx, hy, hz);
+        link_pass_link<MODE, false>(rs, P, shape_of(P), x, y, d, hx, hy, hz);
         double* Fa = rs.Fa + 4 * (size_t)own[d];
         atomicAdd(Fa + 0, hx);
         atomicAdd(Fa + 1, hy);
