@@ -375,6 +375,11 @@ namespace {
 // kernel waits for that part of the side stream:
 //   main: link pass -> [fork] -> wait(mask) -> lattice -> refill store -> wait(side)
 //   side: wait(fork) -> particles -> mask + refill values -> [mask] -> links of t_n+1 -> [side]
+// FP64 runs with more particles than this compute their refill beside the
+// lattice kernel (measured: 64 000 particles, step 1.72 -> 1.62 ms; with
+// 4800 it went 0.749 -> 0.756 ms).
+constexpr int kSplitRefillParticles = 16384;
+
 int enqueue_step(lbm_sim* h, hipEvent_t* ev, hipEvent_t* lat = nullptr) {
     hipStream_t st = h->stream;
     const RunStep R = current_runstep(h);
@@ -407,10 +412,11 @@ int enqueue_step(lbm_sim* h, hipEvent_t* ev, hipEvent_t* lat = nullptr) {
         // two sets, 2- and 4-byte values: the refilled values last on the side
         // stream, beside the lattice kernel (their kernel needs many registers;
         // the link collection must not wait for it).  With 8-byte values the
-        // lattice kernel leaves it no registers: it would start only as lattice
-        // waves retire and slow the lattice kernel by 1 %, so the refill runs
-        // whole after the lattice kernel.
-        const bool split = !aa && h->d.mode != LBM_STORE_F64;
+        // lattice kernel leaves it no registers: it starts only as lattice
+        // waves retire and slows the lattice kernel by 1.5 %, which a few
+        // thousand particles' refill does not repay (the refill runs whole
+        // after the lattice kernel) and tens of thousands' does.
+        const bool split = !aa && (h->d.mode != LBM_STORE_F64 || h->np > kSplitRefillParticles);
         if (split) HIPCHK(h, launch_refill_part(R, mode, false, sd));
         HIPCHK(h, hipEventRecord(h->ev_side, sd));
         if (aa) {
