@@ -370,6 +370,10 @@ namespace {
 // event operation costs the main stream a few microseconds of idle time):
 //   main: link pass -> [fork] -> lattice -> wait(side) -> refill
 //   side: wait(fork) -> particles -> mask -> links of t_n+1 -> [side]
+// With 2- or 4-byte values (or FP64 and many particles) the refill's values
+// are computed last on the side stream and only stored on the main one:
+//   main: link pass -> [fork] -> lattice -> wait(side) -> refill store
+//   side: wait(fork) -> particles -> mask -> links of t_n+1 -> refill values -> [side]
 // In place the refill's values are computed with the owner map, before the
 // lattice kernel overwrites the state they are pulled from, so the lattice
 // kernel waits for that part of the side stream:
