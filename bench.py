@@ -9,15 +9,27 @@ momentum exchange, particle update, solid map, refilling and the fused
 stream-collide over the whole lattice.  MLUPS counts every lattice node,
 solid included (mesh size x steps / time).
 
+Timing: after the warm-up steps, the timed calls of `--steps` steps are
+rehearsed once untimed (so every step graph they replay is captured before
+timing starts), then each of `--repeats` calls is timed between full
+synchronisations; the value is the median.
+
 Prints one JSON line.  Besides the throughput it carries:
   roofline     the fused stream-collide kernel (the dominant one), timed with
                HIP events around it on the library's stream in steps run as
                the timed ones (particle kernels concurrent on a second
                stream); achieved = algorithmic bytes per launch (every node
                reads and writes its 9 + 5 populations) / mean launch time,
-               against 8 TB/s.
+               against 8 TB/s; beside it a plain copy of the same 14 arrays
+               with the same grid (the copy ceiling).
+  step_roofline  the step's MLUPS against the MLUPS of moving the
+               algorithmic bytes at 8 TB/s.
+  forms        the same workload in the other storage forms (FP32, FP16 and
+               BF16 deviations): step MLUPS and the lattice kernel's fraction.
   cpu_baseline the CPU oracle (single thread, FP64) on a bounded sample of
-               the same workload, timed on this host.
+               the same workload (`--cpu-steps` steps after one untimed) and
+               all 200 steps of the small 256^2 workload, timed on this host,
+               with its CPU model and core counts.
   paper_workload  the paper's own benchmark case (Sec. 2.6.3: closed 4000^2
                cavity, 60 x 80 hot particles of diameter 40, Pr 5, Gr_p 60,
                rho_p/rho_f = 1.1), a short timed run beside the paper's
@@ -86,26 +98,121 @@ def place(run, rows):
     (run.set_particles_ellipse if rows.shape[1] == 8 else run.set_particles)(rows)
 
 
-def cpu_baseline(workload, steps):
-    """The CPU oracle on `steps` steps of the same workload (one thread)."""
+def cpu_info():
+    """Host CPU model, logical CPUs of the host and CPUs this process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return model, os.cpu_count(), usable
+
+
+def oracle_mlups(workload, steps, untimed=1):
+    """MLUPS of the CPU oracle (one thread, FP64) over `steps` steps of a
+    named workload, after `untimed` first-touch steps."""
     import lbm_inputs
     from oracle import Oracle
     from paper_2308_16597_amd import params
     kw = params.workload_params(workload)
     w = params.WORKLOADS[workload]
     okw = {k: v for k, v in kw.items() if k not in ("storage", "max_particles", "max_diameter")}
-    rows = lbm_inputs.workload_particles(w)
     orc = Oracle(**okw)
-    place(orc, rows)
-    orc.step(1)  # first touch of the oracle's arrays, not timed
+    place(orc, lbm_inputs.workload_particles(w))
+    if untimed:
+        orc.step(untimed)
     t0 = time.perf_counter()
     orc.step(steps)
     dt = time.perf_counter() - t0
     orc.close()
-    return dict(value=round(params.mlups(w["nx"] * w["ny"], steps, dt), 4), unit="MLUPS", cores=1,
-                kind="oracle",
-                sample=f"steps 2..{steps + 1} of the {w['nx']}x{w['ny']} workload with {w['n']} "
-                       f"particles (FP64, one thread): {dt:.1f} s")
+    return params.mlups(w["nx"] * w["ny"], steps, dt), dt
+
+
+def cpu_baseline(workload, steps, small_steps):
+    """The CPU oracle on this host (one thread): `steps` steps of the timed
+    workload (the value) and `small_steps` steps of the small 256^2
+    workload, with the CPU model and core counts."""
+    from paper_2308_16597_amd import params
+    w = params.WORKLOADS[workload]
+    model, ncpu, usable = cpu_info()
+    v, dt = oracle_mlups(workload, steps)
+    out = dict(value=round(v, 4), unit="MLUPS", cores=1, kind="oracle",
+               sample=f"steps 2..{steps + 1} of the {w['nx']}x{w['ny']} workload with {w['n']} "
+                      f"particles (FP64, one thread, after one untimed first-touch step): {dt:.1f} s",
+               cpu_model=model, host_cpus=ncpu, usable_cpus=usable, threads=1)
+    if small_steps > 0 and workload != "small":
+        ws = params.WORKLOADS["small"]
+        vs, dts = oracle_mlups("small", small_steps, untimed=0)
+        out["small"] = dict(value=round(vs, 4), unit="MLUPS", steps=small_steps, seconds=round(dts, 2),
+                            workload=f"{ws['nx']}x{ws['ny']} channel, {ws['n']} particles d={ws['d']:g}, "
+                                     f"steps 1..{small_steps}")
+    return out
+
+
+def timed_repeats(sim, steps, repeats):
+    """Device seconds of `repeats` calls of sim.step(steps), each bracketed
+    by a full synchronisation, after one untimed rehearsal of the same calls
+    (which captures the step graph of every step state a call starts from,
+    so no capture falls in a timed call) and a return to the starting step
+    state.  Returns the list of times."""
+    import torch
+    for _ in range(repeats):
+        sim.step(steps)
+    pad = (-repeats * steps) % 6   # the step state repeats every 6 steps
+    if pad:
+        sim.step(pad)
+    sim.sync()
+    out = []
+    for _ in range(repeats):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(steps)
+        sim.sync()
+        torch.cuda.synchronize()
+        out.append(time.perf_counter() - t0)
+    if pad:
+        sim.step(pad)
+    return out
+
+
+def form_line(workload, storage, steps, warmup, repeats, phase_steps):
+    """Throughput of one precision form on the workload: step MLUPS (median
+    of `repeats` timed calls of `steps` steps), the lattice kernel's HBM
+    fraction in the overlapped steps and alone, and the copy ceiling."""
+    import lbm_inputs
+    from paper_2308_16597_amd import lbm, params
+    w = params.WORKLOADS[workload]
+    nx, ny = w["nx"], w["ny"]
+    sim = lbm.Sim(lbm.lbm_params_default(**params.workload_params(workload, lbm.STORE[storage])))
+    place(sim, lbm_inputs.workload_particles(w))
+    sim.step(warmup)
+    sim.sync()
+    dts = timed_repeats(sim, steps, repeats)
+    dt = float(np.median(dts))
+    ph = sim.time_phases(phase_steps)
+    copy_ms = sim.time_copy(10)
+    sim.close()
+    es = STORE_BYTES[storage]
+    alg = nx * ny * 28 * es
+    roof = HBM_PEAK_GBS * 1e9 / (28 * es) / 1e6
+    v = params.mlups(nx * ny, steps, dt)
+    frac = lambda ms: round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)  # noqa: E731
+    line = dict(storage=storage, dtype=STORE_DTYPE[storage], mlups=round(v, 1),
+                ms_per_step=round(dt / steps * 1e3, 5), repeats_mlups=[round(params.mlups(nx * ny, steps, t), 1) for t in dts],
+                roofline_mlups=round(roof, 1), step_frac=round(v / roof, 4),
+                lattice_frac=frac(ph["lattice_overlapped"]), lattice_frac_alone=frac(ph["lattice"]),
+                lattice_ms=round(ph["lattice_overlapped"], 5), link_pass_ms=round(ph["links"], 5),
+                copy_ms=round(copy_ms, 5), copy_frac=frac(copy_ms))
+    log(f"[bench] form {storage}: {line}")
+    return line
 
 
 def describe(name, storage):
@@ -140,12 +247,7 @@ def paper_workload(steps, warmup, storage):
     place(sim, lbm_inputs.workload_particles(w))
     sim.step(warmup)
     sim.sync()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    sim.step(steps)
-    sim.sync()
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
+    dt = timed_repeats(sim, steps, 1)[0]
     links = sim.stats()["links"]
     sim.close()
     v = params.mlups(w["nx"] * w["ny"], steps, dt)
@@ -205,7 +307,14 @@ def main():
     ap.add_argument("--streaming", default="two_sets", choices=["two_sets", "in_place"],
                     help="population layout: two sets (pull) or one set in place (AA pattern)")
     ap.add_argument("--phase-steps", type=int, default=100)
-    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--repeats", type=int, default=5, help="timed calls of --steps steps; the median counts")
+    ap.add_argument("--cpu-steps", type=int, default=5,
+                    help="oracle steps timed on the headline workload (one thread)")
+    ap.add_argument("--cpu-small-steps", type=int, default=200,
+                    help="oracle steps timed on the small 256^2 workload")
+    ap.add_argument("--forms", default="f32,shift_f16,shift_bf16",
+                    help="other storage forms timed beside the headline one (comma list, '' for none)")
+    ap.add_argument("--form-steps", type=int, default=120)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-paper-workload", action="store_true",
@@ -245,16 +354,14 @@ def main():
     sim.sync()
     log(f"[bench] warmup {args.warmup} steps done")
 
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    sim.step(args.steps)
-    sim.sync()
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
+    dts = timed_repeats(sim, args.steps, args.repeats)
+    dt = float(np.median(dts))
     mlups = params.mlups(nx * ny, args.steps, dt)
-    log(f"[bench] timed {args.steps} steps in {dt:.3f} s: {mlups:.1f} MLUPS")
+    log(f"[bench] timed {args.repeats} x {args.steps} steps: "
+        f"{[round(params.mlups(nx * ny, args.steps, t), 1) for t in dts]} MLUPS; median {mlups:.1f}")
 
     phases = sim.time_phases(args.phase_steps)
+    copy_ms = sim.time_copy(10)
     stats = sim.stats()
     owner = sim.fields()["owner"]
     n_fluid = int((owner < 0).sum())
@@ -273,6 +380,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(dt / args.steps * 1e3, 5),
+        "repeats": args.repeats,
+        "repeats_mlups": [round(params.mlups(nx * ny, args.steps, t), 2) for t in dts],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": round(mlups / 1750.0, 4) if args.workload == "e4_cavity" else None,
@@ -297,6 +406,13 @@ def main():
             "bytes_per_launch": alg_bytes,
             "launch_ms": round(lat_ms, 5),
             "launch_ms_alone": round(phases["lattice"], 5),
+            # a plain 14-in / 14-out copy of the same arrays, same grid
+            "copy_ceiling_ms": round(copy_ms, 5),
+            "copy_ceiling_frac": round(alg_bytes / (copy_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        },
+        "step_roofline": {
+            "mlups_at_peak": round(HBM_PEAK_GBS * 1e9 / (28 * es) / 1e6, 1),
+            "frac": round(mlups / (HBM_PEAK_GBS * 1e9 / (28 * es) / 1e6), 4),
         },
         "phases_ms": {k: round(v, 5) for k, v in phases.items()},
         # context only: the paper's single-GPU figure, other hardware and workload
@@ -308,14 +424,17 @@ def main():
     }
     sim.close()
     del sim
+    forms = [f for f in args.forms.split(",") if f and f != args.storage]
+    if forms:
+        out["forms"] = {f: form_line(args.workload, f, args.form_steps, 20, args.repeats, 50) for f in forms}
     if args.workload == "paper_scale" and not args.no_paper_workload:
         out["paper_workload"] = paper_workload(args.paper_steps, 20, args.storage)
     if not args.no_serve:
         out["serving"] = serving(args.serve_requests, args.serve_budget_gib, args.serve_chunk,
                                  args.serve_streaming)
     if not args.no_cpu_baseline:
-        log(f"[bench] cpu baseline: oracle, {args.cpu_steps} steps")
-        out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_steps)
+        log(f"[bench] cpu baseline: oracle, {args.cpu_steps} steps (+ {args.cpu_small_steps} on 256^2)")
+        out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_steps, args.cpu_small_steps)
     print(json.dumps(out), flush=True)
 
 

@@ -55,18 +55,19 @@
 extern "C" {
 #endif
 
-#define LBM_ABI_VERSION 3
+#define LBM_ABI_VERSION 4
 
 typedef struct lbm_sim* lbm_handle;
 
 enum {
     LBM_OK = 0,
     LBM_EINVAL = -1,     /* invalid argument or parameter (checked on the host) */
-    LBM_ENOMEM = -2,     /* device allocation failed, or the arena is too small */
+    LBM_ENOMEM = -2,     /* device allocation failed */
     LBM_EDEVICE = -3,    /* HIP runtime error */
     LBM_ESEED = -4,      /* particle seeding could not place every particle */
     LBM_EUNSTABLE = -5,  /* the run became non-finite or a particle moved too fast */
     LBM_ESTATE = -6,     /* call not allowed in the handle's current state */
+    LBM_EBUDGET = -7,    /* the caller's arena (device budget) is smaller than the run needs */
 };
 
 /* Population storage.  F64 computes in FP64; the others compute in FP32.
@@ -145,22 +146,45 @@ int32_t lbm_abi_version(void);
 void lbm_params_default(lbm_params* p);
 
 /* Device bytes a handle with these parameters needs (0 if invalid); the
- * size lbm_create_in_arena requires. */
+ * size lbm_create_in_arena requires, and what a server admitting runs into a
+ * fixed device budget compares against it.  The largest parts: two sets of
+ * 9 + 5 population arrays over the padded lattice (Sec. 2.1; one set in
+ * place), two owner maps, and max_particles link segments of 12 N - 12
+ * entries (Sec. 3). */
 size_t lbm_bytes_required(const lbm_params* p);
 
-/* Create a handle: validate on the host, allocate device memory with
- * hipMalloc, and initialise the fluid at rest (rho0, T_fluid0) with no
- * particles.  hip_stream is a hipStream_t (NULL: the handle creates its own
- * stream).  On failure *out is NULL and lbm_last_error(NULL) explains. */
+/* Admission of a run into a device budget: LBM_OK if a handle with these
+ * parameters fits budget_bytes (lbm_bytes_required), LBM_EBUDGET if not,
+ * LBM_EINVAL for invalid parameters (message: lbm_last_error(NULL)).  Host
+ * only. */
+int lbm_check_budget(const lbm_params* p, size_t budget_bytes);
+
+/* Dynamic LDS bytes one block of the link collection (Sec. 3) requests for
+ * these parameters, the largest over 1..max_particles particles (0 if
+ * invalid or without particles).  The library keeps it within 64 KiB: where
+ * four particles' windows would not fit one block, each particle takes a
+ * whole block.  Host only. */
+size_t lbm_collect_lds_bytes(const lbm_params* p);
+
+/* Create a handle for one run of the method of Secs. 2-3: validate on the
+ * host (relaxation times above 1/2 follow from nu, alpha > 0, Eqs. (5)-(6);
+ * lattice of at least 8 x 8; particle windows of Sec. 3 no wider than the
+ * lattice; a known storage mode), allocate device memory with hipMalloc, and
+ * initialise the fluid at rest (rho0, T_fluid0) with no particles.
+ * hip_stream is a hipStream_t (NULL: the handle creates its own stream).
+ * On failure *out is NULL and lbm_last_error(NULL) explains: LBM_EINVAL for
+ * invalid parameters, LBM_ENOMEM when hipMalloc fails. */
 int lbm_create(const lbm_params* p, void* hip_stream, lbm_handle* out);
 
 /* Same, carving every device buffer out of the caller's allocation
- * [dev_ptr, dev_ptr + bytes), which must hold lbm_bytes_required(p) bytes,
- * be 256-byte aligned and outlive the handle. */
+ * [dev_ptr, dev_ptr + bytes), which must be 256-byte aligned (else
+ * LBM_EINVAL), hold lbm_bytes_required(p) bytes (else LBM_EBUDGET) and
+ * outlive the handle.  Allocates no device memory. */
 int lbm_create_in_arena(const lbm_params* p, void* dev_ptr, size_t bytes, void* hip_stream,
                         lbm_handle* out);
 
-/* Wait for the stream and release the handle (and the memory it allocated). */
+/* Wait for the stream and release the handle (and the memory it
+ * allocated); the graphs and batch tables that refer to it are dropped. */
 void lbm_destroy(lbm_handle h);
 
 /* Message of the last error on h; with h == NULL, of the last failed
@@ -215,10 +239,15 @@ int lbm_set_equilibrium(lbm_handle h, const double* rho, const double* ux, const
 enum { LBM_LINKS_INDIRECT = 0, LBM_LINKS_DIRECT = 1 };
 int lbm_set_addressing(lbm_handle h, int32_t mode);
 
-/* Enqueue nsteps steps on the handle's stream and return.  Within a step,
- * the particle update, the owner map of t_n+1 and the link collection of
- * t_n+1 run on a second stream of the library's, concurrently with the
- * lattice update; each step ends joined on the handle's stream. */
+/* Enqueue nsteps steps of the method (one step: the link pass of Secs.
+ * 2.3-2.4 and 3, the particle update of Sec. 2.2, the solid map, the
+ * stream-collide of Sec. 2.1 and the refilling of Sec. 2.5) on the handle's
+ * stream and return.  Within a step, the particle update, the owner map of
+ * t_n+1 and the link collection of t_n+1 run on a second stream of the
+ * library's, concurrently with the lattice update; each step ends joined on
+ * the handle's stream.  Whole 6-step cycles replay a HIP graph captured once
+ * per step state (the state repeats every 6 steps) and kept until the
+ * particles change.  LBM_EINVAL for nsteps < 0. */
 int lbm_step(lbm_handle h, int32_t nsteps);
 
 /* Advance count runs together, run i by nsteps[i] steps, for serving many
@@ -241,7 +270,9 @@ int lbm_step(lbm_handle h, int32_t nsteps);
  * of a run surface at its next waiting call. */
 int lbm_step_many(lbm_handle* hs, int32_t count, const int32_t* nsteps, void* stream);
 
-/* Wait for the stream; report deferred device errors. */
+/* Wait for the stream; report deferred device errors (LBM_EUNSTABLE: a
+ * non-finite population, a particle faster than half a lattice spacing per
+ * step, a link segment or neighbour cell overflowing). */
 int lbm_sync(lbm_handle h);
 
 /* Pre-collision macroscopics at the current time (Sec. 2.1): rho, u with
@@ -249,9 +280,10 @@ int lbm_sync(lbm_handle h);
  * fluid, else the particle index). */
 int lbm_read_fields(lbm_handle h, double* rho, double* ux, double* uy, double* T, int32_t* owner);
 
-/* Particle state: n rows of x, y, r, ux, uy, theta, omega, Fx, Fy, Tz, where
- * (Fx, Fy, Tz) is the momentum-exchange force and torque of the last step.
- * rows10 may be NULL to query *n only. */
+/* Particle state (Sec. 2.2): n rows of x, y, r, ux, uy, theta, omega, Fx,
+ * Fy, Tz, where (Fx, Fy, Tz) is the momentum-exchange force and torque of
+ * the last step (Sec. 2.4, Eqs. (13)-(14)).  rows10 may be NULL to query *n
+ * only.  Waits. */
 int lbm_read_particles(lbm_handle h, double* rows10, int32_t* n);
 
 /* The fluid-particle links of the current state (Sec. 3), as the library
@@ -272,10 +304,32 @@ int lbm_read_links(lbm_handle h, int32_t* node, int32_t* dir, int32_t* particle,
  * Advances the run by 2 nsteps steps.  Waits. */
 int lbm_time_phases(lbm_handle h, int32_t nsteps, double* ms_out);
 
-/* Counters: out[0] steps done, out[1] links of the current state (those
- * the next step uses), out[2] particles, out[3] lattice nodes, out[4]
- * device bytes held.  Waits. */
-int lbm_stats(lbm_handle h, double* out5);
+/* Bandwidth ceiling of the lattice update (Sec. 2.1): enqueue one untimed
+ * and reps timed plain copies of the run's 9 + 5 population arrays (the
+ * bytes one stream-collide moves, no arithmetic), with the stream-collide
+ * kernel's grid and non-temporal loads and stores, into the set the next
+ * step writes whole (in place: onto itself); *ms_out receives the mean
+ * device milliseconds per copy.  The state is unchanged.  Waits. */
+int lbm_time_copy(lbm_handle h, int32_t reps, double* ms_out);
+
+/* Counters, out[LBM_NSTATS]: steps done; links of the current state (those
+ * the next step uses, Sec. 3); newborn nodes refilled (Sec. 2.5) since the
+ * particles were set; device milliseconds per step of the last lbm_step
+ * call (0 before one); the HBM rate that implies for the lattice update's
+ * algorithmic bytes (28 population values read and written per node,
+ * GB/s); particles; lattice nodes; device bytes held.  Waits. */
+enum {
+    LBM_STAT_STEPS = 0,
+    LBM_STAT_LINKS = 1,
+    LBM_STAT_NEWBORN = 2,
+    LBM_STAT_MS_PER_STEP = 3,
+    LBM_STAT_GBPS = 4,
+    LBM_STAT_PARTICLES = 5,
+    LBM_STAT_NODES = 6,
+    LBM_STAT_DEVICE_BYTES = 7,
+    LBM_NSTATS = 8
+};
+int lbm_stats(lbm_handle h, double* out);
 
 #ifdef __cplusplus
 }

@@ -222,9 +222,14 @@ int create_common(const lbm_params* p, void* dev_ptr, size_t bytes, void* stream
     h->p = *p;
     h->L = make_layout(*p);
     if (dev_ptr) {
-        if (bytes < h->L.total || ((uintptr_t)dev_ptr % kAlign) != 0) {
+        if (((uintptr_t)dev_ptr % kAlign) != 0) {
             delete h;
-            return fail(nullptr, LBM_ENOMEM, "arena of %zu bytes (need %zu, 256-byte aligned)", bytes, h->L.total);
+            return fail(nullptr, LBM_EINVAL, "arena not 256-byte aligned");
+        }
+        if (bytes < h->L.total) {
+            const size_t need = h->L.total;
+            delete h;
+            return fail(nullptr, LBM_EBUDGET, "arena of %zu bytes, the run needs %zu", bytes, need);
         }
         h->base = (char*)dev_ptr;
     } else {
@@ -252,6 +257,9 @@ int create_common(const lbm_params* p, void* dev_ptr, size_t bytes, void* stream
         if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_side, hipEventDisableTiming);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_mask, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_order, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreate(&h->ev_t0);
+        if (e == hipSuccess) e = hipEventCreate(&h->ev_t1);
         if (e != hipSuccess) {
             lbm_destroy(h);
             return fail(nullptr, LBM_EDEVICE, "side stream / events: %s", hipGetErrorString(e));
@@ -446,17 +454,23 @@ void* scratch_of(lbm_sim* h) {
     return h->d.lp.aa ? (void*)(h->base + h->L.off_fscratch) : h->d.S[1 - h->cur][0];
 }
 
-void drop_cycle_graph(lbm_sim* h) {
-    if (h->cycle_graph) (void)hipGraphExecDestroy(h->cycle_graph);
-    h->cycle_graph = nullptr;
-    h->cycle_state = -1;
+void drop_cycle_graphs(lbm_sim* h) {
+    for (hipGraphExec_t& g : h->cycle_graph) {
+        if (g) (void)hipGraphExecDestroy(g);
+        g = nullptr;
+    }
 }
 
-// Capture six overlapped steps from the current state into h->cycle_graph
-// (nothing runs; the state is restored afterwards).
+// Capture six overlapped steps from the current state into the graph slot
+// of that state (nothing runs; the state is restored afterwards).  A graph
+// is kept per state (at most 6 are reachable from one start), so step
+// counts that are not multiples of 6 do not recapture on the next call.
 int capture_cycle(lbm_sim* h) {
-    drop_cycle_graph(h);
     const int cur = h->cur, ring = h->ring, bp = h->bin_parity;
+    const int state = state_index(cur, ring, bp);
+    hipGraphExec_t& slot = h->cycle_graph[state];
+    if (slot) (void)hipGraphExecDestroy(slot);
+    slot = nullptr;
     const int64_t steps = h->steps;
     HIPCHK(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeRelaxed));
     int rc = LBM_OK;
@@ -471,14 +485,13 @@ int capture_cycle(lbm_sim* h) {
         if (g) (void)hipGraphDestroy(g);
         return rc;
     }
-    if (e == hipSuccess) e = hipGraphInstantiate(&h->cycle_graph, g, nullptr, nullptr, 0);
+    if (e == hipSuccess) e = hipGraphInstantiate(&slot, g, nullptr, nullptr, 0);
     if (g) (void)hipGraphDestroy(g);
     if (e != hipSuccess) {
-        h->cycle_graph = nullptr;
+        slot = nullptr;
         return hip_fail(h, e, "capture of the step cycle");
     }
-    h->cycle_state = state_index(cur, ring, bp);
-    h->cycle_generation = h->generation;
+    h->cycle_generation[state] = h->generation;
     return LBM_OK;
 }
 
@@ -531,9 +544,9 @@ void lbm_destroy(lbm_handle h) {
     forget_batches(h);
     if (h->stream) (void)hipStreamSynchronize(h->stream);
     if (h->side) (void)hipStreamSynchronize(h->side);
-    drop_cycle_graph(h);
+    drop_cycle_graphs(h);
     if (h->own_mem && h->base) (void)hipFree(h->base);
-    for (hipEvent_t e : {h->ev_fork, h->ev_side, h->ev_mask})
+    for (hipEvent_t e : {h->ev_fork, h->ev_side, h->ev_mask, h->ev_order, h->ev_t0, h->ev_t1})
         if (e) (void)hipEventDestroy(e);
     if (h->side) (void)hipStreamDestroy(h->side);
     if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
@@ -756,19 +769,21 @@ int lbm_set_equilibrium(lbm_handle h, const double* rho, const double* ux, const
 int lbm_step(lbm_handle h, int32_t nsteps) {
     if (!h) return LBM_EINVAL;
     if (nsteps < 0) return fail(h, LBM_EINVAL, "negative step count");
+    if (nsteps == 0) return LBM_OK;
+    HIPCHK(h, hipEventRecord(h->ev_t0, h->stream));
     int32_t s = 0;
-    // whole 6-step cycles (the step state repeats every 6 steps) replay a
-    // captured graph of the overlapped schedule once there are two of them
-    // or the graph for this state already exists
+    // whole 6-step cycles (the step state repeats every 6 steps) replay the
+    // graph captured for the current state, captured once there are two
+    // cycles to run or kept from an earlier call
     const int state = state_index(h->cur, h->ring, h->bin_parity);
-    const bool have = h->cycle_graph && h->cycle_state == state && h->cycle_generation == h->generation;
+    const bool have = h->cycle_graph[state] && h->cycle_generation[state] == h->generation;
     if (nsteps >= 12 || (have && nsteps >= 6)) {
         if (!have) {
             int rc = capture_cycle(h);
             if (rc != LBM_OK) return rc;
         }
         for (; nsteps - s >= 6; s += 6) {
-            HIPCHK(h, hipGraphLaunch(h->cycle_graph, h->stream));
+            HIPCHK(h, hipGraphLaunch(h->cycle_graph[state], h->stream));
             h->steps += 6;   // six steps return the state to where it was
         }
     }
@@ -776,6 +791,8 @@ int lbm_step(lbm_handle h, int32_t nsteps) {
         int rc = enqueue_step(h, nullptr);
         if (rc != LBM_OK) return rc;
     }
+    HIPCHK(h, hipEventRecord(h->ev_t1, h->stream));
+    h->timed_steps = nsteps;
     return LBM_OK;
 }
 
@@ -945,21 +962,81 @@ int lbm_time_phases(lbm_handle h, int32_t nsteps, double* ms_out) {
     return check_status(h);
 }
 
-int lbm_stats(lbm_handle h, double* out5) {
-    if (!h || !out5) return LBM_EINVAL;
+int lbm_stats(lbm_handle h, double* out) {
+    if (!h || !out) return LBM_EINVAL;
     std::vector<int2> seg((size_t)h->np);
+    unsigned long long newborn = 0;
     if (h->np > 0)
         HIPCHK(h, hipMemcpyAsync(seg.data(), h->d.seg, seg.size() * sizeof(int2), hipMemcpyDeviceToHost,
                                  h->stream));
+    HIPCHK(h, hipMemcpyAsync(&newborn, newborn_counter(h->d.status), sizeof newborn, hipMemcpyDeviceToHost,
+                             h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
     double nl = 0.0;
     for (const int2& sg : seg) nl += sg.y;
-    out5[0] = (double)h->steps;
-    out5[1] = nl;
-    out5[2] = (double)h->np;
-    out5[3] = (double)h->p.nx * h->p.ny;
-    out5[4] = (double)h->L.total;
+    double ms = 0.0;
+    if (h->timed_steps > 0) {
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, h->ev_t0, h->ev_t1) == hipSuccess) ms = (double)t / h->timed_steps;
+        else (void)hipGetLastError();
+    }
+    const double nodes = (double)h->p.nx * h->p.ny;
+    // algorithmic bytes of a lattice update: 9 + 5 populations read and written
+    const double bytes_per_step = nodes * 28.0 * (double)elem_size(h->p.storage);
+    out[LBM_STAT_STEPS] = (double)h->steps;
+    out[LBM_STAT_LINKS] = nl;
+    out[LBM_STAT_NEWBORN] = (double)newborn;
+    out[LBM_STAT_MS_PER_STEP] = ms;
+    out[LBM_STAT_GBPS] = ms > 0.0 ? bytes_per_step / (ms * 1e-3) / 1e9 : 0.0;
+    out[LBM_STAT_PARTICLES] = (double)h->np;
+    out[LBM_STAT_NODES] = nodes;
+    out[LBM_STAT_DEVICE_BYTES] = (double)h->L.total;
     return LBM_OK;
+}
+
+int lbm_check_budget(const lbm_params* p, size_t budget_bytes) {
+    std::string why;
+    if (!validate(p, why)) return fail(nullptr, LBM_EINVAL, "%s", why.c_str());
+    const size_t need = make_layout(*p).total;
+    if (need > budget_bytes) return fail(nullptr, LBM_EBUDGET, "the run needs %zu bytes, the budget is %zu", need, budget_bytes);
+    return LBM_OK;
+}
+
+int lbm_time_copy(lbm_handle h, int32_t reps, double* ms_out) {
+    if (!h || !ms_out || reps <= 0) return h ? fail(h, LBM_EINVAL, "invalid arguments") : LBM_EINVAL;
+    // the current state A is read; B (the set the next step writes whole)
+    // receives the copy; in place the single set is copied onto itself
+    const RunStep R = current_runstep(h);
+    const unsigned nb = run_blocks(GC_LAT, R.lp);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = LBM_OK;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = fail(h, LBM_EDEVICE, "hipEventCreate");
+    if (rc == LBM_OK && launch_copy(R, h->d.mode, nb, h->stream) != hipSuccess) rc = fail(h, LBM_EDEVICE, "copy launch");
+    if (rc == LBM_OK && hipEventRecord(e0, h->stream) != hipSuccess) rc = fail(h, LBM_EDEVICE, "hipEventRecord");
+    for (int32_t r = 0; r < reps && rc == LBM_OK; ++r)
+        if (launch_copy(R, h->d.mode, nb, h->stream) != hipSuccess) rc = fail(h, LBM_EDEVICE, "copy launch");
+    if (rc == LBM_OK && hipEventRecord(e1, h->stream) != hipSuccess) rc = fail(h, LBM_EDEVICE, "hipEventRecord");
+    if (rc == LBM_OK && hipEventSynchronize(e1) != hipSuccess) rc = fail(h, LBM_EDEVICE, "hipEventSynchronize");
+    float ms = 0.f;
+    if (rc == LBM_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = fail(h, LBM_EDEVICE, "hipEventElapsedTime");
+    if (rc == LBM_OK) *ms_out = (double)ms / reps;
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    return rc;
+}
+
+size_t lbm_collect_lds_bytes(const lbm_params* p) {
+    std::string why;
+    if (!validate(p, why) || p->max_particles <= 0) return 0;
+    const int nwin = window_cap(p->max_diameter);
+    LP lp{};
+    lp.nwin = nwin;
+    size_t worst = 0;
+    for (int n : {1, p->max_particles}) {
+        lp.lpp = lanes_per_particle(nwin, n);
+        worst = std::max(worst, links_block_lds(lp));
+    }
+    return worst;
 }
 
 }  // extern "C"

@@ -258,6 +258,23 @@ __global__ __launch_bounds__(LAT_BLOCK) void k_stream_collide_aa_b(const RunStep
     else stream_collide_aa_body<MODE, false>(tab[m.x], m.y);
 }
 
+// A plain copy of the 14 population arrays A -> B with the lattice kernel's
+// grid, node per thread, non-temporal loads and stores: the HBM ceiling the
+// lattice kernel is compared with (it moves the same bytes, no arithmetic).
+template <int MODE>
+__global__ __launch_bounds__(LAT_BLOCK) void k_copy14(RunStep rs) {
+    int x, y;
+    lattice_node<false>(rs.lp, blockIdx.x, x, y);
+    if (x >= rs.lp.nx || y >= rs.lp.ny) return;
+    const size_t k = (size_t)y * rs.lp.pitch + x;
+#pragma unroll
+    for (int i = 0; i < 14; ++i) {
+        const PT_GLOBAL ST<MODE>* a = (const PT_GLOBAL ST<MODE>*)rs.A[i];
+        PT_GLOBAL ST<MODE>* b = (PT_GLOBAL ST<MODE>*)rs.B[i];
+        __builtin_nontemporal_store(__builtin_nontemporal_load(a + k), b + k);
+    }
+}
+
 // -------------------------------------------------------------- launchers ----
 
 static dim3 lattice_grid(const LP& lp, int rows) { return dim3((lp.nx + LAT_BLOCK - 1) / LAT_BLOCK, rows); }
@@ -270,6 +287,11 @@ hipError_t launch_lattice(const RunStep& R, int mode, unsigned nblocks, hipStrea
     } else {
         PTLBM_DISPATCH(mode, (k_stream_collide_aa<M, false><<<nblocks, LAT_BLOCK, 0, st>>>(R)));
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(const RunStep& R, int mode, unsigned nblocks, hipStream_t st) {
+    PTLBM_DISPATCH(mode, (k_copy14<M><<<nblocks, LAT_BLOCK, 0, st>>>(R)));
     return hipGetLastError();
 }
 

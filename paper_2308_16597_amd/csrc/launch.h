@@ -90,11 +90,19 @@ enum StatusBits : unsigned {
     ST_CAND_OVERFLOW = 32u, // more newborn nodes for one particle than its candidate list holds
 };
 
+// The status block of a run (64 bytes, cleared when particles are set):
+// word 0 the StatusBits, bytes 8..15 the count of newborn nodes refilled.
+__host__ __device__ inline unsigned long long* newborn_counter(unsigned* status) {
+    return (unsigned long long*)(status + 2);
+}
+
 // Blocks one run needs for a kernel of class c.  The per-particle kernels
 // give each particle a wavefront (4 per block), or the whole block of 256
 // (lp.lpp) when its window is 32 nodes wide or more and there are at most
 // 1024 particles.
 unsigned run_blocks(int c, const LP& lp);
+// Dynamic LDS of one block of the link collection is kept within this.
+constexpr size_t kLinksLdsLimit = 65536;
 int lanes_per_particle(int nwin, int np);
 int pass_threads(int nwin, int np);
 size_t links_block_lds(const LP& lp);
@@ -103,6 +111,8 @@ hipError_t launch_step(int k, const RunStep& R, int mode, hipStream_t st);
 // The lattice kernel alone (lattice.hip), for one run or batched (two-set
 // or in place, at each run's parity).
 hipError_t launch_lattice(const RunStep& R, int mode, unsigned nblocks, hipStream_t st);
+// A plain copy of the run's 14 population arrays A -> B (the HBM ceiling).
+hipError_t launch_copy(const RunStep& R, int mode, unsigned nblocks, hipStream_t st);
 hipError_t launch_lattice_batch(const RunStep* tab, const uint2* bmap, unsigned nblocks, int mode, bool aa,
                                 hipStream_t st);
 // The two halves of the split refill of one run (store = false: compute).

@@ -844,6 +844,11 @@ __device__ __forceinline__ void refill_body(const RunStep& rs, unsigned bid) {
         }
         const int lay = lp.aa ? 1 + rs.parity : 0;
         const bool mine = refill_node<MODE>(A, lay, gl(rs.Ocur), gl(rs.Onext), P1, sh, p, x, y, lp, args_cc<R>(lp), s, t);
+        {   // newborn nodes refilled since the particles were set (one atomic per wavefront)
+            const unsigned long long m = __ballot(mine);
+            if (m && (threadIdx.x & 63) == (unsigned)(__ffsll((long long)__ballot(1)) - 1))
+                atomicAdd(newborn_counter(rs.status), (unsigned long long)__popcll(m));
+        }
         if (PART == REFILL_TWO_SETS) {
             if (mine) store_node<S>(B, lp, args_cc<R>(lp), x, y, s, t);
         } else {
@@ -925,7 +930,14 @@ __global__ void k_link_q(const PState* __restrict__ Pc, const uint2* __restrict_
 // too few particles to fill the GPU with wavefronts (with thousands of
 // particles the wavefronts already do, and whole blocks would take more of
 // the GPU from the lattice kernel running beside them).
-int lanes_per_particle(int nwin, int np) { return nwin >= 32 && np <= 1024 ? 256 : 64; }
+// The link collection keeps one particle's window, slots and list in LDS
+// (links_wave_lds); four wavefront-particles share a block's LDS, so where
+// four of them would exceed 64 KiB (windows of about 50 nodes and more) a
+// particle takes the whole block instead.
+int lanes_per_particle(int nwin, int np) {
+    if (nwin >= 32 && np <= 1024) return 256;
+    return 4 * links_wave_lds(nwin) > kLinksLdsLimit ? 256 : 64;
+}
 // Threads of a single run's link-pass block: 128 where that covers about
 // three quarters of the segment (12 N - 12 slots for window edge N; a disk
 // of diameter d has about 0.7 of that many links), so that few lanes idle;

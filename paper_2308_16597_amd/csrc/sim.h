@@ -38,6 +38,7 @@ struct lbm_sim {
     hipStream_t side = nullptr;  // particle kernels, concurrent with the lattice kernel
     hipEvent_t ev_fork = nullptr, ev_side = nullptr;
     hipEvent_t ev_mask = nullptr;  // in place: the owner map and refilled values of t_n+1 are ready
+    hipEvent_t ev_order = nullptr; // orders another stream after the work on this handle's stream
     char* base = nullptr;
     bool own_mem = false;
     int cur = 0;         // time level holding the current (post-collision) state; in place its parity
@@ -46,9 +47,13 @@ struct lbm_sim {
     int np = 0;
     int64_t steps = 0;
     uint64_t generation = 0;  // bumped whenever the particle count changes
-    hipGraphExec_t cycle_graph = nullptr;  // six overlapped steps from cycle_state
-    int cycle_state = -1;
-    uint64_t cycle_generation = 0;
+    // six overlapped steps captured from each step state (state_index), for
+    // the particle generation they were captured in
+    hipGraphExec_t cycle_graph[12] = {};
+    uint64_t cycle_generation[12] = {};
+    // device time of the last lbm_step call (lbm_stats)
+    hipEvent_t ev_t0 = nullptr, ev_t1 = nullptr;
+    int32_t timed_steps = 0;
     std::string err;
 };
 

@@ -25,11 +25,13 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libptlbm.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "lbm.h")
 
-LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_ESEED, LBM_EUNSTABLE, LBM_ESTATE = 0, -1, -2, -3, -4, -5, -6
+LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_ESEED, LBM_EUNSTABLE, LBM_ESTATE, LBM_EBUDGET = \
+    0, -1, -2, -3, -4, -5, -6, -7
 STORE = {"f64": 0, "f32": 1, "shift_f32": 2, "shift_f16": 3, "shift_bf16": 4}
 STREAMING = {"two_sets": 0, "in_place": 1}
 LBM_LINKS_INDIRECT, LBM_LINKS_DIRECT = 0, 1
 PHASES = ("links", "particles", "mask", "lattice", "refill", "collect")
+STATS = ("steps", "links", "newborn", "ms_per_step", "gbps", "particles", "nodes", "bytes")
 
 _d, _i = ctypes.c_double, ctypes.c_int32
 
@@ -63,6 +65,9 @@ def _load():
     L.lbm_params_default.restype = None
     L.lbm_bytes_required.argtypes = [P(LbmParams)]
     L.lbm_bytes_required.restype = ctypes.c_size_t
+    L.lbm_check_budget.argtypes = [P(LbmParams), ctypes.c_size_t]
+    L.lbm_collect_lds_bytes.argtypes = [P(LbmParams)]
+    L.lbm_collect_lds_bytes.restype = ctypes.c_size_t
     L.lbm_create.argtypes = [P(LbmParams), vp, P(vp)]
     L.lbm_create_in_arena.argtypes = [P(LbmParams), vp, ctypes.c_size_t, vp, P(vp)]
     L.lbm_destroy.argtypes = [vp]
@@ -83,6 +88,7 @@ def _load():
     L.lbm_read_links.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int64, P(ctypes.c_int64)]
     L.lbm_time_phases.argtypes = [vp, _i, vp]
     L.lbm_stats.argtypes = [vp, vp]
+    L.lbm_time_copy.argtypes = [vp, _i, vp]
     return L
 
 
@@ -131,6 +137,16 @@ def lbm_params_default(**overrides):
 
 def lbm_bytes_required(p):
     return _lib.lbm_bytes_required(ctypes.byref(p))
+
+
+def lbm_check_budget(p, budget_bytes):
+    """LBM_OK if a run with these parameters fits budget_bytes of device
+    memory, LBM_EBUDGET if not, LBM_EINVAL for invalid parameters."""
+    return _lib.lbm_check_budget(ctypes.byref(p), int(budget_bytes))
+
+
+def lbm_collect_lds_bytes(p):
+    return _lib.lbm_collect_lds_bytes(ctypes.byref(p))
 
 
 def lbm_create(p, stream=None):
@@ -241,10 +257,19 @@ def lbm_time_phases(h, nsteps):
 
 
 def lbm_stats(h):
-    out = np.zeros(5)
+    out = np.zeros(len(STATS))
     _check(_lib.lbm_stats(h, _ptr(out)), h)
-    return dict(steps=int(out[0]), links=int(out[1]), particles=int(out[2]), nodes=int(out[3]),
-                bytes=int(out[4]))
+    d = dict(zip(STATS, out.tolist()))
+    for k in ("steps", "links", "newborn", "particles", "nodes", "bytes"):
+        d[k] = int(d[k])
+    return d
+
+
+def lbm_time_copy(h, reps):
+    """Mean device ms of a plain copy of the run's 14 population arrays."""
+    out = np.zeros(1)
+    _check(_lib.lbm_time_copy(h, int(reps), _ptr(out)), h)
+    return float(out[0])
 
 
 # --- convenience wrapper -----------------------------------------------------
@@ -338,3 +363,6 @@ class Sim:
 
     def stats(self):
         return lbm_stats(self._h)
+
+    def time_copy(self, reps=10):
+        return lbm_time_copy(self._h, reps)

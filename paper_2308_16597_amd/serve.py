@@ -124,9 +124,11 @@ class Server:
                 req = requests[i]
                 p, capped = request_params(req, self.storage, self.streaming)
                 need = lbm.lbm_bytes_required(p)
-                if need == 0 or need > self.arena.nbytes:
+                rc = lbm.lbm_check_budget(p, self.arena.nbytes)
+                if rc != lbm.LBM_OK:   # invalid, or larger than the whole budget (LBM_EBUDGET)
                     queue.pop(0)
-                    records[i] = dict(rid=req["rid"], status="rejected", arrival=arrivals[i])
+                    why = "over budget" if rc == lbm.LBM_EBUDGET else "invalid parameters"
+                    records[i] = dict(rid=req["rid"], status=f"rejected: {why}", arrival=arrivals[i])
                     continue
                 got = self.arena.alloc(need)
                 if got is None:
