@@ -270,6 +270,26 @@ int lbm_step(lbm_handle h, int32_t nsteps);
  * of a run surface at its next waiting call. */
 int lbm_step_many(lbm_handle* hs, int32_t count, const int32_t* nsteps, void* stream);
 
+/* lbm_step_many for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same batched kernels and the same bits, launched one by
+ * one (no graph), from run tables and block maps written into a fixed
+ * device array of 8 MiB that the library holds, one per GPU, until the
+ * process ends.  No hipMalloc, hipFree or graph instantiation is made;
+ * the first call on a GPU looks the array up and creates two events.
+ *   hs, nsteps, stream  as for lbm_step_many; at most 64 runs per call.
+ * The tables of the runs with steps must fit the array (3.8 KiB per run,
+ * plus 8 bytes per block of each kernel: a block per 256 lattice nodes of
+ * the padded rows, per particle, and per 1 to 4 particles, e.g. 64 runs of
+ * 1024 x 2048 with 400 particles each take 4.5 MiB): a call that needs more
+ * fails with LBM_EINVAL before enqueuing anything.  Every call on one GPU rewrites that GPU's array:
+ * calls that overlap on one GPU (two host threads, or the same call
+ * enqueued on two streams that run concurrently) race on it; calls in
+ * sequence, on one stream or on streams ordered one after the other, are
+ * safe.  The host waits, before rewriting its copy of the tables, until the
+ * previous upload from it has completed. */
+int lbm_step_many_noalloc(lbm_handle* hs, int32_t count, const int32_t* nsteps, void* stream);
+
 /* Wait for the stream; report deferred device errors (LBM_EUNSTABLE: a
  * non-finite population, a particle faster than half a lattice spacing per
  * step, a link segment or neighbour cell overflowing). */

@@ -4,7 +4,9 @@
 //
 // lbm_step_many keeps the device image of a batch (its run tables and block
 // maps) in memory of its own and captures one 6-step cycle of the batch as a
-// HIP graph, both cached per batch composition.
+// HIP graph, both cached per batch composition.  lbm_step_many_noalloc
+// enqueues the same kernels launch by launch from an image it writes into a
+// fixed device array, for callers that cannot allocate.
 //
 // The step state of a run -- time level, particle ring slot and cell-grid
 // parity -- repeats every 6 steps, so a batch is fully described by its
@@ -296,6 +298,50 @@ int run_segment(Batch& b, int64_t L, hipStream_t S, lbm_sim* herr) {
     return LBM_OK;
 }
 
+// ----------------------------------------- lbm_step_many_noalloc (fixed) ----
+
+constexpr size_t kScratchBytes = (size_t)8 << 20;
+constexpr int kMaxNoAllocRuns = 64;
+constexpr int kMaxDevices = 64;
+
+}  // namespace
+
+// Device image of lbm_step_many_noalloc: the run tables and block maps of
+// the batch segment being stepped.  Each GPU the library runs on holds its
+// own copy until the process ends; every call on a GPU overwrites it.
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+namespace {
+
+struct NoAllocDevice {
+    char* scratch = nullptr;         // device address of `scratch` on this GPU
+    hipEvent_t copied = nullptr;     // the last upload has read the host image
+    hipEvent_t done = nullptr;       // the last call's work on its stream
+};
+NoAllocDevice g_noalloc[kMaxDevices];
+// host image of one segment, rewritten only after its last upload completed
+alignas(256) char g_host_image[kScratchBytes];
+
+// Set-up on the current device (its first call there): the device address
+// of `scratch` (in host code the array's name is no device address), and
+// two events.
+int noalloc_device(NoAllocDevice** out, lbm_sim* herr) {
+    int dev = 0;
+    HIPCHK(herr, hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(herr, LBM_EDEVICE, "device index %d out of range", dev);
+    NoAllocDevice& d = g_noalloc[dev];
+    if (!d.scratch) {
+        void* p = nullptr;
+        HIPCHK(herr, hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(herr, LBM_EDEVICE, "no device address for the step tables");
+        if (!d.copied) HIPCHK(herr, hipEventCreateWithFlags(&d.copied, hipEventDisableTiming));
+        if (!d.done) HIPCHK(herr, hipEventCreateWithFlags(&d.done, hipEventDisableTiming));
+        d.scratch = (char*)p;
+    }
+    *out = &d;
+    return LBM_OK;
+}
+
 }  // namespace
 
 namespace ptlbm {
@@ -350,5 +396,75 @@ extern "C" int lbm_step_many(lbm_handle* hs, int32_t count, const int32_t* nstep
         for (int32_t i = 0; i < count; ++i)
             if (hs[i]->stream != S) HIPCHK(h0, hipStreamWaitEvent(hs[i]->stream, h0->ev_order, 0));
     }
+    return LBM_OK;
+}
+
+extern "C" int lbm_step_many_noalloc(lbm_handle* hs, int32_t count, const int32_t* nsteps, void* hip_stream) {
+    int rc = check_runs(hs, count, nsteps, "lbm_step_many_noalloc");
+    if (rc != LBM_OK) return rc;
+    lbm_sim* h0 = hs[0];
+    if (count > kMaxNoAllocRuns)
+        return fail(h0, LBM_EINVAL, "lbm_step_many_noalloc: %d runs, at most %d", count, kMaxNoAllocRuns);
+    hipStream_t S = hip_stream ? (hipStream_t)hip_stream : h0->stream;
+    std::lock_guard<std::mutex> lock(g_mu);
+    // every segment's image is at most that of all runs with steps left
+    lbm_sim* act[kMaxNoAllocRuns];
+    int n = 0;
+    for (int32_t i = 0; i < count; ++i)
+        if (nsteps[i] > 0) act[n++] = hs[i];
+    if (n == 0) return LBM_OK;
+    if (n > 1) {
+        ImageLayout L;
+        rc = image_layout(act, n, L, h0);
+        if (rc != LBM_OK) return rc;
+        if (L.total > kScratchBytes)
+            return fail(h0, LBM_EINVAL,
+                        "lbm_step_many_noalloc: the run tables and block maps of these runs need %zu bytes, "
+                        "the fixed array holds %zu",
+                        L.total, kScratchBytes);
+    }
+    NoAllocDevice* dev = nullptr;
+    rc = noalloc_device(&dev, h0);
+    if (rc != LBM_OK) return rc;
+    for (int32_t i = 0; i < count; ++i) {
+        rc = order_after_handle(S, hs[i], h0);
+        if (rc != LBM_OK) return rc;
+    }
+    int64_t left[kMaxNoAllocRuns];
+    for (int32_t i = 0; i < count; ++i) left[i] = nsteps[i];
+    for (;;) {
+        int states[kMaxNoAllocRuns];
+        int64_t L = 0;
+        n = 0;
+        for (int32_t i = 0; i < count; ++i)
+            if (left[i] > 0) {
+                act[n] = hs[i];
+                states[n] = state_of(hs[i]);
+                ++n;
+                L = L == 0 ? left[i] : std::min(L, left[i]);
+            }
+        if (n == 0) break;
+        ImageLayout IL;
+        Launches lau;
+        if (n > 1) {
+            rc = image_layout(act, n, IL, h0);
+            if (rc != LBM_OK) return rc;
+            // the host image is rewritten once the previous upload has read it
+            HIPCHK(h0, hipEventSynchronize(dev->copied));
+            write_image(act, n, states, IL, g_host_image);
+            HIPCHK(h0, hipMemcpyAsync(dev->scratch, g_host_image, IL.total, hipMemcpyHostToDevice, S));
+            HIPCHK(h0, hipEventRecord(dev->copied, S));
+        }
+        set_launches(act, n, states, IL, dev->scratch, lau);
+        rc = launch_steps(lau, L, S, h0);
+        if (rc != LBM_OK) return rc;
+        for (int k = 0; k < n; ++k) advance_by(act[k], L);
+        for (int32_t i = 0; i < count; ++i)
+            if (left[i] > 0) left[i] -= L;
+    }
+    // each handle's stream after the work on S
+    HIPCHK(h0, hipEventRecord(dev->done, S));
+    for (int32_t i = 0; i < count; ++i)
+        if (hs[i]->stream != S) HIPCHK(h0, hipStreamWaitEvent(hs[i]->stream, dev->done, 0));
     return LBM_OK;
 }

@@ -82,6 +82,7 @@ def _load():
     L.lbm_step.argtypes = [vp, _i]
     L.lbm_set_addressing.argtypes = [vp, _i]
     L.lbm_step_many.argtypes = [vp, _i, vp, vp]
+    L.lbm_step_many_noalloc.argtypes = [vp, _i, vp, vp]
     L.lbm_sync.argtypes = [vp]
     L.lbm_read_fields.argtypes = [vp, vp, vp, vp, vp, vp]
     L.lbm_read_particles.argtypes = [vp, vp, P(_i)]
@@ -216,6 +217,19 @@ def lbm_step_many(handles, nsteps, stream=None):
     if ns.shape != (n,):
         raise ValueError("one step count per handle")
     rc = _lib.lbm_step_many(ctypes.cast(hs, ctypes.c_void_p), n, _ptr(ns), stream)
+    _check(rc, handles[0])
+
+
+def lbm_step_many_noalloc(handles, nsteps, stream=None):
+    """lbm_step_many from the library's fixed device array (allocates nothing)."""
+    n = len(handles)
+    if n == 0:
+        return
+    hs = (ctypes.c_void_p * n)(*[h.value if isinstance(h, ctypes.c_void_p) else h for h in handles])
+    ns = np.ascontiguousarray(nsteps, dtype=np.int32)
+    if ns.shape != (n,):
+        raise ValueError("one step count per handle")
+    rc = _lib.lbm_step_many_noalloc(ctypes.cast(hs, ctypes.c_void_p), n, _ptr(ns), stream)
     _check(rc, handles[0])
 
 
