@@ -333,8 +333,8 @@ int lbm_time_phases(lbm_handle h, int32_t nsteps, double* ms_out);
 int lbm_time_copy(lbm_handle h, int32_t reps, double* ms_out);
 
 /* Counters, out[LBM_NSTATS]: steps done; links of the current state (those
- * the next step uses, Sec. 3); newborn nodes refilled (Sec. 2.5) since the
- * particles were set; device milliseconds per step of the last lbm_step
+ * the next step uses, Sec. 3); newborn nodes refilled (Sec. 2.5) in the last
+ * step; device milliseconds per step of the last lbm_step
  * call (0 before one); the HBM rate that implies for the lattice update's
  * algorithmic bytes (28 population values read and written per node,
  * GB/s); particles; lattice nodes; device bytes held.  Waits. */

@@ -85,6 +85,7 @@ Layout make_layout(const lbm_params& p) {
     }
     L.off_cand = off; off = round_up(off + cap * 4 * (size_t)L.nwin * sizeof(unsigned), kAlign);
     L.off_ncand = off; off = round_up(off + cap * sizeof(unsigned), kAlign);
+    L.off_nborn = off; off = round_up(off + cap * sizeof(unsigned), kAlign);
     // refilled values of the newborn candidates, computed beside the lattice
     // kernel and stored after it (16 doubles each)
     L.off_rbuf = off; off = round_up(off + cap * 4 * (size_t)L.nwin * 16 * sizeof(double), kAlign);
@@ -285,6 +286,7 @@ int create_common(const lbm_params* p, void* dev_ptr, size_t bytes, void* stream
     }
     d.cand = (unsigned*)(h->base + L.off_cand);
     d.ncand = (unsigned*)(h->base + L.off_ncand);
+    d.nborn = (unsigned*)(h->base + L.off_nborn);
     d.rbuf = L.off_rbuf ? (double*)(h->base + L.off_rbuf) : nullptr;
     fill_lp(h);
     {
@@ -351,6 +353,7 @@ RunStep make_runstep(const lbm_sim* h, int c, int r, int bp) {
     R.cnt_next = d.bcnt[1 - bp];
     R.cand = d.cand;
     R.ncand = d.ncand;
+    R.nborn = d.nborn;
     R.rbuf = d.rbuf;
     return R;
 }
@@ -375,22 +378,20 @@ namespace {
 // handle's stream, an event before each.  Otherwise the particle kernels
 // (update, owner map of t_n+1, links of t_n+1) run on the side stream while
 // the lattice kernel runs on the main one, with one wait on each side (an
-// event operation costs the main stream a few microseconds of idle time):
-//   main: link pass -> [fork] -> lattice -> wait(side) -> refill
-//   side: wait(fork) -> particles -> mask -> links of t_n+1 -> [side]
-// With 2- or 4-byte values (or FP64 and many particles) the refill's values
-// are computed last on the side stream and only stored on the main one:
+// event operation costs the main stream a few microseconds of idle time),
+// and the refill's values are computed last on the side stream and only
+// stored on the main one:
 //   main: link pass -> [fork] -> lattice -> wait(side) -> refill store
 //   side: wait(fork) -> particles -> mask -> links of t_n+1 -> refill values -> [side]
+// (FP64 at 4000^2 with 4800 particles: 21.44 k MLUPS with the whole refill
+// after the lattice kernel, 21.62 k split; the split refill's compute half
+// needs many registers and slows the FP64 lattice kernel beside it by 1 %,
+// less than the refill it takes off the main stream.)
 // In place the refill's values are computed with the owner map, before the
 // lattice kernel overwrites the state they are pulled from, so the lattice
 // kernel waits for that part of the side stream:
 //   main: link pass -> [fork] -> wait(mask) -> lattice -> refill store -> wait(side)
 //   side: wait(fork) -> particles -> mask + refill values -> [mask] -> links of t_n+1 -> [side]
-// FP64 runs with more particles than this compute their refill beside the
-// lattice kernel (measured: 64 000 particles, step 1.72 -> 1.62 ms; with
-// 4800 it went 0.749 -> 0.756 ms).
-constexpr int kSplitRefillParticles = 16384;
 
 int enqueue_step(lbm_sim* h, hipEvent_t* ev, hipEvent_t* lat = nullptr) {
     hipStream_t st = h->stream;
@@ -421,14 +422,10 @@ int enqueue_step(lbm_sim* h, hipEvent_t* ev, hipEvent_t* lat = nullptr) {
         HIPCHK(h, launch_step(SK_MASK, R, mode, sd));   // in place: and the refilled values
         if (aa) HIPCHK(h, hipEventRecord(h->ev_mask, sd));
         HIPCHK(h, launch_step(SK_COLLECT, Rn, mode, sd));
-        // two sets, 2- and 4-byte values: the refilled values last on the side
-        // stream, beside the lattice kernel (their kernel needs many registers;
-        // the link collection must not wait for it).  With 8-byte values the
-        // lattice kernel leaves it no registers: it starts only as lattice
-        // waves retire and slows the lattice kernel by 1.5 %, which a few
-        // thousand particles' refill does not repay (the refill runs whole
-        // after the lattice kernel) and tens of thousands' does.
-        const bool split = !aa && (h->d.mode != LBM_STORE_F64 || h->np > kSplitRefillParticles);
+        // two sets: the refilled values last on the side stream, beside the
+        // lattice kernel (their kernel needs many registers; the link
+        // collection must not wait for it)
+        const bool split = !aa;
         if (split) HIPCHK(h, launch_refill_part(R, mode, false, sd));
         HIPCHK(h, hipEventRecord(h->ev_side, sd));
         if (aa) {
@@ -697,6 +694,7 @@ int set_particles_rows(lbm_handle h, int32_t n, const double* rows, int cols) {
         for (int b = 0; b < 2; ++b)
             HIPCHK(h, hipMemsetAsync(d.bcnt[b], 0, sizeof(unsigned) * (size_t)d.lp.ncells, st));
         HIPCHK(h, hipMemsetAsync(d.ncand, 0, sizeof(unsigned) * n, st));
+        HIPCHK(h, hipMemsetAsync(d.nborn, 0, sizeof(unsigned) * n, st));
         // owner map of t_0 into O[0] from the particles in ring slot 0
         HIPCHK(h, launch_mask_setup(make_runstep(h, 1, 2, 0), st));
         HIPCHK(h, launch_bin_init(d, d.P[0], 0, st));
@@ -965,15 +963,17 @@ int lbm_time_phases(lbm_handle h, int32_t nsteps, double* ms_out) {
 int lbm_stats(lbm_handle h, double* out) {
     if (!h || !out) return LBM_EINVAL;
     std::vector<int2> seg((size_t)h->np);
-    unsigned long long newborn = 0;
-    if (h->np > 0)
+    std::vector<unsigned> nb((size_t)h->np);
+    if (h->np > 0) {
         HIPCHK(h, hipMemcpyAsync(seg.data(), h->d.seg, seg.size() * sizeof(int2), hipMemcpyDeviceToHost,
                                  h->stream));
-    HIPCHK(h, hipMemcpyAsync(&newborn, newborn_counter(h->d.status), sizeof newborn, hipMemcpyDeviceToHost,
-                             h->stream));
+        HIPCHK(h, hipMemcpyAsync(nb.data(), h->d.nborn, nb.size() * sizeof(unsigned), hipMemcpyDeviceToHost,
+                                 h->stream));
+    }
     HIPCHK(h, hipStreamSynchronize(h->stream));
-    double nl = 0.0;
+    double nl = 0.0, newborn = 0.0;
     for (const int2& sg : seg) nl += sg.y;
+    for (unsigned v : nb) newborn += v;
     double ms = 0.0;
     if (h->timed_steps > 0) {
         float t = 0.f;
@@ -985,7 +985,7 @@ int lbm_stats(lbm_handle h, double* out) {
     const double bytes_per_step = nodes * 28.0 * (double)elem_size(h->p.storage);
     out[LBM_STAT_STEPS] = (double)h->steps;
     out[LBM_STAT_LINKS] = nl;
-    out[LBM_STAT_NEWBORN] = (double)newborn;
+    out[LBM_STAT_NEWBORN] = newborn;
     out[LBM_STAT_MS_PER_STEP] = ms;
     out[LBM_STAT_GBPS] = ms > 0.0 ? bytes_per_step / (ms * 1e-3) / 1e9 : 0.0;
     out[LBM_STAT_PARTICLES] = (double)h->np;

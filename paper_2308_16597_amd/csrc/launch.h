@@ -27,6 +27,7 @@ struct DevState {
     unsigned* bcnt[2];           // particles per cell
     unsigned* cand;              // newborn-node candidates, 4 nwin per particle (x | y << 16)
     unsigned* ncand;             // candidates per particle
+    unsigned* nborn;             // newborn nodes refilled per particle in the last step
     double* rbuf;                // refilled post-collision values per candidate (16 each)
 };
 
@@ -55,6 +56,7 @@ struct RunStep {
     unsigned* cnt_next;
     unsigned* cand;
     unsigned* ncand;
+    unsigned* nborn;
     double* rbuf;
 };
 
@@ -89,12 +91,6 @@ enum StatusBits : unsigned {
     ST_BIN_OVERFLOW = 16u,  // more than BINCAP particles in one neighbour-search cell
     ST_CAND_OVERFLOW = 32u, // more newborn nodes for one particle than its candidate list holds
 };
-
-// The status block of a run (64 bytes, cleared when particles are set):
-// word 0 the StatusBits, bytes 8..15 the count of newborn nodes refilled.
-__host__ __device__ inline unsigned long long* newborn_counter(unsigned* status) {
-    return (unsigned long long*)(status + 2);
-}
 
 // Blocks one run needs for a kernel of class c.  The per-particle kernels
 // give each particle a wavefront (4 per block), or the whole block of 256

@@ -40,7 +40,7 @@
 // exactly as the CPU oracle rounds them.
 #include <hip/hip_runtime.h>
 
-#include "launch.h"
+#include "link.h"
 
 namespace ptlbm {
 
@@ -54,7 +54,6 @@ constexpr int OUTSIDE = -2;
 // windows are 32 nodes wide or more get the whole block of 256 lanes when
 // there are few of them (lp.lpp), with block barriers between the phases.
 
-__device__ __forceinline__ bool in_rows(int y, const LP& lp) { return y >= 0 && y < lp.ny; }
 
 // Lanes of one particle: a wavefront (4 particles per block of 256) or, for
 // particles whose windows are large (lp.lpp == 256), the whole block.
@@ -256,107 +255,35 @@ __device__ __forceinline__ void links_body(const RunStep& rs, unsigned bid) {
 // issued together, after its (arithmetic-only) link fraction.
 constexpr int PASS_CHUNKS = (12 * 100 - 12 + 63) / 64;   // the window edge is at most 100
 
-// One link: fluid node (x, y), direction i towards particle P.  QFIRST:
-// gather only what the branch of q needs (the link pass); otherwise gather
-// both branches' populations without waiting for q (the direct pass, whose
-// threads take their links one after another).
+// One link in the link pass: the values of eval_link (link.h) stored where
+// the next pull reads them -- slot ibar of the solid node x_f + e_i (two
+// sets), slot i there (in place, before the odd kernel), slot ibar of x_f
+// itself (in place, before the even one) -- and the link's momentum
+// exchange, Eqs. (13)-(14), added to (hx, hy, hz).
 template <int MODE, bool QFIRST = true>
 __device__ __forceinline__ void link_pass_link(const RunStep& rs, const PState& P, const Shape& sh, int x, int y,
                                                int i, double& hx, double& hy, double& hz) {
     using S = Store<MODE>;
     const LP& lp = rs.lp;
-    // population arrays picked straight from the run's pointer table (a
-    // local copy indexed by the link direction would live in scratch)
-    auto F = [&](int a) { return (const PT_GLOBAL ST<MODE>*)rs.A[a]; };
     auto Fw = [&](int a) { return (PT_GLOBAL ST<MODE>*)rs.A[a]; };
-    const PT_GLOBAL int32_t* __restrict__ Ocur = gl(rs.Ocur);
-    const int pitch = lp.pitch;
+    const LinkEval e = eval_link<MODE, QFIRST>(rs, P, sh, x, y, i);
     const int ib = OPPd(i), ex = EXd(i), ey = EYd(i);
-    const int x1 = col_of(x - ex, lp), y1 = y - ey;
-    const int x2 = col_of(x - 2 * ex, lp), y2 = y - 2 * ey;
-    const bool in1 = in_rows(y1, lp) && x1 >= 0, in2 = in_rows(y2, lp) && x2 >= 0;
-    const size_t k = (size_t)y * pitch + x;
-    const size_t k1 = in1 ? (size_t)y1 * pitch + x1 : k;
-    const size_t k2 = in2 ? (size_t)y2 * pitch + x2 : k;
-    const int32_t o1 = Ocur[k1], o2 = Ocur[k2];
-    // where the post-collision state keeps f_a*(node): slot a at the node
-    // (two sets), slot abar at the node (in place, reversed), or slot a at
-    // the node + e_a (in place, pushed; slot abar at the node at a wall)
     const int lay = lp.aa ? 1 + rs.parity : 0;
-    // q first: the two branches of Eqs. (9)-(10) read different populations
-    // (q <= 1/2: f_i at x_f, x_f - e_i, x_f - 2 e_i; q > 1/2: f_i at x_f and
-    // f_ibar at x_f, x_f - e_i), so only those are gathered
-    const double dx = min_image_x((double)x - P.x, lp);
-    const double dy = (double)y - P.y;
-    const double q = link_q_shape(sh, dx, dy, i);
-    const bool lo = q <= 0.5;
-    const bool get_lo = !QFIRST || lo, get_hi = !QFIRST || !lo;
-    double fi, fib = 0.0, fi1 = 0.0, fib1 = 0.0, fi2 = 0.0, gi = 0.0, gib = 0.0, gi1 = 0.0;
-    if (lay != 2) {
-        const int si = lay ? ib : i, sib = lay ? i : ib;
-        fi = (double)S::ld(F(si) + k);
-        if (get_lo) {
-            fi1 = (double)S::ld(F(si) + k1);
-            fi2 = (double)S::ld(F(si) + k2);
-        }
-        if (get_hi) {
-            fib = (double)S::ld(F(sib) + k);
-            fib1 = (double)S::ld(F(sib) + k1);
-        }
-        if (i <= 4) {
-            gi = (double)S::ld(F(9 + si) + k);
-            gib = (double)S::ld(F(9 + sib) + k);
-            gi1 = (double)S::ld(F(9 + si) + k1);
-        }
-    } else {
-        int sl;
-        size_t at;
-        at = pushed_at(lp, x, y, i, sl);
-        fi = (double)S::ld(F(sl) + at);
-        if (i <= 4) gi = (double)S::ld(F(9 + sl) + at);
-        at = pushed_at(lp, x, y, ib, sl);
-        if (get_hi) fib = (double)S::ld(F(sl) + at);
-        if (i <= 4) gib = (double)S::ld(F(9 + sl) + at);
-        if (in1) {
-            at = pushed_at(lp, x1, y1, i, sl);
-            if (get_lo) fi1 = (double)S::ld(F(sl) + at);
-            if (i <= 4) gi1 = (double)S::ld(F(9 + sl) + at);
-            if (get_hi) {
-                at = pushed_at(lp, x1, y1, ib, sl);
-                fib1 = (double)S::ld(F(sl) + at);
-            }
-        }
-        if (in2 && get_lo) {
-            at = pushed_at(lp, x2, y2, i, sl);
-            fi2 = (double)S::ld(F(sl) + at);
-        }
-    }
-    const bool have1 = in1 && o1 == -1;
-    const bool have2 = have1 && in2 && o2 == -1;
-    const double rx = dx + q * ex, ry = dy + q * ey;   // x_w - X_c
-    const double uwx = P.ux - P.om * ry, uwy = P.uy + P.om * rx;
-    const double w9i = i <= 4 ? 1.0 / 9.0 : 1.0 / 36.0;
-    const double wall = 6.0 * w9i * lp.rho0 * (-(ex * uwx) - ey * uwy);
-    const double fnew = bouzidi(q, fi, fi1, fi2, fib, fib1, have1, have2, wall);
-    // f_ibar(x_f) goes where the next lattice kernel reads it: slot ibar of
-    // the solid node x_f + e_i (two sets), slot i there (in place, before
-    // the odd kernel), slot ibar of x_f itself (in place, before the even one)
-    const size_t kb = (size_t)(y + ey) * pitch + col_of(x + ex, lp);   // a node of P
+    const size_t k = (size_t)y * lp.pitch + x;
+    const size_t kb = (size_t)(y + ey) * lp.pitch + col_of(x + ex, lp);   // a node of P
     const size_t ko = lay == 2 ? k : kb;
     const int so = lay == 1 ? i : ib;
-    S::st(Fw(so) + ko, (typename S::R)fnew);
-    if (i <= 4) {
-        const double gnew = thermal_link(q, gi, gi1, gib, have1, lp.w5_k, lp.particle_T - lp.T_sh);
-        S::st(Fw(9 + so) + ko, (typename S::R)gnew);
-    }
+    S::st(Fw(so) + ko, (typename S::R)e.fnew);
+    if (i <= 4) S::st(Fw(9 + so) + ko, (typename S::R)e.gnew);
     // Eq. (13) on full populations (stored value + rest part w rho0)
+    const double w9i = i <= 4 ? 1.0 / 9.0 : 1.0 / 36.0;
     const double shf = S::shifted ? lp.rho0 : 0.0;
-    const double Fi = fi + w9i * shf, Fb = (double)(typename S::R)fnew + w9i * shf;
-    const double dFx = Fi * (ex - uwx) - Fb * (-ex - uwx);
-    const double dFy = Fi * (ey - uwy) - Fb * (-ey - uwy);
+    const double Fi = e.fi + w9i * shf, Fb = (double)(typename S::R)e.fnew + w9i * shf;
+    const double dFx = Fi * (ex - e.uwx) - Fb * (-ex - e.uwx);
+    const double dFy = Fi * (ey - e.uwy) - Fb * (-ey - e.uwy);
     hx += dFx;
     hy += dFy;
-    hz += rx * dFy - ry * dFx;   // Eq. (14), z component
+    hz += e.rx * dFy - e.ry * dFx;   // Eq. (14), z component
 }
 
 template <int MODE, int NT>
@@ -712,6 +639,7 @@ __device__ __forceinline__ void mask_body(const RunStep& rs, unsigned bid) {
             nc = ccap;
         }
         if (with_prev) ncand[p] = nc;
+        gl(rs.nborn)[p] = 0u;
     }
 }
 
@@ -828,6 +756,7 @@ __device__ __forceinline__ void refill_body(const RunStep& rs, unsigned bid) {
     PT_GLOBAL double* buf = gl(rs.rbuf);
     const PState P1 = ld_state(rs.Pn + p);
     const Shape sh = shape_of(P1);
+    unsigned refilled = 0;   // this lane's newborn nodes
     for (unsigned i = lane; i < n; i += pl.nl) {
         const unsigned code = gl(rs.cand)[(size_t)p * ccap + i];
         const int x = (int)(code & 0xffffu), y = (int)(code >> 16);
@@ -844,11 +773,7 @@ __device__ __forceinline__ void refill_body(const RunStep& rs, unsigned bid) {
         }
         const int lay = lp.aa ? 1 + rs.parity : 0;
         const bool mine = refill_node<MODE>(A, lay, gl(rs.Ocur), gl(rs.Onext), P1, sh, p, x, y, lp, args_cc<R>(lp), s, t);
-        {   // newborn nodes refilled since the particles were set (one atomic per wavefront)
-            const unsigned long long m = __ballot(mine);
-            if (m && (threadIdx.x & 63) == (unsigned)(__ffsll((long long)__ballot(1)) - 1))
-                atomicAdd(newborn_counter(rs.status), (unsigned long long)__popcll(m));
-        }
+        refilled += mine ? 1u : 0u;
         if (PART == REFILL_TWO_SETS) {
             if (mine) store_node<S>(B, lp, args_cc<R>(lp), x, y, s, t);
         } else {
@@ -859,6 +784,10 @@ __device__ __forceinline__ void refill_body(const RunStep& rs, unsigned bid) {
             buf[slot + 14] = mine ? 1.0 : 0.0;
         }
     }
+    if (PART == REFILL_STORE) return;
+    // newborn nodes of the particle this step (its count, zeroed by k_mask_mark)
+    for (int off = 32; off > 0; off >>= 1) refilled += __shfl_xor(refilled, off);
+    if ((threadIdx.x & 63) == 0 && refilled) atomicAdd(rs.nborn + p, refilled);
 }
 
 // ------------------------------------------------------- step kernels ----
