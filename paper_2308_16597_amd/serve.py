@@ -191,13 +191,24 @@ def percentile_nearest_rank(values, q):
 
 
 def summarize(records, wall):
+    """Completed requests' latency percentiles (nearest rank), throughput
+    over the wall time, and the same for the requests that ran at their
+    requested Rayleigh number and for those whose viscosity was raised to
+    NU_MIN ("Ra capped"), separately."""
     ok = [r for r in records if r["status"] == "ok"]
-    lat = [r["latency"] for r in ok]
-    lups = sum(r["nodes"] * r["steps"] for r in ok)
-    return dict(requests=len(records), completed=len(ok),
-                failed=len(records) - len(ok),
-                p50_s=percentile_nearest_rank(lat, 0.50) if lat else None,
-                p99_s=percentile_nearest_rank(lat, 0.99) if lat else None,
-                wall_s=wall, req_per_s=len(ok) / wall if wall > 0 else None,
-                mlups=lups / wall / 1e6 if wall > 0 else None,
-                ra_capped=sum(1 for r in ok if r.get("ra_capped")))
+
+    def part(rs):
+        lat = [r["latency"] for r in rs]
+        lups = sum(r["nodes"] * r["steps"] for r in rs)
+        return dict(completed=len(rs),
+                    p50_s=percentile_nearest_rank(lat, 0.50) if lat else None,
+                    p99_s=percentile_nearest_rank(lat, 0.99) if lat else None,
+                    mlups=lups / wall / 1e6 if wall > 0 else None)
+
+    out = dict(requests=len(records), failed=len(records) - len(ok), wall_s=wall,
+               req_per_s=len(ok) / wall if wall > 0 else None,
+               ra_capped=sum(1 for r in ok if r.get("ra_capped")))
+    out.update(part(ok))
+    out["uncapped"] = part([r for r in ok if not r.get("ra_capped")])
+    out["capped"] = part([r for r in ok if r.get("ra_capped")])
+    return out

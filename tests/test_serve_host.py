@@ -61,3 +61,17 @@ def test_nearest_rank_percentiles():
     assert serve.percentile_nearest_rank(v, 0.5) == 128
     assert serve.percentile_nearest_rank(v, 0.99) == 254
     assert serve.percentile_nearest_rank([3.0], 0.99) == 3.0
+
+
+def test_summary_splits_capped_and_uncapped_requests():
+    recs = [dict(status="ok", latency=float(i + 1), nodes=100, steps=10, ra_capped=(i % 3 == 0))
+            for i in range(9)]
+    recs.append(dict(status="rejected: over budget", arrival=0.0))
+    s = serve.summarize(recs, wall=2.0)
+    assert s["requests"] == 10 and s["failed"] == 1 and s["completed"] == 9
+    assert s["ra_capped"] == 3 and s["capped"]["completed"] == 3 and s["uncapped"]["completed"] == 6
+    # capped latencies 1, 4, 7; uncapped 2, 3, 5, 6, 8, 9 (nearest rank)
+    assert s["capped"]["p50_s"] == 4.0 and s["capped"]["p99_s"] == 7.0
+    assert s["uncapped"]["p50_s"] == 5.0 and s["uncapped"]["p99_s"] == 9.0
+    assert s["mlups"] == pytest.approx(9 * 1000 / 2.0 / 1e6)
+    assert s["capped"]["mlups"] + s["uncapped"]["mlups"] == pytest.approx(s["mlups"])
