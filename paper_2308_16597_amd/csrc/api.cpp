@@ -1007,14 +1007,14 @@ int lbm_time_copy(lbm_handle h, int32_t reps, double* ms_out) {
     // the current state A is read; B (the set the next step writes whole)
     // receives the copy; in place the single set is copied onto itself
     const RunStep R = current_runstep(h);
-    const unsigned nb = run_blocks(GC_LAT, R.lp);
+    const size_t bytes = h->L.npitched * elem_size(h->p.storage);   // a multiple of 16: rows of 64 nodes
     hipEvent_t e0 = nullptr, e1 = nullptr;
     int rc = LBM_OK;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = fail(h, LBM_EDEVICE, "hipEventCreate");
-    if (rc == LBM_OK && launch_copy(R, h->d.mode, nb, h->stream) != hipSuccess) rc = fail(h, LBM_EDEVICE, "copy launch");
+    if (rc == LBM_OK && launch_copy(R, bytes, h->stream) != hipSuccess) rc = fail(h, LBM_EDEVICE, "copy launch");
     if (rc == LBM_OK && hipEventRecord(e0, h->stream) != hipSuccess) rc = fail(h, LBM_EDEVICE, "hipEventRecord");
     for (int32_t r = 0; r < reps && rc == LBM_OK; ++r)
-        if (launch_copy(R, h->d.mode, nb, h->stream) != hipSuccess) rc = fail(h, LBM_EDEVICE, "copy launch");
+        if (launch_copy(R, bytes, h->stream) != hipSuccess) rc = fail(h, LBM_EDEVICE, "copy launch");
     if (rc == LBM_OK && hipEventRecord(e1, h->stream) != hipSuccess) rc = fail(h, LBM_EDEVICE, "hipEventRecord");
     if (rc == LBM_OK && hipEventSynchronize(e1) != hipSuccess) rc = fail(h, LBM_EDEVICE, "hipEventSynchronize");
     float ms = 0.f;

@@ -258,20 +258,20 @@ __global__ __launch_bounds__(LAT_BLOCK) void k_stream_collide_aa_b(const RunStep
     else stream_collide_aa_body<MODE, false>(tab[m.x], m.y);
 }
 
-// A plain copy of the 14 population arrays A -> B with the lattice kernel's
-// grid, node per thread, non-temporal loads and stores: the HBM ceiling the
-// lattice kernel is compared with (it moves the same bytes, no arithmetic).
-template <int MODE>
-__global__ __launch_bounds__(LAT_BLOCK) void k_copy14(RunStep rs) {
-    int x, y;
-    lattice_node<false>(rs.lp, blockIdx.x, x, y);
-    if (x >= rs.lp.nx || y >= rs.lp.ny) return;
-    const size_t k = (size_t)y * rs.lp.pitch + x;
+// A plain copy of the 14 population arrays A -> B, 16 bytes per lane (8, 4
+// or 2 nodes of each array; every array holds the padded lattice), with
+// non-temporal loads and stores: the HBM ceiling the lattice kernel is
+// compared with (the same bytes moved, no arithmetic, and no per-node
+// instruction cost for the narrow types).
+__global__ __launch_bounds__(LAT_BLOCK) void k_copy14(RunStep rs, size_t nchunks) {
+    const size_t c = (size_t)blockIdx.x * LAT_BLOCK + threadIdx.x;
+    if (c >= nchunks) return;
 #pragma unroll
     for (int i = 0; i < 14; ++i) {
-        const PT_GLOBAL ST<MODE>* a = (const PT_GLOBAL ST<MODE>*)rs.A[i];
-        PT_GLOBAL ST<MODE>* b = (PT_GLOBAL ST<MODE>*)rs.B[i];
-        __builtin_nontemporal_store(__builtin_nontemporal_load(a + k), b + k);
+        typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+        const PT_GLOBAL u32x4* a = (const PT_GLOBAL u32x4*)rs.A[i];
+        PT_GLOBAL u32x4* b = (PT_GLOBAL u32x4*)rs.B[i];
+        __builtin_nontemporal_store(__builtin_nontemporal_load(a + c), b + c);
     }
 }
 
@@ -290,8 +290,10 @@ hipError_t launch_lattice(const RunStep& R, int mode, unsigned nblocks, hipStrea
     return hipGetLastError();
 }
 
-hipError_t launch_copy(const RunStep& R, int mode, unsigned nblocks, hipStream_t st) {
-    PTLBM_DISPATCH(mode, (k_copy14<M><<<nblocks, LAT_BLOCK, 0, st>>>(R)));
+hipError_t launch_copy(const RunStep& R, size_t array_bytes, hipStream_t st) {
+    const size_t nchunks = array_bytes / 16;
+    const unsigned nblocks = (unsigned)((nchunks + LAT_BLOCK - 1) / LAT_BLOCK);
+    k_copy14<<<nblocks, LAT_BLOCK, 0, st>>>(R, nchunks);
     return hipGetLastError();
 }
 

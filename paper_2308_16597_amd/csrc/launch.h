@@ -107,8 +107,9 @@ hipError_t launch_step(int k, const RunStep& R, int mode, hipStream_t st);
 // The lattice kernel alone (lattice.hip), for one run or batched (two-set
 // or in place, at each run's parity).
 hipError_t launch_lattice(const RunStep& R, int mode, unsigned nblocks, hipStream_t st);
-// A plain copy of the run's 14 population arrays A -> B (the HBM ceiling).
-hipError_t launch_copy(const RunStep& R, int mode, unsigned nblocks, hipStream_t st);
+// A plain copy of the run's 14 population arrays A -> B, array_bytes each
+// (a multiple of 16), the HBM ceiling.
+hipError_t launch_copy(const RunStep& R, size_t array_bytes, hipStream_t st);
 hipError_t launch_lattice_batch(const RunStep* tab, const uint2* bmap, unsigned nblocks, int mode, bool aa,
                                 hipStream_t st);
 // The two halves of the split refill of one run (store = false: compute).

@@ -22,14 +22,17 @@ STEPS, EVERY = 2000, 250
 C1 = P.workload_params("small")
 ROWS = lbm_inputs.rsa_particles(256, 256, 20, 12.0, 1.0, 1)
 # stated bounds: L2 velocity error, L2 temperature error, largest particle
-# displacement (lattice units), relative Nusselt error (time-averaged)
-# (about twice the errors measured on gfx950; BF16 keeps 8 significand bits,
-# so small temperature increments of the cold fluid are largely rounded away)
+# displacement (lattice units), relative Nusselt error (time-averaged).
+# FP32 and FP16: accuracy statements (about twice the errors measured on
+# gfx950).  BF16 keeps 8 significand bits, so small temperature increments
+# of the cold fluid are largely rounded away (eps_T 0.39 measured): it is a
+# throughput form, and its bounds (1.5 x the measured errors: eps_u 0.058,
+# eps_T 0.39, dX 0.33, dNu 0.031) only guard that result against change.
 BOUNDS = {
     "f32": (1e-4, 1e-5, 1e-3, 1e-4),
     "shift_f32": (1e-4, 1e-5, 1e-3, 1e-4),
     "shift_f16": (2e-3, 1.5e-2, 0.02, 2e-3),
-    "shift_bf16": (0.15, 0.8, 0.8, 0.08),
+    "shift_bf16": (0.09, 0.6, 0.5, 0.05),
 }
 
 
