@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libptlbm.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("lattice.hip", "particles.hip", "api.cpp", "serve.cpp")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("lattice.hip", "particles.hip", "copy.hip", "api.cpp", "serve.cpp")]
 
 
 def hipcc_command(out=LIB, arch="gfx950"):

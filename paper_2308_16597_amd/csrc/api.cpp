@@ -1011,15 +1011,21 @@ int lbm_time_copy(lbm_handle h, int32_t reps, double* ms_out) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     int rc = LBM_OK;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = fail(h, LBM_EDEVICE, "hipEventCreate");
-    if (rc == LBM_OK && launch_copy(R, bytes, h->stream) != hipSuccess) rc = fail(h, LBM_EDEVICE, "copy launch");
-    if (rc == LBM_OK && hipEventRecord(e0, h->stream) != hipSuccess) rc = fail(h, LBM_EDEVICE, "hipEventRecord");
-    for (int32_t r = 0; r < reps && rc == LBM_OK; ++r)
-        if (launch_copy(R, bytes, h->stream) != hipSuccess) rc = fail(h, LBM_EDEVICE, "copy launch");
-    if (rc == LBM_OK && hipEventRecord(e1, h->stream) != hipSuccess) rc = fail(h, LBM_EDEVICE, "hipEventRecord");
-    if (rc == LBM_OK && hipEventSynchronize(e1) != hipSuccess) rc = fail(h, LBM_EDEVICE, "hipEventSynchronize");
-    float ms = 0.f;
-    if (rc == LBM_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = fail(h, LBM_EDEVICE, "hipEventElapsedTime");
-    if (rc == LBM_OK) *ms_out = (double)ms / reps;
+    double best = 0.0;
+    // the faster of 8- and 16-byte lanes (which is faster depends on the GPU
+    // and the value size)
+    for (int lane : {8, 16}) {
+        if (rc == LBM_OK && launch_copy(R, bytes, lane, h->stream) != hipSuccess) rc = fail(h, LBM_EDEVICE, "copy launch");
+        if (rc == LBM_OK && hipEventRecord(e0, h->stream) != hipSuccess) rc = fail(h, LBM_EDEVICE, "hipEventRecord");
+        for (int32_t r = 0; r < reps && rc == LBM_OK; ++r)
+            if (launch_copy(R, bytes, lane, h->stream) != hipSuccess) rc = fail(h, LBM_EDEVICE, "copy launch");
+        if (rc == LBM_OK && hipEventRecord(e1, h->stream) != hipSuccess) rc = fail(h, LBM_EDEVICE, "hipEventRecord");
+        if (rc == LBM_OK && hipEventSynchronize(e1) != hipSuccess) rc = fail(h, LBM_EDEVICE, "hipEventSynchronize");
+        float ms = 0.f;
+        if (rc == LBM_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = fail(h, LBM_EDEVICE, "hipEventElapsedTime");
+        if (rc == LBM_OK && (best == 0.0 || ms / reps < best)) best = (double)ms / reps;
+    }
+    if (rc == LBM_OK) *ms_out = best;
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     return rc;

@@ -258,23 +258,6 @@ __global__ __launch_bounds__(LAT_BLOCK) void k_stream_collide_aa_b(const RunStep
     else stream_collide_aa_body<MODE, false>(tab[m.x], m.y);
 }
 
-// A plain copy of the 14 population arrays A -> B, 16 bytes per lane (8, 4
-// or 2 nodes of each array; every array holds the padded lattice), with
-// non-temporal loads and stores: the HBM ceiling the lattice kernel is
-// compared with (the same bytes moved, no arithmetic, and no per-node
-// instruction cost for the narrow types).
-__global__ __launch_bounds__(LAT_BLOCK) void k_copy14(RunStep rs, size_t nchunks) {
-    const size_t c = (size_t)blockIdx.x * LAT_BLOCK + threadIdx.x;
-    if (c >= nchunks) return;
-#pragma unroll
-    for (int i = 0; i < 14; ++i) {
-        typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
-        const PT_GLOBAL u32x4* a = (const PT_GLOBAL u32x4*)rs.A[i];
-        PT_GLOBAL u32x4* b = (PT_GLOBAL u32x4*)rs.B[i];
-        __builtin_nontemporal_store(__builtin_nontemporal_load(a + c), b + c);
-    }
-}
-
 // -------------------------------------------------------------- launchers ----
 
 static dim3 lattice_grid(const LP& lp, int rows) { return dim3((lp.nx + LAT_BLOCK - 1) / LAT_BLOCK, rows); }
@@ -287,13 +270,6 @@ hipError_t launch_lattice(const RunStep& R, int mode, unsigned nblocks, hipStrea
     } else {
         PTLBM_DISPATCH(mode, (k_stream_collide_aa<M, false><<<nblocks, LAT_BLOCK, 0, st>>>(R)));
     }
-    return hipGetLastError();
-}
-
-hipError_t launch_copy(const RunStep& R, size_t array_bytes, hipStream_t st) {
-    const size_t nchunks = array_bytes / 16;
-    const unsigned nblocks = (unsigned)((nchunks + LAT_BLOCK - 1) / LAT_BLOCK);
-    k_copy14<<<nblocks, LAT_BLOCK, 0, st>>>(R, nchunks);
     return hipGetLastError();
 }
 

@@ -108,8 +108,9 @@ hipError_t launch_step(int k, const RunStep& R, int mode, hipStream_t st);
 // or in place, at each run's parity).
 hipError_t launch_lattice(const RunStep& R, int mode, unsigned nblocks, hipStream_t st);
 // A plain copy of the run's 14 population arrays A -> B, array_bytes each
-// (a multiple of 16), the HBM ceiling.
-hipError_t launch_copy(const RunStep& R, size_t array_bytes, hipStream_t st);
+// (a multiple of 16), lane_bytes (8 or 16) per lane: the HBM ceiling
+// (copy.hip).
+hipError_t launch_copy(const RunStep& R, size_t array_bytes, int lane_bytes, hipStream_t st);
 hipError_t launch_lattice_batch(const RunStep* tab, const uint2* bmap, unsigned nblocks, int mode, bool aa,
                                 hipStream_t st);
 // The two halves of the split refill of one run (store = false: compute).
