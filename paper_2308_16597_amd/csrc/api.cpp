@@ -86,6 +86,7 @@ Layout make_layout(const lbm_params& p) {
     L.off_cand = off; off = round_up(off + cap * 4 * (size_t)L.nwin * sizeof(unsigned), kAlign);
     L.off_ncand = off; off = round_up(off + cap * sizeof(unsigned), kAlign);
     L.off_nborn = off; off = round_up(off + cap * sizeof(unsigned), kAlign);
+    L.off_order = off; off = round_up(off + cap * sizeof(unsigned), kAlign);
     // refilled values of the newborn candidates, computed beside the lattice
     // kernel and stored after it (16 doubles each)
     L.off_rbuf = off; off = round_up(off + cap * 4 * (size_t)L.nwin * 16 * sizeof(double), kAlign);
@@ -287,6 +288,7 @@ int create_common(const lbm_params* p, void* dev_ptr, size_t bytes, void* stream
     d.cand = (unsigned*)(h->base + L.off_cand);
     d.ncand = (unsigned*)(h->base + L.off_ncand);
     d.nborn = (unsigned*)(h->base + L.off_nborn);
+    d.order = (unsigned*)(h->base + L.off_order);
     d.rbuf = L.off_rbuf ? (double*)(h->base + L.off_rbuf) : nullptr;
     fill_lp(h);
     {
@@ -354,6 +356,7 @@ RunStep make_runstep(const lbm_sim* h, int c, int r, int bp) {
     R.cand = d.cand;
     R.ncand = d.ncand;
     R.nborn = d.nborn;
+    R.order = d.order;
     R.rbuf = d.rbuf;
     return R;
 }
@@ -688,6 +691,20 @@ int set_particles_rows(lbm_handle h, int32_t n, const double* rows, int cols) {
     if (n > 0) {
         for (int r = 0; r < 3; ++r)
             HIPCHK(h, hipMemcpyAsync(d.P[r], P.data(), sizeof(PState) * n, hipMemcpyHostToDevice, st));
+        // the link pass takes the particles in rows of bands one neighbour
+        // cell high, left to right within a band: neighbouring blocks then
+        // gather from the same cache lines
+        const double band = h->p.max_diameter + std::max(h->p.rep_range, 0.0);
+        std::vector<unsigned> order((size_t)n);
+        std::vector<long long> key((size_t)n);
+        for (int i = 0; i < n; ++i) {
+            order[i] = (unsigned)i;
+            key[i] = (long long)std::floor((P[i].y + 0.5) / band) * (2LL * h->p.nx + 2) +
+                     (long long)std::floor(P[i].x + 0.5);
+        }
+        std::stable_sort(order.begin(), order.end(), [&](unsigned a, unsigned b) { return key[a] < key[b]; });
+        HIPCHK(h, hipMemcpyAsync(d.order, order.data(), sizeof(unsigned) * n, hipMemcpyHostToDevice, st));
+        HIPCHK(h, hipStreamSynchronize(st));   // the host vector goes out of scope
         HIPCHK(h, hipMemsetAsync(d.Fh, 0, sizeof(double) * 4 * n, st));
         HIPCHK(h, hipMemsetAsync(d.Fa, 0, sizeof(double) * 4 * n, st));
         HIPCHK(h, hipMemsetAsync(d.seg, 0, sizeof(int2) * n, st));

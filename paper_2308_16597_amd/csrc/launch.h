@@ -28,6 +28,7 @@ struct DevState {
     unsigned* cand;              // newborn-node candidates, 4 nwin per particle (x | y << 16)
     unsigned* ncand;             // candidates per particle
     unsigned* nborn;             // newborn nodes refilled per particle in the last step
+    unsigned* order;             // particles in row-band order (the link pass's block order)
     double* rbuf;                // refilled post-collision values per candidate (16 each)
 };
 
@@ -57,6 +58,7 @@ struct RunStep {
     unsigned* cand;
     unsigned* ncand;
     unsigned* nborn;
+    const unsigned* order;
     double* rbuf;
 };
 

@@ -71,7 +71,12 @@ __device__ __forceinline__ PartLanes part_lanes(const LP& lp, unsigned bid) {
     q.p = q.blk ? (int)bid : (int)bid * 4 + (int)(threadIdx.x >> 6);
     return q;
 }
-
+// Block slot of a launch whose grid is a multiple of 8 blocks: consecutive
+// blocks go to the 8 XCDs in turn (each with its own L2), and XCD k (the
+// blocks b = k mod 8) takes the k-th eighth of the slots.
+__device__ __forceinline__ unsigned xcd_slot(unsigned bid) {
+    return (bid & 7u) * (gridDim.x >> 3) + (bid >> 3);
+}
 // Orders the LDS accesses of the lanes of one wavefront.
 __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -160,7 +165,7 @@ __host__ __device__ inline size_t links_wave_lds(int nwin) {
 //      count within each wavefront, and across the wavefronts of a block);
 //  (c) the list goes to the particle's fixed segment of the link array,
 //      12 N - 12 entries from p (12 N - 12): no atomics between particles.
-__device__ __forceinline__ void links_body(const RunStep& rs, unsigned bid) {
+__device__ __forceinline__ void links_body(const RunStep& rs, const PartLanes& pl) {
     extern __shared__ uint2 smem[];
     const LP& lp = rs.lp;
     const PT_GLOBAL int32_t* __restrict__ Ocur = gl(rs.Ocur);
@@ -168,7 +173,6 @@ __device__ __forceinline__ void links_body(const RunStep& rs, unsigned bid) {
     uint2* links = rs.links;
     int2* seg = rs.seg;
     unsigned* status = rs.status;
-    const PartLanes pl = part_lanes(lp, bid);
     const int lane = pl.lane, nl = pl.nl, p = pl.p;
     const int w = pl.blk ? 0 : (int)(threadIdx.x >> 6);   // the particle's LDS area in the block
     const bool have_p = p < lp.np;
@@ -417,13 +421,12 @@ __global__ __launch_bounds__(256) void k_bin_init(const PState* __restrict__ P, 
 //    3 x 3 cells around the particle), summed in ascending partner index (the
 //    order of a plain loop over all partners); walls; net weight;
 //  - Newton-Euler; the new state goes into the cell grid of t_n+1.
-__device__ __forceinline__ void particles_body(const RunStep& rs, unsigned bid) {
+__device__ __forceinline__ void particles_body(const RunStep& rs, const PartLanes& pl) {
     const LP& lp = rs.lp;
     const PState* __restrict__ Pc = rs.Pc;
     const PT_GLOBAL unsigned* __restrict__ bins_cur = gl(rs.bins_cur);
     const PT_GLOBAL unsigned* __restrict__ cnt_cur = gl(rs.cnt_cur);
     unsigned* status = rs.status;
-    const PartLanes pl = part_lanes(lp, bid);
     const int p = pl.p;
     if (p >= lp.np) return;
     {   // the owner-map buffer that will hold t_n+1 still holds t_n-1: clear
@@ -564,7 +567,7 @@ __device__ __forceinline__ void particles_body(const RunStep& rs, unsigned bid) 
 // candidate (k_refill keeps it if this particle owned it at t_n and no
 // particle covers it at t_n+1).  Also clears the cell-grid counts read this
 // step.
-__device__ __forceinline__ void mask_body(const RunStep& rs, unsigned bid) {
+__device__ __forceinline__ void mask_body(const RunStep& rs, unsigned bid, const PartLanes& pl) {
     const LP& lp = rs.lp;
     int32_t* O = rs.Onext;
     const PState* __restrict__ Pp = rs.Pn;
@@ -572,7 +575,6 @@ __device__ __forceinline__ void mask_body(const RunStep& rs, unsigned bid) {
     PT_GLOBAL unsigned* cand = gl(rs.cand);
     PT_GLOBAL unsigned* ncand = gl(rs.ncand);
     unsigned* status = rs.status;
-    const PartLanes pl = part_lanes(lp, bid);
     if (rs.cnt_cur) {   // every thread of the run's grid clears a share of the counts
         const int nblocks = pl.blk ? lp.np : (lp.np + 3) / 4;
         for (int c = (int)bid * 256 + threadIdx.x; c < lp.ncells; c += nblocks * 256) gl(rs.cnt_cur)[c] = 0u;
@@ -648,11 +650,16 @@ __device__ __forceinline__ void mask_body(const RunStep& rs, unsigned bid) {
 // index); pre-collision f at x + m e_c (m = 1..3, nodes fluid at t_n and
 // t_n+1) rebuilt by pulling from A; Eq. (16) extrapolation (lower order when
 // fewer points are fluid, equilibrium at rho0 with none); momentum set so
-// that u = u_w; g = g^eq(T_w, u_w) (Eq. (17)); then collided: the node's
-// post-collision values of t_n+1 in s, t.  Returns false (nothing to
-// refill) unless p owned the node at t_n and it is fluid at t_n+1.  lay:
-// the layout of A (0 two sets, 1 in place reversed, 2 in place pushed).
-template <int MODE>
+// that u = u_w; g = g^eq(T_w, u_w) (Eq. (17)).  COLLIDE: then collided (the
+// node's post-collision values of t_n+1 in s, t); otherwise s, t hold the
+// refilled values before the collision.  Returns false (nothing to refill)
+// unless p owned the node at t_n and it is fluid at t_n+1.  lay: the layout
+// of A (0 two sets, 1 in place reversed, 2 in place pushed).  SEQ_PULLS:
+// only the stencil nodes the extrapolation uses are pulled, one at a time
+// into the running sum, so that few values are live at once; otherwise all
+// in-lattice ones at once, before any is used.  Either way the same values
+// enter the same sums.
+template <int MODE, bool COLLIDE, bool SEQ_PULLS>
 __device__ bool refill_node(const Pops<ST<MODE>>& A, int lay, const PT_GLOBAL int32_t* Ocur,
                             const PT_GLOBAL int32_t* Onext, const PState& P, const Shape& sh, int p, int x,
                             int y, const LP& lp, const CC<typename Store<MODE>::R>& cc,
@@ -680,36 +687,67 @@ __device__ bool refill_node(const Pops<ST<MODE>>& A, int lay, const PT_GLOBAL in
             c = d;
         }
     }
-    // owner tests of the node and of the stencil, and the pulls of every
-    // in-lattice stencil node, all issued before any is used
-    int xs[3], ys[3];
-    bool fl[3];
-    R sm[3][9];
-    const bool mine = Ocur[k0] == p && Onext[k0] == -1;
-    for (int m = 0; m < 3; ++m) {
-        ys[m] = y + (m + 1) * EYd(c);
-        xs[m] = col_of(x + (m + 1) * EXd(c), lp);
-        fl[m] = false;
-        if (in_rows(ys[m], lp) && xs[m] >= 0) {
-            const size_t km = (size_t)ys[m] * lp.pitch + xs[m];
-            fl[m] = Ocur[km] == -1 && Onext[km] == -1;
-            R tt[5];
-            if (lay == 0) pull_node<S>(A, lp, cc, xs[m], ys[m], sm[m], tt);
-            else if (lay == 1) pull_node<S>(opp_view(A), lp, cc, xs[m], ys[m], sm[m], tt);
-            else pull_node_pushed<S>(A, lp, cc, xs[m], ys[m], sm[m], tt);
-        }
-    }
-    if (!mine) return false;
-    const int K = !fl[0] ? 0 : (!fl[1] ? 1 : (!fl[2] ? 2 : 3));
     const double uwx = P.ux - P.om * dy, uwy = P.uy + P.om * dx;
-    if (K == 3) {
-        for (int a = 0; a < 9; ++a) s[a] = (R)3 * sm[0][a] - (R)3 * sm[1][a] + sm[2][a];
-    } else if (K == 2) {
-        for (int a = 0; a < 9; ++a) s[a] = (R)2 * sm[0][a] - sm[1][a];
-    } else if (K == 1) {
-        for (int a = 0; a < 9; ++a) s[a] = sm[0][a];
+    // Eq. (16): 3 f1 - 3 f2 + f3, 2 f1 - f2 or f1 from the K fluid points
+    // (K = 0: the equilibrium at rho0 and u_w)
+    if constexpr (SEQ_PULLS) {
+        // owner tests first, then one stencil node at a time into the sum
+        bool fl[3];
+        for (int m = 0; m < 3; ++m) {
+            const int ym = y + (m + 1) * EYd(c), xm = col_of(x + (m + 1) * EXd(c), lp);
+            const size_t km = (size_t)ym * lp.pitch + xm;
+            fl[m] = in_rows(ym, lp) && xm >= 0 && Ocur[km] == -1 && Onext[km] == -1;
+        }
+        if (!(Ocur[k0] == p && Onext[k0] == -1)) return false;
+        const int K = !fl[0] ? 0 : (!fl[1] ? 1 : (!fl[2] ? 2 : 3));
+        if (K == 0) feq_dev<R>((R)lp.rho0, (R)lp.rho0, (R)uwx, (R)uwy, s);
+#pragma nounroll
+        for (int m = 0; m < K; ++m) {
+            const int ym = y + (m + 1) * EYd(c), xm = col_of(x + (m + 1) * EXd(c), lp);
+            R sm[9], tt[5];
+            if (lay == 0) pull_node<S>(A, lp, cc, xm, ym, sm, tt);
+            else if (lay == 1) pull_node<S>(opp_view(A), lp, cc, xm, ym, sm, tt);
+            else pull_node_pushed<S>(A, lp, cc, xm, ym, sm, tt);
+            if (m == 0) {
+                const R c0 = K == 3 ? (R)3 : (K == 2 ? (R)2 : (R)1);
+                for (int a = 0; a < 9; ++a) s[a] = K == 1 ? sm[a] : c0 * sm[a];
+            } else if (m == 1) {
+                for (int a = 0; a < 9; ++a) s[a] = K == 3 ? s[a] - (R)3 * sm[a] : s[a] - sm[a];
+            } else {
+                for (int a = 0; a < 9; ++a) s[a] = s[a] + sm[a];
+            }
+        }
     } else {
-        feq_dev<R>((R)lp.rho0, (R)lp.rho0, (R)uwx, (R)uwy, s);
+        // owner tests and the pulls of every in-lattice stencil node, all
+        // issued before any is used
+        int xs[3], ys[3];
+        bool fl[3];
+        R sm[3][9];
+        const bool mine = Ocur[k0] == p && Onext[k0] == -1;
+        for (int m = 0; m < 3; ++m) {
+            ys[m] = y + (m + 1) * EYd(c);
+            xs[m] = col_of(x + (m + 1) * EXd(c), lp);
+            fl[m] = false;
+            if (in_rows(ys[m], lp) && xs[m] >= 0) {
+                const size_t km = (size_t)ys[m] * lp.pitch + xs[m];
+                fl[m] = Ocur[km] == -1 && Onext[km] == -1;
+                R tt[5];
+                if (lay == 0) pull_node<S>(A, lp, cc, xs[m], ys[m], sm[m], tt);
+                else if (lay == 1) pull_node<S>(opp_view(A), lp, cc, xs[m], ys[m], sm[m], tt);
+                else pull_node_pushed<S>(A, lp, cc, xs[m], ys[m], sm[m], tt);
+            }
+        }
+        if (!mine) return false;
+        const int K = !fl[0] ? 0 : (!fl[1] ? 1 : (!fl[2] ? 2 : 3));
+        if (K == 3) {
+            for (int a = 0; a < 9; ++a) s[a] = (R)3 * sm[0][a] - (R)3 * sm[1][a] + sm[2][a];
+        } else if (K == 2) {
+            for (int a = 0; a < 9; ++a) s[a] = (R)2 * sm[0][a] - sm[1][a];
+        } else if (K == 1) {
+            for (int a = 0; a < 9; ++a) s[a] = sm[0][a];
+        } else {
+            feq_dev<R>((R)lp.rho0, (R)lp.rho0, (R)uwx, (R)uwy, s);
+        }
     }
     R drho = (R)0, jx = (R)0, jy = (R)0;
     for (int a = 0; a < 9; ++a) {
@@ -724,29 +762,36 @@ __device__ bool refill_node(const Pops<ST<MODE>>& A, int lay, const PT_GLOBAL in
     const R djy = (rho * (R)uwy - (R)0.5 * Fy) - jy;
     for (int a = 0; a < 9; ++a) s[a] += ((R)EXd(a) * djx + (R)EYd(a) * djy) * (R)(1.0 / 6.0);
     geq_dev<R>(Tw, (R)lp.T_sh, (R)uwx, (R)uwy, (R)lp.w5_0, (R)lp.w5_k, t);
-    R r_, u_, v_, T_;
-    collide<R>(cc, s, t, r_, u_, v_, T_);
+    if (COLLIDE) {
+        R r_, u_, v_, T_;
+        collide<R>(cc, s, t, r_, u_, v_, T_);
+    }
     return true;
 }
 
 // Refill of particle p's newborn nodes, the particle's lanes and one
 // lane per candidate from k_mask_mark.  REFILL_TWO_SETS: after the lattice
-// kernel, pulling from A and storing into B.  Split: REFILL_COMPUTE (the
-// refilled post-collision values of each candidate into rbuf, 16 doubles:
-// 14 values and a flag), REFILL_STORE (into the node's slots of the new
-// state) after the lattice kernel.  In place the split is needed: the
-// lattice kernel overwrites what the stencil pulls read, so the values are
-// computed before it.  An overlapped two-set step of a single run with 2- or
-// 4-byte values computes them at the end of the side stream, beside the
-// lattice kernel, and only the store waits on the main stream.  The values
-// are the same in every form.
+// kernel, pulling from A, colliding and storing into B.  Split:
+// REFILL_COMPUTE (the refilled values of each candidate into rbuf, 16
+// doubles: 14 values and a flag; collided unless refill_collides_at_store),
+// REFILL_STORE (into the node's slots of the new state) after the
+// lattice kernel.  In place the split is needed: the lattice kernel
+// overwrites what the stencil pulls read, so the values are computed before
+// it.  An overlapped two-set step of a single run computes them at the end
+// of the side stream, beside the lattice kernel, and only the store (with
+// 8-byte values the collision and the store) waits on the main stream.  The
+// values are the same bits in every form.
 enum RefillPart { REFILL_TWO_SETS = 0, REFILL_COMPUTE, REFILL_STORE };
+// Where a split refill collides: in the store half with 8-byte values (the
+// compute half then fits the register slot that one retiring FP64 lattice
+// wavefront frees), in the compute half otherwise (the narrower lattice
+// kernels leave it room, and the store on the main stream stays short).
+template <int MODE> __device__ __forceinline__ constexpr bool refill_collides_at_store() { return MODE == 0; }
 template <int MODE, int PART>
-__device__ __forceinline__ void refill_body(const RunStep& rs, unsigned bid) {
+__device__ __forceinline__ void refill_body(const RunStep& rs, const PartLanes& pl) {
     using S = Store<MODE>;
     using R = typename S::R;
     const LP& lp = rs.lp;
-    const PartLanes pl = part_lanes(lp, bid);
     const int lane = pl.lane, p = pl.p;
     if (p >= lp.np) return;
     const unsigned ccap = (unsigned)(4 * lp.nwin);
@@ -766,13 +811,19 @@ __device__ __forceinline__ void refill_body(const RunStep& rs, unsigned bid) {
             if (buf[slot + 14] == 0.0) continue;
             for (int a = 0; a < 9; ++a) s[a] = (R)buf[slot + a];
             for (int a = 0; a < 5; ++a) t[a] = (R)buf[slot + 9 + a];
+            if (refill_collides_at_store<MODE>()) {
+                R r_, u_, v_, T_;
+                collide<R>(args_cc<R>(lp), s, t, r_, u_, v_, T_);
+            }
             if (!lp.aa) store_node<S>(B, lp, args_cc<R>(lp), x, y, s, t);
             else if (rs.parity == 0) store_node_pushed<S>(A, lp, args_cc<R>(lp), x, y, s, t);   // the odd kernel ran
             else store_node<S>(opp_view(A), lp, args_cc<R>(lp), x, y, s, t);
             continue;
         }
         const int lay = lp.aa ? 1 + rs.parity : 0;
-        const bool mine = refill_node<MODE>(A, lay, gl(rs.Ocur), gl(rs.Onext), P1, sh, p, x, y, lp, args_cc<R>(lp), s, t);
+        const bool mine = refill_node<MODE, PART == REFILL_TWO_SETS || !refill_collides_at_store<MODE>(),
+                                      refill_collides_at_store<MODE>()>(A, lay, gl(rs.Ocur), gl(rs.Onext), P1, sh, p, x,
+                                                                        y, lp, args_cc<R>(lp), s, t);
         refilled += mine ? 1u : 0u;
         if (PART == REFILL_TWO_SETS) {
             if (mine) store_node<S>(B, lp, args_cc<R>(lp), x, y, s, t);
@@ -797,14 +848,21 @@ __device__ __forceinline__ void refill_body(const RunStep& rs, unsigned bid) {
 // tab[bmap[b].x]).  Both call the same body, so a run computes the same bits
 // alone and in a batch.
 
-__global__ __launch_bounds__(256) void k_links(RunStep rs) { links_body(rs, blockIdx.x); }
+__global__ __launch_bounds__(256) void k_links(RunStep rs) { links_body(rs, part_lanes(rs.lp, blockIdx.x)); }
 __global__ __launch_bounds__(256) void k_links_b(const RunStep* __restrict__ tab, const uint2* __restrict__ bmap) {
     const uint2 m = bmap[blockIdx.x];
-    links_body(tab[m.x], m.y);
+    links_body(tab[m.x], part_lanes(tab[m.x].lp, m.y));
 }
 
 template <int MODE, int NT>
-__global__ __launch_bounds__(NT) void k_link_pass(RunStep rs) { link_pass_body<MODE, NT>(rs, blockIdx.x); }
+__global__ __launch_bounds__(NT) void k_link_pass(RunStep rs) {
+    // the particles in band order, an eighth per XCD (xcd_slot): those
+    // whose gathers share cache lines are taken on one XCD, one after
+    // another.  Any order gives the same bits.
+    const unsigned s = xcd_slot(blockIdx.x);
+    if (s >= (unsigned)rs.lp.np) return;
+    link_pass_body<MODE, NT>(rs, rs.order[s]);
+}
 template <int MODE>
 __global__ __launch_bounds__(LAT_BLOCK) void k_link_pass_direct(RunStep rs) {
     link_pass_direct_body<MODE>(rs, blockIdx.x);
@@ -816,26 +874,44 @@ __global__ __launch_bounds__(256) void k_link_pass_b(const RunStep* __restrict__
     link_pass_body<MODE, 256>(tab[m.x], m.y);
 }
 
-__global__ __launch_bounds__(256) void k_particles(RunStep rs) { particles_body(rs, blockIdx.x); }
+__global__ __launch_bounds__(256) void k_particles(RunStep rs) { particles_body(rs, part_lanes(rs.lp, blockIdx.x)); }
 __global__ __launch_bounds__(256) void k_particles_b(const RunStep* __restrict__ tab,
                                                      const uint2* __restrict__ bmap) {
     const uint2 m = bmap[blockIdx.x];
-    particles_body(tab[m.x], m.y);
+    particles_body(tab[m.x], part_lanes(tab[m.x].lp, m.y));
 }
 
-__global__ __launch_bounds__(256) void k_mask_mark(RunStep rs) { mask_body(rs, blockIdx.x); }
+__global__ __launch_bounds__(256) void k_mask_mark(RunStep rs) {
+    mask_body(rs, blockIdx.x, part_lanes(rs.lp, blockIdx.x));
+}
 __global__ __launch_bounds__(256) void k_mask_mark_b(const RunStep* __restrict__ tab,
                                                      const uint2* __restrict__ bmap) {
     const uint2 m = bmap[blockIdx.x];
-    mask_body(tab[m.x], m.y);
+    mask_body(tab[m.x], m.y, part_lanes(tab[m.x].lp, m.y));
 }
 
 template <int MODE, int PART>
-__global__ __launch_bounds__(256) void k_refill(RunStep rs) { refill_body<MODE, PART>(rs, blockIdx.x); }
+__global__ __launch_bounds__(256) void k_refill(RunStep rs) {
+    refill_body<MODE, PART>(rs, part_lanes(rs.lp, blockIdx.x));
+}
+// The compute half with a block of one wavefront per particle (particles
+// whose lanes are a wavefront), used with 8-byte values: beside the FP64
+// lattice kernel a block of 256 threads must wait until four of its
+// wavefronts' register slots are free on one compute unit at once, a block
+// of 64 only for one.
+template <int MODE>
+__global__ __launch_bounds__(64) void k_refill_w(RunStep rs) {
+    PartLanes pl;
+    pl.p = (int)blockIdx.x;
+    pl.lane = (int)threadIdx.x;
+    pl.nl = 64;
+    pl.blk = false;
+    refill_body<MODE, REFILL_COMPUTE>(rs, pl);
+}
 template <int MODE, int PART>
 __global__ __launch_bounds__(256) void k_refill_b(const RunStep* __restrict__ tab, const uint2* __restrict__ bmap) {
     const uint2 m = bmap[blockIdx.x];
-    refill_body<MODE, PART>(tab[m.x], m.y);
+    refill_body<MODE, PART>(tab[m.x], part_lanes(tab[m.x].lp, m.y));
 }
 
 __global__ void k_link_q(const PState* __restrict__ Pc, const uint2* __restrict__ links, int n, int32_t* node,
@@ -892,6 +968,10 @@ unsigned run_blocks(int c, const LP& lp) {
     }
 }
 
+// Grid of the single-run link pass: a whole number of blocks per XCD, as
+// xcd_slot assumes (the blocks beyond the particle count return).
+static unsigned xcd_grid(unsigned nb) { return 8u * ((nb + 7u) / 8u); }
+
 hipError_t launch_step(int k, const RunStep& R, int mode, hipStream_t st) {
     if (R.lp.direct && R.lp.np > 0) {   // direct addressing: no collection, a thread per node
         if (k == SK_COLLECT) return hipSuccess;
@@ -906,13 +986,15 @@ hipError_t launch_step(int k, const RunStep& R, int mode, hipStream_t st) {
         case SK_COLLECT:   // R: the RunStep of the step whose links are collected
             k_links<<<nb, 256, links_block_lds(R.lp), st>>>(R);
             break;
-        case SK_PASS:
+        case SK_PASS: {
+            const unsigned nb8 = xcd_grid(nb);
             switch (pass_threads(R.lp.nwin, R.lp.np)) {
-                case 128: PTLBM_DISPATCH(mode, (k_link_pass<M, 128><<<nb, 128, 0, st>>>(R))); break;
-                case 256: PTLBM_DISPATCH(mode, (k_link_pass<M, 256><<<nb, 256, 0, st>>>(R))); break;
-                default: PTLBM_DISPATCH(mode, (k_link_pass<M, 512><<<nb, 512, 0, st>>>(R))); break;
+                case 128: PTLBM_DISPATCH(mode, (k_link_pass<M, 128><<<nb8, 128, 0, st>>>(R))); break;
+                case 256: PTLBM_DISPATCH(mode, (k_link_pass<M, 256><<<nb8, 256, 0, st>>>(R))); break;
+                default: PTLBM_DISPATCH(mode, (k_link_pass<M, 512><<<nb8, 512, 0, st>>>(R))); break;
             }
             break;
+        }
         case SK_PARTICLES: k_particles<<<nb, 256, 0, st>>>(R); break;
         case SK_MASK:   // in place, the refill is computed here, before the lattice kernel
             k_mask_mark<<<nb, 256, 0, st>>>(R);
@@ -938,6 +1020,8 @@ hipError_t launch_refill_part(const RunStep& R, int mode, bool store, hipStream_
     if (nb == 0) return hipSuccess;
     if (store) {
         PTLBM_DISPATCH(mode, (k_refill<M, REFILL_STORE><<<nb, 256, 0, st>>>(R)));
+    } else if (mode == 0 && R.lp.lpp <= 64) {
+        k_refill_w<0><<<(unsigned)R.lp.np, 64, 0, st>>>(R);
     } else {
         PTLBM_DISPATCH(mode, (k_refill<M, REFILL_COMPUTE><<<nb, 256, 0, st>>>(R)));
     }

@@ -19,7 +19,7 @@ struct Layout {
     size_t npitched = 0, array_stride = 0, state_bytes = 0;
     size_t off_S[2] = {0, 0}, off_O[2] = {0, 0}, off_P = 0, off_Fh = 0, off_Fa = 0, off_seg = 0,
            off_links = 0, off_lscratch = 0, off_counter = 0, off_status = 0, off_bins[2] = {0, 0},
-           off_bcnt[2] = {0, 0}, off_cand = 0, off_ncand = 0, off_nborn = 0, off_rbuf = 0, off_fscratch = 0, off_cc = 0,
+           off_bcnt[2] = {0, 0}, off_cand = 0, off_ncand = 0, off_nborn = 0, off_order = 0, off_rbuf = 0, off_fscratch = 0, off_cc = 0,
            total = 0;
     int field_rows = 0;   // rows per chunk of the field upload / read-back scratch
     int nwin = 0;
