@@ -387,9 +387,9 @@ namespace {
 //   main: link pass -> [fork] -> lattice -> wait(side) -> refill store
 //   side: wait(fork) -> particles -> mask -> links of t_n+1 -> refill values -> [side]
 // (FP64 at 4000^2 with 4800 particles: 21.44 k MLUPS with the whole refill
-// after the lattice kernel, 21.62 k split; the split refill's compute half
-// needs many registers and slows the FP64 lattice kernel beside it by 1 %,
-// less than the refill it takes off the main stream.)
+// after the lattice kernel, 21.62 k split with a compute half that waited for
+// register room beside the lattice kernel, 22.24 k with the compute half
+// that fits one retiring lattice wavefront's registers, k_refill_w.)
 // In place the refill's values are computed with the owner map, before the
 // lattice kernel overwrites the state they are pulled from, so the lattice
 // kernel waits for that part of the side stream:

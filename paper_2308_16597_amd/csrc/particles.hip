@@ -773,7 +773,7 @@ __device__ bool refill_node(const Pops<ST<MODE>>& A, int lay, const PT_GLOBAL in
 // lane per candidate from k_mask_mark.  REFILL_TWO_SETS: after the lattice
 // kernel, pulling from A, colliding and storing into B.  Split:
 // REFILL_COMPUTE (the refilled values of each candidate into rbuf, 16
-// doubles: 14 values and a flag; collided unless refill_collides_at_store),
+// doubles: 14 values and a flag; collided unless LATE),
 // REFILL_STORE (into the node's slots of the new state) after the
 // lattice kernel.  In place the split is needed: the lattice kernel
 // overwrites what the stencil pulls read, so the values are computed before
@@ -782,12 +782,15 @@ __device__ bool refill_node(const Pops<ST<MODE>>& A, int lay, const PT_GLOBAL in
 // 8-byte values the collision and the store) waits on the main stream.  The
 // values are the same bits in every form.
 enum RefillPart { REFILL_TWO_SETS = 0, REFILL_COMPUTE, REFILL_STORE };
-// Where a split refill collides: in the store half with 8-byte values (the
-// compute half then fits the register slot that one retiring FP64 lattice
-// wavefront frees), in the compute half otherwise (the narrower lattice
-// kernels leave it room, and the store on the main stream stays short).
-template <int MODE> __device__ __forceinline__ constexpr bool refill_collides_at_store() { return MODE == 0; }
-template <int MODE, int PART>
+// LATE (the compute half of a single two-set FP64 run with a wavefront per
+// particle, k_refill_w<0, true>): the compute half pulls only the stencil
+// nodes it uses, one at a time, and leaves the collision to the store half,
+// so that it fits the register slot that one retiring FP64 lattice
+// wavefront frees.  Otherwise the compute half pulls every stencil node at
+// once and collides (in place it runs alone, before the lattice kernel, and
+// the narrower lattice kernels leave it room).  The whole refill pulls one
+// node at a time with 8-byte values.  The same arithmetic either way.
+template <int MODE, int PART, bool LATE>
 __device__ __forceinline__ void refill_body(const RunStep& rs, const PartLanes& pl) {
     using S = Store<MODE>;
     using R = typename S::R;
@@ -811,7 +814,7 @@ __device__ __forceinline__ void refill_body(const RunStep& rs, const PartLanes& 
             if (buf[slot + 14] == 0.0) continue;
             for (int a = 0; a < 9; ++a) s[a] = (R)buf[slot + a];
             for (int a = 0; a < 5; ++a) t[a] = (R)buf[slot + 9 + a];
-            if (refill_collides_at_store<MODE>()) {
+            if (LATE) {
                 R r_, u_, v_, T_;
                 collide<R>(args_cc<R>(lp), s, t, r_, u_, v_, T_);
             }
@@ -821,8 +824,8 @@ __device__ __forceinline__ void refill_body(const RunStep& rs, const PartLanes& 
             continue;
         }
         const int lay = lp.aa ? 1 + rs.parity : 0;
-        const bool mine = refill_node<MODE, PART == REFILL_TWO_SETS || !refill_collides_at_store<MODE>(),
-                                      refill_collides_at_store<MODE>()>(A, lay, gl(rs.Ocur), gl(rs.Onext), P1, sh, p, x,
+        const bool mine = refill_node<MODE, PART == REFILL_TWO_SETS || !LATE,
+                                      LATE || (PART == REFILL_TWO_SETS && MODE == 0)>(A, lay, gl(rs.Ocur), gl(rs.Onext), P1, sh, p, x,
                                                                         y, lp, args_cc<R>(lp), s, t);
         refilled += mine ? 1u : 0u;
         if (PART == REFILL_TWO_SETS) {
@@ -890,28 +893,28 @@ __global__ __launch_bounds__(256) void k_mask_mark_b(const RunStep* __restrict__
     mask_body(tab[m.x], m.y, part_lanes(tab[m.x].lp, m.y));
 }
 
-template <int MODE, int PART>
+template <int MODE, int PART, bool LATE = false>
 __global__ __launch_bounds__(256) void k_refill(RunStep rs) {
-    refill_body<MODE, PART>(rs, part_lanes(rs.lp, blockIdx.x));
+    refill_body<MODE, PART, LATE>(rs, part_lanes(rs.lp, blockIdx.x));
 }
 // The compute half with a block of one wavefront per particle (particles
-// whose lanes are a wavefront), used with 8-byte values: beside the FP64
-// lattice kernel a block of 256 threads must wait until four of its
-// wavefronts' register slots are free on one compute unit at once, a block
-// of 64 only for one.
-template <int MODE>
+// whose lanes are a wavefront): beside the lattice kernel a block of 256
+// threads must wait until four of its wavefronts' register slots are free
+// on one compute unit at once, a block of 64 only for one.  LATE with
+// 8-byte values.
+template <int MODE, bool LATE>
 __global__ __launch_bounds__(64) void k_refill_w(RunStep rs) {
     PartLanes pl;
     pl.p = (int)blockIdx.x;
     pl.lane = (int)threadIdx.x;
     pl.nl = 64;
     pl.blk = false;
-    refill_body<MODE, REFILL_COMPUTE>(rs, pl);
+    refill_body<MODE, REFILL_COMPUTE, LATE>(rs, pl);
 }
 template <int MODE, int PART>
 __global__ __launch_bounds__(256) void k_refill_b(const RunStep* __restrict__ tab, const uint2* __restrict__ bmap) {
     const uint2 m = bmap[blockIdx.x];
-    refill_body<MODE, PART>(tab[m.x], part_lanes(tab[m.x].lp, m.y));
+    refill_body<MODE, PART, false>(tab[m.x], part_lanes(tab[m.x].lp, m.y));
 }
 
 __global__ void k_link_q(const PState* __restrict__ Pc, const uint2* __restrict__ links, int n, int32_t* node,
@@ -1018,10 +1021,15 @@ hipError_t launch_step(int k, const RunStep& R, int mode, hipStream_t st) {
 hipError_t launch_refill_part(const RunStep& R, int mode, bool store, hipStream_t st) {
     const unsigned nb = run_blocks(GC_WAVE, R.lp);
     if (nb == 0) return hipSuccess;
-    if (store) {
+    const bool late = mode == 0 && R.lp.lpp <= 64;   // k_refill_w<0, true> and its store
+    if (store && late) {
+        k_refill<0, REFILL_STORE, true><<<nb, 256, 0, st>>>(R);
+    } else if (store) {
         PTLBM_DISPATCH(mode, (k_refill<M, REFILL_STORE><<<nb, 256, 0, st>>>(R)));
-    } else if (mode == 0 && R.lp.lpp <= 64) {
-        k_refill_w<0><<<(unsigned)R.lp.np, 64, 0, st>>>(R);
+    } else if (late) {
+        k_refill_w<0, true><<<(unsigned)R.lp.np, 64, 0, st>>>(R);
+    } else if (R.lp.lpp <= 64) {
+        PTLBM_DISPATCH(mode, (k_refill_w<M, false><<<(unsigned)R.lp.np, 64, 0, st>>>(R)));
     } else {
         PTLBM_DISPATCH(mode, (k_refill<M, REFILL_COMPUTE><<<nb, 256, 0, st>>>(R)));
     }
