@@ -691,9 +691,9 @@ int set_particles_rows(lbm_handle h, int32_t n, const double* rows, int cols) {
     if (n > 0) {
         for (int r = 0; r < 3; ++r)
             HIPCHK(h, hipMemcpyAsync(d.P[r], P.data(), sizeof(PState) * n, hipMemcpyHostToDevice, st));
-        // the link pass takes the particles in rows of bands one neighbour
-        // cell high, left to right within a band: neighbouring blocks then
-        // gather from the same cache lines
+        // the order the link pass takes the particles in: row bands one
+        // neighbour cell high, left to right within a band, so that blocks
+        // that run close in time gather from the same cache lines
         const double band = h->p.max_diameter + std::max(h->p.rep_range, 0.0);
         std::vector<unsigned> order((size_t)n);
         std::vector<long long> key((size_t)n);

@@ -778,9 +778,9 @@ __device__ bool refill_node(const Pops<ST<MODE>>& A, int lay, const PT_GLOBAL in
 // lattice kernel.  In place the split is needed: the lattice kernel
 // overwrites what the stencil pulls read, so the values are computed before
 // it.  An overlapped two-set step of a single run computes them at the end
-// of the side stream, beside the lattice kernel, and only the store (with
-// 8-byte values the collision and the store) waits on the main stream.  The
-// values are the same bits in every form.
+// of the side stream, beside the lattice kernel, and only the store (LATE:
+// the collision and the store) waits on the main stream.  The values are the
+// same bits in every form.
 enum RefillPart { REFILL_TWO_SETS = 0, REFILL_COMPUTE, REFILL_STORE };
 // LATE (the compute half of a single two-set FP64 run with a wavefront per
 // particle, k_refill_w<0, true>): the compute half pulls only the stencil
