@@ -824,9 +824,10 @@ __device__ __forceinline__ void refill_body(const RunStep& rs, const PartLanes& 
             continue;
         }
         const int lay = lp.aa ? 1 + rs.parity : 0;
-        const bool mine = refill_node<MODE, PART == REFILL_TWO_SETS || !LATE,
-                                      LATE || (PART == REFILL_TWO_SETS && MODE == 0)>(A, lay, gl(rs.Ocur), gl(rs.Onext), P1, sh, p, x,
-                                                                        y, lp, args_cc<R>(lp), s, t);
+        constexpr bool COLLIDE = PART == REFILL_TWO_SETS || !LATE;   // LATE: the store half collides
+        constexpr bool SEQ = LATE || (PART == REFILL_TWO_SETS && MODE == 0);
+        const bool mine = refill_node<MODE, COLLIDE, SEQ>(A, lay, gl(rs.Ocur), gl(rs.Onext), P1, sh, p, x, y, lp,
+                                                          args_cc<R>(lp), s, t);
         refilled += mine ? 1u : 0u;
         if (PART == REFILL_TWO_SETS) {
             if (mine) store_node<S>(B, lp, args_cc<R>(lp), x, y, s, t);
