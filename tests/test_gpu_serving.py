@@ -115,6 +115,31 @@ def test_link_pass_block_sizes_give_the_same_bits():
         sim.close()
 
 
+def test_edge_runs_alone_and_in_mix():
+    """A batch of a run created for particles that holds none, a run with a
+    single particle and an 8 x 9 lattice (the smallest accepted) with
+    moving walls: every run matches itself alone bit for bit (the empty run
+    adds no blocks to the per-particle grids)."""
+    base = dict(nu=0.05, alpha=0.04, gravity=1e-4, beta=0.5, particle_T=1.0, rho_ratio=2.0)
+    runs = [(dict(base, nx=96, ny=64, max_particles=3, max_diameter=12.0), None,
+             lbm_inputs.smooth_fields(96, 64, seed=8)),
+            (dict(base, nx=80, ny=72, max_particles=1, max_diameter=12.0),
+             np.array([[39.6, 35.2, 6.0, 0.03, -0.02, 0.0, 0.002]]), None),
+            (dict(base, nx=8, ny=9, wall_T=(0.9, 0.1), wall_ux=(0.02, -0.01)), None,
+             lbm_inputs.smooth_fields(8, 9, seed=9))]
+    alone = [_make(r) for r in runs]
+    mix = [_make(r) for r in runs]
+    for call in ([13, 7, 20], [36, 36, 36], [0, 12, 5], [36, 36, 36]):
+        for sim, n in zip(alone, call):
+            sim.step(n)
+        lbm.step_many(mix, call)
+        for r, (a, b) in enumerate(zip(alone, mix)):
+            _same(_state(a), _state(b), f"run {r} after call {call}")
+        _say("edge runs", call, "bitwise equal")
+    for sim in alone + mix:
+        sim.close()
+
+
 def test_step_many_argument_errors():
     runs = _runs("f64")
     a, b = _make(runs[0]), _make(runs[1])
