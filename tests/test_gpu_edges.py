@@ -3,7 +3,8 @@ a single particle, a run filled to its particle capacity, particles removed
 from a run that had them (the step then runs with no particle at all over
 buffers that still hold the earlier set) and set again, and particles whose
 windows all lie in one row band (the link pass's particle order is then the
-order along x alone).  Same bar as the other FP64 parity tests: fields within
+order along x alone), and particles near the far end of lattices 65 535
+nodes long.  Same bar as the other FP64 parity tests: fields within
 1e-12 (velocities on the flow's scale), particles within 1e-12, owner maps
 and link sets bit-identical, link fractions within 1e-12 after steps."""
 import numpy as np
@@ -109,3 +110,34 @@ def test_particles_in_one_row_band():
     sim.step(15)
     orc.step(15)
     _check(sim, orc, "one row band")
+
+
+@pytest.mark.parametrize("shape", ["wide", "tall"])
+def test_extreme_coordinates(shape):
+    """Lattices at the largest accepted edge (65 535 nodes): link records
+    and newborn candidates pack a node as x | y << 16, so particles near
+    the far end (and across the periodic seam at x = 65 535) use the top
+    bits of both halves."""
+    _say("extreme coordinates", shape)
+    if shape == "wide":
+        nx, ny = 65535, 48
+        rows = np.array([[10.3, 20.6, 6.0, 0.02, 0.0, 0.0, 0.001],
+                         [40000.7, 24.2, 6.0, -0.02, 0.01, 0.0, 0.0],
+                         [65532.2, 22.9, 6.0, 0.03, 0.0, 0.0, -0.002]])
+    else:
+        nx, ny = 48, 65535
+        rows = np.array([[20.6, 20.2, 6.0, 0.0, -0.02, 0.0, 0.001],
+                         [24.2, 40000.6, 6.0, 0.01, 0.02, 0.0, 0.0],
+                         [22.9, 65510.3, 6.0, 0.0, 0.03, 0.0, -0.002]])
+    kw = dict(C1_PHYS, nx=nx, ny=ny, max_particles=3, max_diameter=12.0)
+    sim, orc = make_pair(**kw)
+    sim.set_particles(rows)
+    orc.set_particles(rows)
+    lg, lo = sim.links(), orc.links()
+    compare_links(lg, lo)
+    far = lg["node"] % nx if shape == "wide" else lg["node"] // nx
+    assert far.max() >= 65500
+    for n in (1, 2):
+        sim.step(n)
+        orc.step(n)
+        _check(sim, orc, shape)
