@@ -4,7 +4,7 @@ from a run that had them (the step then runs with no particle at all over
 buffers that still hold the earlier set) and set again, and particles whose
 windows all lie in one row band (the link pass's particle order is then the
 order along x alone), and particles near the far end of lattices 65 535
-nodes long.  Same bar as the other FP64 parity tests: fields within
+nodes long; the last two also with in-place streaming.  Same bar as the other FP64 parity tests: fields within
 1e-12 (velocities on the flow's scale), particles within 1e-12, owner maps
 and link sets bit-identical, link fractions within 1e-12 after steps."""
 import numpy as np
@@ -65,12 +65,13 @@ def test_particles_at_capacity():
         sim.set_particles(lbm_inputs.rsa_particles(128, 128, n + 1, 10.0, 1.0, 22))
 
 
-def test_particles_removed_then_set_again():
+@pytest.mark.parametrize("streaming", ["two_sets", "in_place"])
+def test_particles_removed_then_set_again(streaming):
     """Three particles for 10 steps; then none (the particle kernels have no
     work and the buffers still hold the earlier set) for 13 steps; then two
     others.  Each set restarts the fluid at rest on both sides."""
-    _say("particles removed and set again, 112 x 72")
-    kw = dict(C1_PHYS, nx=112, ny=72, max_particles=4, max_diameter=14.0)
+    _say("particles removed and set again, 112 x 72,", streaming)
+    kw = dict(C1_PHYS, nx=112, ny=72, max_particles=4, max_diameter=14.0, streaming=streaming)
     sim, orc = make_pair(**kw)
     first = np.array([[20.4, 30.2, 6.0, 0.02, 0.0, 0.0, 0.0],
                       [60.7, 40.9, 7.0, -0.01, 0.01, 0.0, 0.002],
@@ -112,13 +113,14 @@ def test_particles_in_one_row_band():
     _check(sim, orc, "one row band")
 
 
+@pytest.mark.parametrize("streaming", ["two_sets", "in_place"])
 @pytest.mark.parametrize("shape", ["wide", "tall"])
-def test_extreme_coordinates(shape):
+def test_extreme_coordinates(shape, streaming):
     """Lattices at the largest accepted edge (65 535 nodes): link records
     and newborn candidates pack a node as x | y << 16, so particles near
     the far end (and across the periodic seam at x = 65 535) use the top
     bits of both halves."""
-    _say("extreme coordinates", shape)
+    _say("extreme coordinates", shape, streaming)
     if shape == "wide":
         nx, ny = 65535, 48
         rows = np.array([[10.3, 20.6, 6.0, 0.02, 0.0, 0.0, 0.001],
@@ -129,7 +131,7 @@ def test_extreme_coordinates(shape):
         rows = np.array([[20.6, 20.2, 6.0, 0.0, -0.02, 0.0, 0.001],
                          [24.2, 40000.6, 6.0, 0.01, 0.02, 0.0, 0.0],
                          [22.9, 65510.3, 6.0, 0.0, 0.03, 0.0, -0.002]])
-    kw = dict(C1_PHYS, nx=nx, ny=ny, max_particles=3, max_diameter=12.0)
+    kw = dict(C1_PHYS, nx=nx, ny=ny, max_particles=3, max_diameter=12.0, streaming=streaming)
     sim, orc = make_pair(**kw)
     sim.set_particles(rows)
     orc.set_particles(rows)
