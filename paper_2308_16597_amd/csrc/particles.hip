@@ -429,9 +429,13 @@ __device__ __forceinline__ void particles_body(const RunStep& rs, const PartLane
     unsigned* status = rs.status;
     const int p = pl.p;
     if (p >= lp.np) return;
+    // the loads that need nothing else first, issued together
+    const PState po = ld_state(rs.Pold + p);
+    const PState P = ld_state(Pc + p);
+    PT_GLOBAL double* Fa = gl(rs.Fa);
+    const double hx = Fa[4 * p + 0], hy = Fa[4 * p + 1], hz = Fa[4 * p + 2];   // from the link pass
     {   // the owner-map buffer that will hold t_n+1 still holds t_n-1: clear
         // this particle's marks there (its window at t_n-1)
-        const PState po = ld_state(rs.Pold + p);
         const Win wo = window_of(po);
         PT_GLOBAL int32_t* Onext = gl(rs.Onext);
         if (particle_ok(po, lp) && wo.nxw <= lp.nwin && wo.nyw <= lp.nwin)
@@ -443,10 +447,7 @@ __device__ __forceinline__ void particles_body(const RunStep& rs, const PartLane
     }
     if (threadIdx.x >= 64 && pl.blk) return;   // the rest on the first wavefront
     const int lane = threadIdx.x & 63;
-    const PState P = ld_state(Pc + p);
     const Shape sh = shape_of(P);
-    PT_GLOBAL double* Fa = gl(rs.Fa);
-    const double hx = Fa[4 * p + 0], hy = Fa[4 * p + 1], hz = Fa[4 * p + 2];   // from the link pass
     double Rx = 0.0, Ry = 0.0;
     if (lp.repulsion && particle_ok(P, lp)) {
         const int c0 = cell_of(P, lp);
@@ -469,8 +470,9 @@ __device__ __forceinline__ void particles_body(const RunStep& rs, const PartLane
             }
             if (cell_ok) {
                 const int c = yy * lp.ncx + xx;
-                if ((unsigned)sl < min(cnt_cur[c], (unsigned)BINCAP)) {
-                    const int qq = (int)bins_cur[(size_t)c * BINCAP + sl];
+                const unsigned cnt = cnt_cur[c];
+                const int qq = (int)bins_cur[(size_t)c * BINCAP + sl];   // with the count: one round trip
+                if ((unsigned)sl < min(cnt, (unsigned)BINCAP)) {
                     if (qq != p && repulsion_pair(lp, P, sh, ld_state(Pc + qq), fx, fy)) {
                         near = true;
                         q = qq;
@@ -582,14 +584,15 @@ __device__ __forceinline__ void mask_body(const RunStep& rs, unsigned bid, const
     const int lane = pl.lane, p = pl.p;
     if (p >= lp.np) return;
     const PState P = ld_state(Pp + p);
+    const PState Q0 = Pprev != nullptr ? ld_state(Pprev + p) : PState{};   // issued with P
     if (!particle_ok(P, lp)) return;
     Win w = window_of(P);
     if (w.nxw > lp.nwin || w.nyw > lp.nwin) return;
     int xa = w.x0, xb = w.x0 + w.nxw, ya = w.y0, yb = w.y0 + w.nyw;
     PState Q{};
-    const bool with_prev = Pprev != nullptr && particle_ok(ld_state(Pprev + p), lp);
+    const bool with_prev = Pprev != nullptr && particle_ok(Q0, lp);
     if (with_prev) {
-        Q = ld_state(Pprev + p);
+        Q = Q0;
         Win v = window_of(Q);
         if (lp.periodic_x) {   // the two windows on the same side of the seam
             if (v.x0 - w.x0 > lp.nx / 2) v.x0 -= lp.nx;
