@@ -173,7 +173,8 @@ size_t lbm_collect_lds_bytes(const lbm_params* p);
  * initialise the fluid at rest (rho0, T_fluid0) with no particles.
  * hip_stream is a hipStream_t (NULL: the handle creates its own stream).
  * On failure *out is NULL and lbm_last_error(NULL) explains: LBM_EINVAL for
- * invalid parameters, LBM_ENOMEM when hipMalloc fails. */
+ * invalid parameters, LBM_ENOMEM when hipMalloc runs out of device memory,
+ * LBM_EDEVICE for any other HIP error (no GPU, for one). */
 int lbm_create(const lbm_params* p, void* hip_stream, lbm_handle* out);
 
 /* Same, carving every device buffer out of the caller's allocation

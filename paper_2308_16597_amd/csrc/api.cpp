@@ -235,11 +235,13 @@ int create_common(const lbm_params* p, void* dev_ptr, size_t bytes, void* stream
         }
         h->base = (char*)dev_ptr;
     } else {
-        hipError_t e = hipMalloc((void**)&h->base, h->L.total);
+        const size_t total = h->L.total;
+        hipError_t e = hipMalloc((void**)&h->base, total);
         if (e != hipSuccess) {
             delete h;
             (void)hipGetLastError();
-            return fail(nullptr, LBM_ENOMEM, "hipMalloc of %zu bytes: %s", h->L.total, hipGetErrorString(e));
+            return fail(nullptr, e == hipErrorOutOfMemory ? LBM_ENOMEM : LBM_EDEVICE, "hipMalloc of %zu bytes: %s",
+                        total, hipGetErrorString(e));
         }
         h->own_mem = true;
     }

@@ -139,3 +139,16 @@ def test_arena_smaller_than_the_run_is_a_budget_error():
     with pytest.raises(lbm.LbmError) as e:
         lbm.lbm_create_in_arena(p, 1 << 20, lbm.lbm_bytes_required(p) - 256)
     assert e.value.rc == lbm.LBM_EBUDGET
+
+
+def test_create_without_a_gpu_is_a_device_error():
+    """With no GPU the library fails loudly at creation: a device error that
+    names the allocation, and no handle (there is no CPU path)."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    p = lbm.lbm_params_default(nx=64, ny=64)
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_create(p)
+    assert e.value.rc == lbm.LBM_EDEVICE
+    assert "hipMalloc" in str(e.value) and "hipMalloc" in lbm.lbm_last_error()
