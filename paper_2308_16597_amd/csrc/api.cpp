@@ -49,6 +49,9 @@ Layout make_layout(const lbm_params& p) {
     L.pitch = (int)round_up((size_t)p.nx, 64);
     L.npitched = (size_t)L.pitch * p.ny;
     const size_t es = elem_size(p.storage);
+    // a state: 14 arrays, each 64 KiB aligned and staggered by 4 KiB (2- and
+    // 4-byte values), or the same bytes as one block of 64-node tiles
+    // (8-byte values, lattice.h)
     L.array_stride = round_up(L.npitched * es, kArrayAlign) + kStagger;
     L.state_bytes = round_up(14 * L.array_stride, kArrayAlign);
     size_t off = 0;
@@ -273,7 +276,8 @@ int create_common(const lbm_params* p, void* dev_ptr, size_t bytes, void* stream
     d.mode = p->storage;
     const Layout& L = h->L;
     for (int s = 0; s < 2; ++s)
-        for (int i = 0; i < 14; ++i) d.S[s][i] = h->base + L.off_S[s] + (size_t)i * L.array_stride;
+        for (int i = 0; i < 14; ++i)   // 8-byte values in tiles of 64 nodes (lattice.h), others array by array
+            d.S[s][i] = h->base + L.off_S[s] + (size_t)i * (elem_size(p->storage) == 8 ? 64 * 8 : L.array_stride);
     d.O[0] = (int32_t*)(h->base + L.off_O[0]);
     d.O[1] = (int32_t*)(h->base + L.off_O[1]);
     const size_t cap = (size_t)(p->max_particles > 0 ? p->max_particles : 0);

@@ -198,9 +198,9 @@ __global__ __launch_bounds__(LAT_BLOCK) void k_macros(Pops<ST<MODE>> A, const in
         for (int i = 0; i < 5; ++i) t[i] = S::ld(pushed_ptr(A.g[i], A.g[OPPd(i)], lp, x, y, i));
     } else {
 #pragma unroll
-        for (int i = 0; i < 9; ++i) s[i] = S::ld(A.f[i] + k) - (S::shifted ? (R)0 : w9<R>(i) * (R)lp.rho0);
+        for (int i = 0; i < 9; ++i) s[i] = S::ld(A.f[i] + tix<ST<MODE>>(k)) - (S::shifted ? (R)0 : w9<R>(i) * (R)lp.rho0);
 #pragma unroll
-        for (int i = 0; i < 5; ++i) t[i] = S::ld(A.g[i] + k);
+        for (int i = 0; i < 5; ++i) t[i] = S::ld(A.g[i] + tix<ST<MODE>>(k));
     }
     R drho = (R)0, jx = (R)0, jy = (R)0, dT = (R)0;
 #pragma unroll

@@ -61,41 +61,42 @@ __device__ __forceinline__ LinkEval eval_link(const RunStep& rs, const PState& P
     double fi, fib = 0.0, fi1 = 0.0, fib1 = 0.0, fi2 = 0.0, gi = 0.0, gib = 0.0, gi1 = 0.0;
     if (lay != 2) {
         const int si = lay ? ib : i, sib = lay ? i : ib;
-        fi = (double)S::ld(F(si) + k);
+        const size_t tk = tix<ST<MODE>>(k), tk1 = tix<ST<MODE>>(k1), tk2 = tix<ST<MODE>>(k2);
+        fi = (double)S::ld(F(si) + tk);
         if (get_lo) {
-            fi1 = (double)S::ld(F(si) + k1);
-            fi2 = (double)S::ld(F(si) + k2);
+            fi1 = (double)S::ld(F(si) + tk1);
+            fi2 = (double)S::ld(F(si) + tk2);
         }
         if (get_hi) {
-            fib = (double)S::ld(F(sib) + k);
-            fib1 = (double)S::ld(F(sib) + k1);
+            fib = (double)S::ld(F(sib) + tk);
+            fib1 = (double)S::ld(F(sib) + tk1);
         }
         if (i <= 4) {
-            gi = (double)S::ld(F(9 + si) + k);
-            gib = (double)S::ld(F(9 + sib) + k);
-            gi1 = (double)S::ld(F(9 + si) + k1);
+            gi = (double)S::ld(F(9 + si) + tk);
+            gib = (double)S::ld(F(9 + sib) + tk);
+            gi1 = (double)S::ld(F(9 + si) + tk1);
         }
     } else {
         int sl;
         size_t at;
         at = pushed_at(lp, x, y, i, sl);
-        fi = (double)S::ld(F(sl) + at);
-        if (i <= 4) gi = (double)S::ld(F(9 + sl) + at);
+        fi = (double)S::ld(F(sl) + tix<ST<MODE>>(at));
+        if (i <= 4) gi = (double)S::ld(F(9 + sl) + tix<ST<MODE>>(at));
         at = pushed_at(lp, x, y, ib, sl);
-        if (get_hi) fib = (double)S::ld(F(sl) + at);
-        if (i <= 4) gib = (double)S::ld(F(9 + sl) + at);
+        if (get_hi) fib = (double)S::ld(F(sl) + tix<ST<MODE>>(at));
+        if (i <= 4) gib = (double)S::ld(F(9 + sl) + tix<ST<MODE>>(at));
         if (in1) {
             at = pushed_at(lp, x1, y1, i, sl);
-            if (get_lo) fi1 = (double)S::ld(F(sl) + at);
-            if (i <= 4) gi1 = (double)S::ld(F(9 + sl) + at);
+            if (get_lo) fi1 = (double)S::ld(F(sl) + tix<ST<MODE>>(at));
+            if (i <= 4) gi1 = (double)S::ld(F(9 + sl) + tix<ST<MODE>>(at));
             if (get_hi) {
                 at = pushed_at(lp, x1, y1, ib, sl);
-                fib1 = (double)S::ld(F(sl) + at);
+                fib1 = (double)S::ld(F(sl) + tix<ST<MODE>>(at));
             }
         }
         if (in2 && get_lo) {
             at = pushed_at(lp, x2, y2, i, sl);
-            fi2 = (double)S::ld(F(sl) + at);
+            fi2 = (double)S::ld(F(sl) + tix<ST<MODE>>(at));
         }
     }
     const bool have1 = in1 && o1 == -1;

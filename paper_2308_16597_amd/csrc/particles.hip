@@ -277,8 +277,8 @@ __device__ __forceinline__ void link_pass_link(const RunStep& rs, const PState& 
     const size_t kb = (size_t)(y + ey) * lp.pitch + col_of(x + ex, lp);   // a node of P
     const size_t ko = lay == 2 ? k : kb;
     const int so = lay == 1 ? i : ib;
-    S::st(Fw(so) + ko, (typename S::R)e.fnew);
-    if (i <= 4) S::st(Fw(9 + so) + ko, (typename S::R)e.gnew);
+    S::st(Fw(so) + tix<ST<MODE>>(ko), (typename S::R)e.fnew);
+    if (i <= 4) S::st(Fw(9 + so) + tix<ST<MODE>>(ko), (typename S::R)e.gnew);
     // Eq. (13) on full populations (stored value + rest part w rho0)
     const double w9i = i <= 4 ? 1.0 / 9.0 : 1.0 / 36.0;
     const double shf = S::shifted ? lp.rho0 : 0.0;
