@@ -9,19 +9,25 @@ namespace ptlbm {
 
 // A -> B, one V (8 or 16 bytes: 1 to 8 nodes of each array; every array
 // holds the padded lattice, whose size is a multiple of 16 bytes) per lane
-// and array, non-temporal loads and stores, in the arrays' own layout (8-byte
-// values in tiles of 64 nodes: a lane's 1 or 2 nodes lie in one tile).
-template <class V, class T>
+// and array, non-temporal loads and stores.
+template <class V>
 __global__ __launch_bounds__(LAT_BLOCK) void k_copy14(RunStep rs, size_t nchunks) {
     const size_t c = (size_t)blockIdx.x * LAT_BLOCK + threadIdx.x;
     if (c >= nchunks) return;
-    const size_t off = tix<T>(c * (sizeof(V) / sizeof(T))) * sizeof(T);
 #pragma unroll
     for (int i = 0; i < 14; ++i) {
-        const PT_GLOBAL V* a = (const PT_GLOBAL V*)((const PT_GLOBAL char*)rs.A[i] + off);
-        PT_GLOBAL V* b = (PT_GLOBAL V*)((PT_GLOBAL char*)rs.B[i] + off);
-        __builtin_nontemporal_store(__builtin_nontemporal_load(a), b);
+        const PT_GLOBAL V* a = (const PT_GLOBAL V*)rs.A[i];
+        PT_GLOBAL V* b = (PT_GLOBAL V*)rs.B[i];
+        __builtin_nontemporal_store(__builtin_nontemporal_load(a + c), b + c);
     }
+}
+// The tiled 8-byte state (lattice.h) is one block of 14 arrays' bytes from
+// A[0] on: copied as one array, one V per lane.
+template <class V>
+__global__ __launch_bounds__(LAT_BLOCK) void k_copy_block(RunStep rs, size_t nchunks) {
+    const size_t c = (size_t)blockIdx.x * LAT_BLOCK + threadIdx.x;
+    if (c >= nchunks) return;
+    __builtin_nontemporal_store(__builtin_nontemporal_load((const PT_GLOBAL V*)rs.A[0] + c), (PT_GLOBAL V*)rs.B[0] + c);
 }
 
 hipError_t launch_copy(const RunStep& R, size_t array_bytes, int lane_bytes, hipStream_t st) {
@@ -30,12 +36,15 @@ hipError_t launch_copy(const RunStep& R, size_t array_bytes, int lane_bytes, hip
     const size_t nchunks = array_bytes / (size_t)lane_bytes;
     const unsigned nblocks = (unsigned)((nchunks + LAT_BLOCK - 1) / LAT_BLOCK);
     const size_t es = array_bytes / ((size_t)R.lp.pitch * (size_t)R.lp.ny);
-    if (es == 8) {
-        if (lane_bytes == 16) k_copy14<u32x4, double><<<nblocks, LAT_BLOCK, 0, st>>>(R, nchunks);
-        else k_copy14<u32x2, double><<<nblocks, LAT_BLOCK, 0, st>>>(R, nchunks);
-    } else {   // the copy of untiled arrays does not depend on their element type
-        if (lane_bytes == 16) k_copy14<u32x4, unsigned short><<<nblocks, LAT_BLOCK, 0, st>>>(R, nchunks);
-        else k_copy14<u32x2, unsigned short><<<nblocks, LAT_BLOCK, 0, st>>>(R, nchunks);
+    if (es == 8) {   // tiled: the 14 arrays' bytes as one block
+        const size_t nflat = 14 * nchunks;
+        const unsigned nbf = (unsigned)((nflat + LAT_BLOCK - 1) / LAT_BLOCK);
+        if (lane_bytes == 16) k_copy_block<u32x4><<<nbf, LAT_BLOCK, 0, st>>>(R, nflat);
+        else k_copy_block<u32x2><<<nbf, LAT_BLOCK, 0, st>>>(R, nflat);
+    } else if (lane_bytes == 16) {
+        k_copy14<u32x4><<<nblocks, LAT_BLOCK, 0, st>>>(R, nchunks);
+    } else {
+        k_copy14<u32x2><<<nblocks, LAT_BLOCK, 0, st>>>(R, nchunks);
     }
     return hipGetLastError();
 }
