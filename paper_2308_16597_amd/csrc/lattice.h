@@ -321,7 +321,7 @@ __device__ __forceinline__ void geq_dev(R T, R Tsh, R ux, R uy, R w0, R wk, R (&
 // lose more to the tiles than the lattice kernel gains).
 template <class T> __device__ __forceinline__ constexpr bool byte_offsets() { return sizeof(T) < 8; }
 template <class T> __host__ __device__ __forceinline__ constexpr bool tiled() { return sizeof(T) == 8; }
-template <class T> __device__ __forceinline__ size_t tix(size_t k) {
+template <class T> __host__ __device__ __forceinline__ size_t tix(size_t k) {
     return tiled<T>() ? (k >> 6) * (size_t)(14 * 64) + (k & 63u) : k;
 }
 template <class T> __device__ __forceinline__ size_t row_off(const LP& lp, int y) {
