@@ -328,7 +328,8 @@ int lbm_time_phases(lbm_handle h, int32_t nsteps, double* ms_out);
 /* Bandwidth ceiling of the lattice update (Sec. 2.1): enqueue one untimed
  * and reps timed plain copies of the run's 9 + 5 population arrays (the
  * bytes one stream-collide moves, no arithmetic; the rows padded to a
- * multiple of 64 nodes), with 8-byte and again with 16-byte lanes and
+ * multiple of 64 nodes; 8-byte values, whose arrays lie in tiles of 64
+ * nodes, copied as one block), with 8-byte and again with 16-byte lanes and
  * non-temporal loads and stores, into the set the next step writes whole
  * (in place: onto itself); *ms_out receives the mean device milliseconds
  * per copy of the faster width.  The state is unchanged.  Waits. */
